@@ -1,0 +1,92 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/benchmark and the oracle.
+
+Holds no arithmetic of the method: it draws Gaussian spectral coefficients
+with variance proportional to (n+1)^-3 (m-major layout, m = 0..N, n = m..N,
+n = 0 set to zero, imaginary part zero for m = 0) and multiplies them by
+stored scale factors.  The scale factors (max wind 40 m/s, max |Phi'| equal
+to 1 % of the mean geopotential, both over the workload's Gaussian grid) were
+computed once by tests/golden/make_input_scales.py and are read from
+tests/golden/input_scales.json.
+
+The workloads stand in for the paper's R_f = 256 test suite, whose initial
+conditions are not reproduced; the physical constants are the ones the
+benchmark configurations state.
+"""
+import json
+import os
+
+import numpy as np
+
+CONSTANTS = dict(a=6.37122e6, omega=7.292e-5, g=9.80616, phibar=2.94e4, nu=1.0e5)
+
+_SCALES = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "tests", "golden", "input_scales.json")
+
+# spectral truncation -> its alias-free Gaussian grid (nlon = 3(N+1), nlat = nlon/2)
+WORKLOADS = {
+    "T31": dict(N=31, J=48, I=96),
+    "T63": dict(N=63, J=96, I=192),
+    "T127": dict(N=127, J=192, I=384),
+    "T255": dict(N=255, J=384, I=768),
+    "T511": dict(N=511, J=768, I=1536),
+    "T1023": dict(N=1023, J=1536, I=3072),
+}
+
+
+def nspec(N):
+    return (N + 1) * (N + 2) // 2
+
+
+def raw_spectrum(N, seed, nfield=3):
+    """Unscaled seeded coefficients, complex128 [nfield, nspec(N)], m-major.
+
+    Field f uses draws g1, g2 ~ N(0, 1) of shape (nfield, 2, nspec) from
+    numpy.random.default_rng(seed); coefficient = (n+1)^-1.5 (g1 + i g2)/sqrt(2)
+    for m >= 1 and (n+1)^-1.5 g1 for m = 0; n = 0 entries are zero.
+    """
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((nfield, 2, nspec(N)))
+    n = np.concatenate([np.arange(m, N + 1) for m in range(N + 1)])
+    m = np.concatenate([np.full(N + 1 - mm, mm) for mm in range(N + 1)])
+    amp = (n + 1.0) ** -1.5
+    re = np.where(m == 0, g[:, 0], g[:, 0] / np.sqrt(2.0))
+    im = np.where(m == 0, 0.0, g[:, 1] / np.sqrt(2.0))
+    out = amp * (re + 1j * im)
+    out[:, n == 0] = 0.0
+    return out
+
+
+def load_scales():
+    with open(_SCALES) as f:
+        return json.load(f)
+
+
+def scale_key(N, seed):
+    return f"N{N}_seed{seed}"
+
+
+def state(N, seed):
+    """Scaled initial state (Phi', zeta, delta) as complex128 [3, nspec(N)]."""
+    sc = load_scales()
+    key = scale_key(N, seed)
+    if key not in sc:
+        raise KeyError(f"no stored scale for {key}; run tests/golden/make_input_scales.py")
+    raw = raw_spectrum(N, seed)
+    raw[0] *= sc[key]["phi"]
+    raw[1:] *= sc[key]["wind"]
+    return raw
+
+
+def states(N, seeds):
+    return np.stack([state(N, s) for s in seeds])
+
+
+# Seeds: 1000 + configuration index (+ 10 * state index for multi-state runs)
+SEEDS = {
+    "sdc_T31": [1000],
+    "mlsdc_T127": [1001],
+    "pair_T255": [1002 + 10 * k for k in range(5)],
+    "adjoint_T127": [1003],
+    "mlsdc_T1023": [1004],
+    "mlsdc_T255": [1005],
+}
