@@ -1,0 +1,202 @@
+/*
+ * mlsdc_sh.h -- C ABI of the MI355X (gfx950) MLSDC-SH hot path.
+ *
+ * Method: Hamon, Schreiber & Minion, "Multi-Level Spectral Deferred
+ * Corrections Scheme for the Shallow Water Equations on the Rotating Sphere"
+ * (arXiv:1805.07923).  Each entry point names the passage it implements.
+ *
+ * Conventions shared by every call
+ *   - Truncation T_N (triangular, Sec. 3: S(r) = R, here N), zonal order m,
+ *     degree n.  Spectral arrays hold m = 0..N, n = m..N, m-major:
+ *     flat index idx(m, n) = m (2N + 3 - m) / 2 + (n - m), count shx_nspec(N)
+ *     = (N+1)(N+2)/2.  Entries are complex FP64, interleaved (re, im), so a
+ *     spectral field is `double[2 * nspec]` (a torch complex128 view).
+ *     Real fields: m < 0 is implied by xi^{-m} = conj(xi^m); Im xi^0_n = 0.
+ *   - Normalised associated Legendre functions: int_{-1}^{1} (P^m_n)^2 = 1,
+ *     no Condon-Shortley phase (the normalisation for which the synthesis of
+ *     eq. spectral_to_physical_space and the analysis of eqs.
+ *     fourier_transform / legendre_transform are inverse to each other).
+ *   - Grid arrays: real FP64 [field][nlat][nlon], latitude j = 0 northmost
+ *     (Gaussian latitudes, roots of P_nlat), longitude lambda_i = 2 pi i / nlon.
+ *   - State arrays: [3][nspec] complex in the order (Phi', zeta, delta) of
+ *     Sec. 2 (U = [Phi, zeta, delta]).  Batches of states are contiguous.
+ *   - Device arrays and workspaces must be 16-byte aligned (SHX_EINVAL
+ *     otherwise); workspace sizes come from the *_workspace_bytes queries.
+ *   - Every pointer argument named *_dev / device is device memory owned by
+ *     the caller (e.g. allocated by PyTorch); the library never frees it.
+ *     Plans and levels are owned by the library (create/destroy).
+ *   - All compute calls only enqueue work on `stream` (hipStream_t, 0 = the
+ *     null stream) and return without synchronising; argument errors are
+ *     returned synchronously and nothing is enqueued then.  Calls that share
+ *     a workspace must be ordered on one stream.
+ *   - Return value: SHX_OK (0) or a negative shx_status.  No C++ exception
+ *     crosses the ABI.
+ */
+#ifndef MLSDC_SH_H
+#define MLSDC_SH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shx_plan shx_plan;   /* opaque; immutable after creation      */
+typedef struct sdc_level sdc_level; /* opaque; a plan plus an SDC node set   */
+typedef void* shx_stream_t;         /* a hipStream_t                          */
+
+enum shx_status {
+    SHX_OK = 0,
+    SHX_EINVAL = -1,       /* null pointer, negative count, bad enum value   */
+    SHX_ESHAPE = -2,       /* grid too small for the truncation (see below)  */
+    SHX_EUNSUPPORTED = -3, /* nlon not of the form 2^k or 3*2^k, or a
+                              precision / node kind not built               */
+    SHX_EWORKSPACE = -4,   /* workspace pointer null or smaller than needed  */
+    SHX_EHIP = -5          /* a HIP runtime call or launch failed            */
+};
+
+/* Precision of the Legendre contractions (everything else is FP64). */
+enum shx_precision {
+    SHX_FP64 = 0,
+    SHX_FP32 = 1,          /* FP32 tables and FP32 accumulation               */
+    SHX_SPLIT_BF16_2 = 2,  /* bf16 hi+lo splits, 3 products, FP32 accumulation */
+    SHX_SPLIT_BF16_3 = 3   /* bf16 three-way splits, 6 products, FP32 accum.  */
+};
+
+enum sdc_node_kind {
+    SDC_GAUSS_LOBATTO = 0, /* Sec. 4.2: Gauss-Lobatto nodes on [t^n, t^n + dt] */
+    SDC_RADAU_RIGHT = 1    /* t^n followed by the Radau-IIA points            */
+};
+
+/* Physical constants of Sec. 2: Earth radius a, rotation rate Omega,
+ * gravity g, mean geopotential Phibar, diffusion coefficient nu. */
+typedef struct { double a, omega, g, phibar, nu; } swe_params;
+
+/* Algorithm 1 controls: iterations N_ML, sweeps per call of SweepFine /
+ * SweepCoarse (the paper uses 1 and 1), and whether to compute the FP64
+ * collocation residual of the final fine nodes (eq. collocation_problem). */
+typedef struct { int niter, nsweep_fine, nsweep_coarse, residual_check; } mlsdc_opts;
+
+/* ---------------------------------------------------------------- plans */
+
+/* Number of spectral coefficients (N+1)(N+2)/2 of truncation T_N. */
+size_t shx_nspec(int ntrunc);
+
+/* Create a transform plan for T_ntrunc on nlat Gaussian latitudes and nlon
+ * longitudes (Sec. 3, eqs. spectral_to_physical_space, fourier_transform,
+ * legendre_transform).  Requires ntrunc >= 1, nlat even, nlon > 2 ntrunc,
+ * nlat > ntrunc (else SHX_ESHAPE) and nlon = 2^k or 3*2^k with
+ * 16 <= nlon <= 3072 (else SHX_EUNSUPPORTED).  Computes the Gaussian
+ * latitudes and weights on the host in quad precision, the FFT twiddles in
+ * extended precision, and the P^m_n tables (n <= ntrunc + 1) on the current
+ * device with an FP64 recurrence, stored in `precision`.  Synchronises the
+ * current device.  *out receives the plan (library-owned). */
+int shx_plan_create(int ntrunc, int nlat, int nlon, int precision, shx_plan** out);
+void shx_plan_destroy(shx_plan* plan);
+
+/* Host copies of the plan's FP64 latitude data, each array [nlat]:
+ * mu_j = cos(theta_j), sin(theta_j), Gauss weights w_j.  Any may be NULL. */
+int shx_plan_latitudes(const shx_plan* plan, double* mu, double* sin_theta, double* w);
+
+/* Copy P^m_n(mu_j) (FP64 table values, or the working-precision table
+ * values widened to FP64) for the northern latitudes j = 0..nlat/2-1 to the
+ * host array out[nlat/2].  Requires 0 <= m <= n <= ntrunc + 1, m <= ntrunc.
+ * Synchronous. */
+int shx_plan_legendre(const shx_plan* plan, int m, int n, double* out);
+
+/* ------------------------------------------------------- the SH pair */
+
+/* Device workspace bytes for sh_inverse / sh_forward with nfield fields. */
+size_t shx_workspace_bytes(const shx_plan* plan, int nfield);
+
+/* Synthesis, eq. spectral_to_physical_space (Sec. 3):
+ *   grid(lambda_i, mu_j) = Re xi_0(mu_j) + 2 Re sum_{m=1}^{N} xi_m(mu_j) e^{i m lambda_i},
+ *   xi_m(mu_j) = sum_{n=m}^{N} xi^m_n P^m_n(mu_j).
+ * spec_dev: [nfield][nspec] complex (read only); grid_dev: [nfield][nlat][nlon]
+ * real (written).  Im xi^0_n is ignored. */
+int sh_inverse(const shx_plan* plan, int nfield, const double* spec_dev, double* grid_dev,
+               void* ws_dev, size_t ws_bytes, shx_stream_t stream);
+
+/* Analysis, eqs. fourier_transform and legendre_transform (Sec. 3):
+ *   xi_m(mu_j) = (1/nlon) sum_i grid(lambda_i, mu_j) e^{-i m lambda_i},
+ *   xi^m_n = sum_j w_j xi_m(mu_j) P^m_n(mu_j).
+ * grid_dev: [nfield][nlat][nlon] real (read only); spec_dev: [nfield][nspec]. */
+int sh_forward(const shx_plan* plan, int nfield, const double* grid_dev, double* spec_dev,
+               void* ws_dev, size_t ws_bytes, shx_stream_t stream);
+
+/* ------------------------------------------------ SWE right-hand sides */
+
+/* Device workspace bytes for swe_tendency on nstate states. */
+size_t swe_workspace_bytes(const shx_plan* plan, int nstate);
+
+/* The split right-hand side of eq. system_of_odes (Sec. 4.1):
+ * F_I = L_G (eq. linear_wave_motion_induced_by_gravitational_forces) and
+ * F_E = L_F + N (eqs. linear_harmonic_oscillator_on_the_velocity_components,
+ * nonlinear_operators) of the vorticity-divergence equations of Sec. 2, in
+ * spectral space (eq. semidiscrete_system).  With L_n = n(n+1)/a^2:
+ *   F_I = [-Phibar delta - nu L Phi', -nu L zeta, L Phi' - nu L delta],
+ *   F_E = [-div(Phi' V), -div(eta V), curl(eta V) + L_n (V.V/2)^],
+ * eta = zeta + 2 Omega mu; the products are formed on the Gaussian grid
+ * (the grid must be alias free: nlon >= 3N+1, nlat >= (3N+1)/2, else
+ * SHX_ESHAPE).  state_dev: [nstate][3][nspec] complex (read only);
+ * f_impl_dev, f_expl_dev: same shape (written; may be NULL to skip). */
+int swe_tendency(const shx_plan* plan, const swe_params* params, int nstate,
+                 const double* state_dev, double* f_impl_dev, double* f_expl_dev,
+                 void* ws_dev, size_t ws_bytes, shx_stream_t stream);
+
+/* Solve Theta - h F_I(Theta) = b (Sec. 4.4, eq. implicit_systems) for each
+ * (m, n): the geopotential from the diagonal reduced system, then delta and
+ * zeta by local updates.  h = dt * qI_{m+1,m+1}.  rhs_dev, out_dev:
+ * [nstate][3][nspec] complex; out may alias rhs. */
+int imex_solve(const shx_plan* plan, const swe_params* params, int nstate, double h,
+               const double* rhs_dev, double* out_dev, shx_stream_t stream);
+
+/* ------------------------------------------------------ SDC and MLSDC */
+
+/* An SDC level: the plan, the SWE constants and nnodes = M+1 nodes of
+ * node_kind with the matrices of Sec. 4.2 (computed on the host in quad
+ * precision, used in FP64): Q (eq. weights), forward-Euler Q_E, and the
+ * LU-trick Q_Delta (Q_Delta[1:,1:] = U^T where Q[1:,1:]^T = L U, Doolittle).
+ * 2 <= nnodes <= 9.  The plan must outlive the level. */
+int sdc_level_create(const shx_plan* plan, const swe_params* params, int node_kind,
+                     int nnodes, sdc_level** out);
+void sdc_level_destroy(sdc_level* level);
+
+/* Host copies of the level's nodes tau[M+1] on [0,1] and the row-major
+ * (M+1)x(M+1) matrices Q, Q_E, Q_Delta.  Any may be NULL. */
+int sdc_level_matrices(const sdc_level* level, double* tau, double* Q, double* QE, double* QD);
+
+size_t sdc_sweep_workspace_bytes(const sdc_level* level);
+
+/* One IMEX SDC sweep (Sec. 4.2, eq. update_equation_sdcq_discrete_form; with
+ * tau, Sec. 4.3.1, eq. modified_update_equation_sdcq_discrete_form), nodes
+ * m = 0..M-1 in order, in place.  theta_dev, f_impl_dev, f_expl_dev:
+ * [M+1][3][nspec] complex; node 0 is the initial value (read only), F at all
+ * nodes must be those of the current iterate.  tau_dev: [M+1][3][nspec] or
+ * NULL. */
+int sdc_sweep(const sdc_level* level, double dt, double* theta_dev, double* f_impl_dev,
+              double* f_expl_dev, const double* tau_dev, void* ws_dev, size_t ws_bytes,
+              shx_stream_t stream);
+
+size_t mlsdc_workspace_bytes(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts* opts);
+
+/* One time step of two-level MLSDC (Sec. 4.3.2, Algorithm 1; spread
+ * initialisation; transfer by spectral truncation / zero padding and
+ * Lagrange time interpolation, Sec. 4.3.3), or of single-level SDC when
+ * coarse is NULL (step A only, niter sweeps of nsweep_fine).  The coarse plan
+ * must have a smaller truncation than the fine plan.  theta_n_dev,
+ * theta_np1_dev: [3][nspec_fine] complex (may alias).  status_dev: NULL or
+ * device double[2]: [0] = FP64 collocation residual of the fine nodes
+ * max_m ||r^m||_2 / ||Theta^0||_2 if opts->residual_check, else 0;
+ * [1] = 1 if the new state holds a non-finite value, else 0. */
+int mlsdc_step(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts* opts,
+               double dt, const double* theta_n_dev, double* theta_np1_dev,
+               double* status_dev, void* ws_dev, size_t ws_bytes, shx_stream_t stream);
+
+/* Text for a status code. */
+const char* shx_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

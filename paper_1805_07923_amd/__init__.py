@@ -1,0 +1,261 @@
+"""Python binding of libmlsdc_sh.so, the MI355X MLSDC-SH hot path.
+
+Argument marshalling only: every step runs in the HIP library.  Tensors are
+torch tensors on the current HIP device; spectral arrays are complex128
+(m-major, see include/mlsdc_sh.h), grids float64.  Work is enqueued on
+torch's current stream.  Importing works without a GPU; the library is
+loaded on first use and a missing library raises immediately.
+"""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlsdc_sh.so")
+
+SHX_FP64, SHX_FP32, SHX_SPLIT_BF16_2, SHX_SPLIT_BF16_3 = 0, 1, 2, 3
+SDC_GAUSS_LOBATTO, SDC_RADAU_RIGHT = 0, 1
+
+_lib = None
+
+
+class SwePar(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("omega", ctypes.c_double), ("g", ctypes.c_double),
+                ("phibar", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+class MlsdcOpts(ctypes.Structure):
+    _fields_ = [("niter", ctypes.c_int), ("nsweep_fine", ctypes.c_int),
+                ("nsweep_coarse", ctypes.c_int), ("residual_check", ctypes.c_int)]
+
+
+# name -> (restype, argtypes)
+_P, _D, _I, _SZ = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
+_SIGS = {
+    "shx_nspec": (_SZ, [_I]),
+    "shx_strerror": (ctypes.c_char_p, [_I]),
+    "shx_plan_create": (_I, [_I, _I, _I, _I, ctypes.POINTER(_P)]),
+    "shx_plan_destroy": (None, [_P]),
+    "shx_plan_latitudes": (_I, [_P, _P, _P, _P]),
+    "shx_plan_legendre": (_I, [_P, _I, _I, _P]),
+    "shx_workspace_bytes": (_SZ, [_P, _I]),
+    "sh_inverse": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
+    "sh_forward": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
+    "swe_workspace_bytes": (_SZ, [_P, _I]),
+    "swe_tendency": (_I, [_P, ctypes.POINTER(SwePar), _I, _P, _P, _P, _P, _SZ, _P]),
+    "imex_solve": (_I, [_P, ctypes.POINTER(SwePar), _I, _D, _P, _P, _P]),
+    "sdc_level_create": (_I, [_P, ctypes.POINTER(SwePar), _I, _I, ctypes.POINTER(_P)]),
+    "sdc_level_destroy": (None, [_P]),
+    "sdc_level_matrices": (_I, [_P, _P, _P, _P, _P]),
+    "sdc_sweep_workspace_bytes": (_SZ, [_P]),
+    "sdc_sweep": (_I, [_P, _D, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mlsdc_workspace_bytes": (_SZ, [_P, _P, ctypes.POINTER(MlsdcOpts)]),
+    "mlsdc_step": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P, _SZ, _P]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+class ShxError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ShxError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_07923_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ShxError(f"{what}: {lib().shx_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, numel, name):
+    import torch
+    if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ShxError(f"{name}: expected a contiguous {dtype} cuda tensor with >= {numel} elements, "
+                       f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    return t
+
+
+def nspec(N):
+    return int(lib().shx_nspec(N))
+
+
+class Workspace:
+    """A reusable device byte buffer (grown on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+class Plan:
+    """Transform plan for truncation T_N on an nlat x nlon Gaussian grid."""
+
+    def __init__(self, N, nlat, nlon, precision=SHX_FP64):
+        self.N, self.nlat, self.nlon, self.precision = N, nlat, nlon, precision
+        h = ctypes.c_void_p()
+        _check(lib().shx_plan_create(N, nlat, nlon, precision, ctypes.byref(h)), "shx_plan_create")
+        self.h = h
+        self.nspec = nspec(N)
+        self.ws = Workspace()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.shx_plan_destroy(self.h)
+            self.h = None
+
+    def latitudes(self):
+        import numpy as np
+        mu, st, w = (np.empty(self.nlat) for _ in range(3))
+        _check(lib().shx_plan_latitudes(self.h, mu.ctypes.data, st.ctypes.data, w.ctypes.data), "latitudes")
+        return mu, st, w
+
+    def legendre(self, m, n):
+        import numpy as np
+        out = np.empty(self.nlat // 2)
+        _check(lib().shx_plan_legendre(self.h, m, n, out.ctypes.data), "shx_plan_legendre")
+        return out
+
+    def inverse(self, spec, grid=None):
+        """spec complex128 [F, nspec] -> grid float64 [F, nlat, nlon]."""
+        import torch
+        F = spec.shape[0]
+        _need(spec, torch.complex128, F * self.nspec, "spec")
+        if grid is None:
+            grid = torch.empty(F, self.nlat, self.nlon, dtype=torch.float64, device=spec.device)
+        _need(grid, torch.float64, F * self.nlat * self.nlon, "grid")
+        nb = lib().shx_workspace_bytes(self.h, F)
+        ws = self.ws.get(nb)
+        _check(lib().sh_inverse(self.h, F, _ptr(spec), _ptr(grid), _ptr(ws), nb, _stream()), "sh_inverse")
+        return grid
+
+    def forward(self, grid, spec=None):
+        """grid float64 [F, nlat, nlon] -> spec complex128 [F, nspec]."""
+        import torch
+        F = grid.shape[0]
+        _need(grid, torch.float64, F * self.nlat * self.nlon, "grid")
+        if spec is None:
+            spec = torch.empty(F, self.nspec, dtype=torch.complex128, device=grid.device)
+        _need(spec, torch.complex128, F * self.nspec, "spec")
+        nb = lib().shx_workspace_bytes(self.h, F)
+        ws = self.ws.get(nb)
+        _check(lib().sh_forward(self.h, F, _ptr(grid), _ptr(spec), _ptr(ws), nb, _stream()), "sh_forward")
+        return spec
+
+
+def swe_params(a=6.37122e6, omega=7.292e-5, g=9.80616, phibar=2.94e4, nu=1.0e5):
+    return SwePar(a, omega, g, phibar, nu)
+
+
+def tendency(plan, params, state, f_impl=None, f_expl=None, ws=None):
+    """state complex128 [S, 3, nspec] -> (F_I, F_E), same shape."""
+    import torch
+    S = state.shape[0] if state.dim() == 3 else 1
+    _need(state, torch.complex128, S * 3 * plan.nspec, "state")
+    if f_impl is None:
+        f_impl = torch.empty_like(state)
+    if f_expl is None:
+        f_expl = torch.empty_like(state)
+    nb = lib().swe_workspace_bytes(plan.h, S)
+    w = (ws or plan.ws).get(nb)
+    _check(lib().swe_tendency(plan.h, ctypes.byref(params), S, _ptr(state), _ptr(f_impl), _ptr(f_expl),
+                              _ptr(w), nb, _stream()), "swe_tendency")
+    return f_impl, f_expl
+
+
+def solve(plan, params, h, rhs, out=None):
+    """Solve Theta - h F_I(Theta) = rhs; rhs complex128 [S, 3, nspec]."""
+    import torch
+    S = rhs.shape[0] if rhs.dim() == 3 else 1
+    _need(rhs, torch.complex128, S * 3 * plan.nspec, "rhs")
+    if out is None:
+        out = torch.empty_like(rhs)
+    _check(lib().imex_solve(plan.h, ctypes.byref(params), S, float(h), _ptr(rhs), _ptr(out), _stream()),
+           "imex_solve")
+    return out
+
+
+class Level:
+    """An SDC level: plan + physical constants + node set."""
+
+    def __init__(self, plan, params, kind=SDC_GAUSS_LOBATTO, nnodes=3):
+        self.plan, self.params, self.kind, self.nnodes = plan, params, kind, nnodes
+        h = ctypes.c_void_p()
+        _check(lib().sdc_level_create(plan.h, ctypes.byref(params), kind, nnodes, ctypes.byref(h)),
+               "sdc_level_create")
+        self.h = h
+        self.ws = Workspace()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sdc_level_destroy(self.h)
+            self.h = None
+
+    def matrices(self):
+        import numpy as np
+        n = self.nnodes
+        tau, Q, QE, QD = np.empty(n), np.empty((n, n)), np.empty((n, n)), np.empty((n, n))
+        _check(lib().sdc_level_matrices(self.h, tau.ctypes.data, Q.ctypes.data, QE.ctypes.data,
+                                        QD.ctypes.data), "sdc_level_matrices")
+        return tau, Q, QE, QD
+
+    def sweep(self, dt, theta, f_impl, f_expl, tau=None):
+        """In-place sweep over node arrays complex128 [M+1, 3, nspec]."""
+        import torch
+        n = self.nnodes * 3 * self.plan.nspec
+        for t, nm in ((theta, "theta"), (f_impl, "f_impl"), (f_expl, "f_expl")):
+            _need(t, torch.complex128, n, nm)
+        if tau is not None:
+            _need(tau, torch.complex128, n, "tau")
+        nb = lib().sdc_sweep_workspace_bytes(self.h)
+        w = self.ws.get(nb)
+        _check(lib().sdc_sweep(self.h, float(dt), _ptr(theta), _ptr(f_impl), _ptr(f_expl), _ptr(tau), _ptr(w),
+                               nb, _stream()), "sdc_sweep")
+
+
+class Stepper:
+    """mlsdc_step with a persistent workspace (coarse=None: single-level SDC)."""
+
+    def __init__(self, fine, coarse=None, niter=4, nsweep_fine=1, nsweep_coarse=1, residual_check=False):
+        self.fine, self.coarse = fine, coarse
+        self.opts = MlsdcOpts(niter, nsweep_fine, nsweep_coarse, int(bool(residual_check)))
+        self.ws = Workspace()
+        self.nbytes = lib().mlsdc_workspace_bytes(fine.h, coarse.h if coarse else None, ctypes.byref(self.opts))
+
+    def step(self, dt, theta_n, theta_np1=None, status=None):
+        import torch
+        n = 3 * self.fine.plan.nspec
+        _need(theta_n, torch.complex128, n, "theta_n")
+        if theta_np1 is None:
+            theta_np1 = torch.empty_like(theta_n)
+        _need(theta_np1, torch.complex128, n, "theta_np1")
+        if status is not None:
+            _need(status, torch.float64, 2, "status")
+        w = self.ws.get(self.nbytes)
+        _check(lib().mlsdc_step(self.fine.h, self.coarse.h if self.coarse else None, ctypes.byref(self.opts),
+                                float(dt), _ptr(theta_n), _ptr(theta_np1), _ptr(status), _ptr(w), self.nbytes,
+                                _stream()), "mlsdc_step")
+        return theta_np1

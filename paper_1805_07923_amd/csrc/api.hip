@@ -1,0 +1,516 @@
+// C ABI entry points: plan and level set-up, the SH transform pair, the
+// shallow-water tendency, the implicit solve, the IMEX SDC sweep and the
+// two-level MLSDC step (Algorithm 1).  Host code only enqueues kernels on the
+// caller's stream; argument checks happen before anything is enqueued.
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "setup_host.h"
+
+namespace {
+
+inline hipStream_t S(shx_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+    return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T) > 0 ? n * sizeof(T) : 1);
+}
+
+void plan_free(shx_plan* p) {
+    if (!p) return;
+    (void)hipFree(p->mu);
+    (void)hipFree(p->sint);
+    (void)hipFree(p->cos2);
+    (void)hipFree(p->w);
+    (void)hipFree(p->tw);
+    (void)hipFree(p->psyn);
+    (void)hipFree(p->pan);
+    (void)hipFree(p->off);
+    (void)hipFree(p->ord);
+    (void)hipFree(p->deg);
+    (void)hipFree(p->ord_e);
+    (void)hipFree(p->deg_e);
+    delete p;
+}
+
+#define HIPCHK(x)                          \
+    do {                                   \
+        if ((x) != hipSuccess) return SHX_EHIP; \
+    } while (0)
+
+// Workspace carve-up helper.
+struct Carve {
+    char* base;
+    size_t used = 0;
+    template <class T>
+    T* take(size_t n) {
+        T* r = reinterpret_cast<T*>(base ? base + used : nullptr);
+        used += align256(n * sizeof(T));
+        return r;
+    }
+};
+
+// Tendency workspace for S states: cin [S][ext][4], FI [S][J][N+1][4],
+// G [S][J][N+1][5], cout [S][ext][5] (double2).
+struct TendWS {
+    double2 *cin, *FI, *G, *cout;
+};
+TendWS carve_tend(Carve& c, const shx_plan* pl, int S) {
+    TendWS t;
+    t.cin = c.take<double2>((size_t)S * pl->nspec_e * 4);
+    t.FI = c.take<double2>((size_t)S * pl->J * (pl->N + 1) * 4);
+    t.G = c.take<double2>((size_t)S * pl->J * (pl->N + 1) * 5);
+    t.cout = c.take<double2>((size_t)S * pl->nspec_e * 5);
+    return t;
+}
+size_t tend_bytes(const shx_plan* pl, int S) {
+    Carve c{nullptr};
+    carve_tend(c, pl, S);
+    return c.used;
+}
+
+bool alias_free(const shx_plan* pl) {
+    return pl->I >= 3 * pl->N + 1 && 2 * pl->J >= 3 * pl->N + 1;
+}
+
+int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double2* state, double2* fi,
+                  double2* fe, const TendWS& t, hipStream_t st) {
+    if (fe) {
+        HIPCHK(launch_swe_prep(pl, p.a, state, t.cin, nst, st));
+        HIPCHK(launch_leg_syn(pl, t.cin, t.FI, 4, nst, pl->nmax, st));
+        HIPCHK(launch_swe_grid(pl, t.FI, t.G, nst, p.omega, st));
+        HIPCHK(launch_leg_an(pl, t.G, t.cout, 5, nst, pl->nmax, st));
+    }
+    HIPCHK(launch_swe_combine(pl, p, t.cout, state, fi, fe, nst, st));
+    return SHX_OK;
+}
+
+// Sweep workspace: F_I and F_E of the previous iterate at all nodes, and
+// the tendency workspace for one state.
+struct SweepWS {
+    double2 *fi_old, *fe_old;
+    TendWS t;
+};
+SweepWS carve_sweep(Carve& c, const sdc_level* lv) {
+    SweepWS w;
+    const size_t n = (size_t)lv->nnodes * 3 * lv->plan->nspec;
+    w.fi_old = c.take<double2>(n);
+    w.fe_old = c.take<double2>(n);
+    w.t = carve_tend(c, lv->plan, 1);
+    return w;
+}
+
+int sweep_impl(const sdc_level* lv, double dt, double2* th, double2* fi, double2* fe, const double2* tau,
+               const SweepWS& w, hipStream_t st) {
+    const shx_plan* pl = lv->plan;
+    const int M = lv->nnodes - 1, n1 = lv->nnodes;
+    const size_t ns3 = 3 * (size_t)pl->nspec;
+    HIPCHK(hipMemcpyAsync(w.fi_old, fi, n1 * ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.fe_old, fe, n1 * ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    for (int m = 0; m < M; ++m) {
+        NodeWeights wt;
+        for (int j = 0; j < 9; ++j) {
+            const bool in = j < n1;
+            wt.q[j] = in ? dt * lv->Q[(m + 1) * n1 + j] : 0.0;
+            wt.qe[j] = in ? dt * lv->QE[(m + 1) * n1 + j] : 0.0;
+            wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
+        }
+        const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
+        HIPCHK(launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi, fe, w.fi_old, w.fe_old, tau, st));
+        const size_t o = (size_t)(m + 1) * ns3;
+        int rc = tendency_impl(pl, lv->p, 1, th + o, fi + o, fe + o, w.t, st);
+        if (rc) return rc;
+    }
+    return SHX_OK;
+}
+
+Mat9x9 to_mat(const double* a, int n) {
+    Mat9x9 r;
+    std::memset(&r, 0, sizeof(r));
+    for (int i = 0; i < n; ++i) r.a[i] = a[i];
+    return r;
+}
+
+// MLSDC workspace.
+struct StepWS {
+    double2 *thf, *fif, *fef;                          // fine [Mf+1][3][nsf]
+    double2 *thc, *fic, *fec, *thct, *fict, *fect, *tau;  // coarse [Mc+1][3][nsc]
+    double2 *rfi, *rfe;                                // residual re-evaluation [Mf+1][3][nsf]
+    double* partial;
+    SweepWS swf, swc;
+    TendWS tc;                                         // coarse, Mc states
+    TendWS tr;                                         // fine, Mf+1 states (residual)
+};
+StepWS carve_step(Carve& c, const sdc_level* f, const sdc_level* cl, const mlsdc_opts* o) {
+    StepWS w{};
+    const size_t nf = (size_t)f->nnodes * 3 * f->plan->nspec;
+    w.thf = c.take<double2>(nf);
+    w.fif = c.take<double2>(nf);
+    w.fef = c.take<double2>(nf);
+    w.swf = carve_sweep(c, f);
+    if (cl) {
+        const size_t nc = (size_t)cl->nnodes * 3 * cl->plan->nspec;
+        w.thc = c.take<double2>(nc);
+        w.fic = c.take<double2>(nc);
+        w.fec = c.take<double2>(nc);
+        w.thct = c.take<double2>(nc);
+        w.fict = c.take<double2>(nc);
+        w.fect = c.take<double2>(nc);
+        w.tau = c.take<double2>(nc);
+        w.swc = carve_sweep(c, cl);
+        w.tc = carve_tend(c, cl->plan, cl->nnodes - 1);
+    }
+    if (o && o->residual_check) {
+        w.rfi = c.take<double2>(nf);
+        w.rfe = c.take<double2>(nf);
+        w.tr = carve_tend(c, f->plan, f->nnodes);
+        w.partial = c.take<double>((size_t)residual_blocks(f->plan) * f->nnodes);
+    }
+    return w;
+}
+
+// Complex and grid arrays are accessed as 16-byte double2.
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+bool valid_params(const swe_params* p) {
+    return p && p->a > 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t shx_nspec(int ntrunc) { return ntrunc < 0 ? 0 : (size_t)nspec_of(ntrunc); }
+
+const char* shx_strerror(int s) {
+    switch (s) {
+        case SHX_OK: return "ok";
+        case SHX_EINVAL: return "invalid argument";
+        case SHX_ESHAPE: return "grid too small for the truncation";
+        case SHX_EUNSUPPORTED: return "unsupported size or option";
+        case SHX_EWORKSPACE: return "workspace missing or too small";
+        case SHX_EHIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
+    if (!out || N < 1 || J < 2 || I < 2) return SHX_EINVAL;
+    *out = nullptr;
+    if (prec != SHX_FP64) return SHX_EUNSUPPORTED;
+    if ((J & 1) || I <= 2 * N || J <= N) return SHX_ESHAPE;
+    if (!fft_length_supported(I)) return SHX_EUNSUPPORTED;
+    shx_plan* p = new (std::nothrow) shx_plan();
+    if (!p) return SHX_EINVAL;
+    p->N = N;
+    p->J = J;
+    p->I = I;
+    p->prec = prec;
+    p->nmax = N + 1;
+    p->Jh = J / 2;
+    p->nspec = nspec_of(N);
+    p->nspec_e = nspec_ext_of(N);
+    if (hipGetDevice(&p->dev) != hipSuccess) { delete p; return SHX_EHIP; }
+    p->h_mu.resize(J);
+    p->h_sint.resize(J);
+    p->h_cos2.resize(J);
+    p->h_w.resize(J);
+    if (shx_host_gauss(J, p->h_mu.data(), p->h_sint.data(), p->h_cos2.data(), p->h_w.data())) {
+        delete p;
+        return SHX_EINVAL;
+    }
+    std::vector<double> twr(I), twi(I);
+    shx_host_twiddles(I, twr.data(), twi.data());
+    std::vector<double2> tw(I);
+    for (int t = 0; t < I; ++t) tw[t] = make_double2(twr[t], twi[t]);
+    // table offsets per (m, p)
+    p->h_off.resize(2 * (N + 1));
+    long long acc = 0;
+    for (int m = 0; m <= N; ++m)
+        for (int q = 0; q < 2; ++q) {
+            p->h_off[2 * m + q] = acc;
+            acc += (long long)kcount(p->nmax, m, q) * p->Jh;
+        }
+    p->table_elems = acc;
+    std::vector<int> ord(p->nspec), deg(p->nspec), orde(p->nspec_e), dege(p->nspec_e);
+    for (int m = 0; m <= N; ++m) {
+        for (int n = m; n <= N; ++n) {
+            ord[spec_idx(N, m, n)] = m;
+            deg[spec_idx(N, m, n)] = n;
+        }
+        for (int n = m; n <= N + 1; ++n) {
+            orde[ext_idx(N, m, n)] = m;
+            dege[ext_idx(N, m, n)] = n;
+        }
+    }
+    bool ok = dalloc(&p->mu, J) == hipSuccess && dalloc(&p->sint, J) == hipSuccess &&
+              dalloc(&p->cos2, J) == hipSuccess && dalloc(&p->w, J) == hipSuccess &&
+              dalloc(&p->tw, I) == hipSuccess && dalloc(&p->psyn, acc) == hipSuccess &&
+              dalloc(&p->pan, acc) == hipSuccess && dalloc(&p->off, p->h_off.size()) == hipSuccess &&
+              dalloc(&p->ord, p->nspec) == hipSuccess && dalloc(&p->deg, p->nspec) == hipSuccess &&
+              dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess;
+    ok = ok && hipMemcpy(p->mu, p->h_mu.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->sint, p->h_sint.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->cos2, p->h_cos2.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->w, p->h_w.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->tw, tw.data(), I * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->off, p->h_off.data(), p->h_off.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->ord, ord.data(), ord.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->deg, deg.data(), deg.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->ord_e, orde.data(), orde.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->deg_e, dege.data(), dege.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && launch_plm_table(p, 0) == hipSuccess;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        plan_free(p);
+        return SHX_EHIP;
+    }
+    *out = p;
+    return SHX_OK;
+}
+
+void shx_plan_destroy(shx_plan* plan) { plan_free(plan); }
+
+int shx_plan_latitudes(const shx_plan* pl, double* mu, double* st, double* w) {
+    if (!pl) return SHX_EINVAL;
+    for (int j = 0; j < pl->J; ++j) {
+        if (mu) mu[j] = pl->h_mu[j];
+        if (st) st[j] = pl->h_sint[j];
+        if (w) w[j] = pl->h_w[j];
+    }
+    return SHX_OK;
+}
+
+int shx_plan_legendre(const shx_plan* pl, int m, int n, double* out) {
+    if (!pl || !out || m < 0 || m > pl->N || n < m || n > pl->nmax) return SHX_EINVAL;
+    const int p = (n - m) & 1, k = (n - m) >> 1;
+    const double* src = pl->psyn + pl->h_off[2 * m + p] + (long long)k * pl->Jh;
+    if (hipMemcpy(out, src, pl->Jh * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return SHX_EHIP;
+    return SHX_OK;
+}
+
+size_t shx_workspace_bytes(const shx_plan* pl, int F) {
+    if (!pl || F < 1) return 0;
+    return align256((size_t)pl->nspec_e * F * sizeof(double2)) +
+           align256((size_t)pl->J * (pl->N + 1) * F * sizeof(double2));
+}
+
+int sh_inverse(const shx_plan* pl, int F, const double* spec, double* grid, void* ws, size_t wsb,
+               shx_stream_t stream) {
+    if (!pl || F < 1 || !spec || !grid || !aligned16(spec) || !aligned16(grid)) return SHX_EINVAL;
+    if (!ws || wsb < shx_workspace_bytes(pl, F)) return SHX_EWORKSPACE;
+    Carve c{static_cast<char*>(ws)};
+    double2* cin = c.take<double2>((size_t)pl->nspec_e * F);
+    double2* FI = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
+    hipStream_t st = S(stream);
+    HIPCHK(launch_spec_to_ext(pl, reinterpret_cast<const double2*>(spec), cin, F, st));
+    HIPCHK(launch_leg_syn(pl, cin, FI, F, 1, pl->N, st));
+    HIPCHK(launch_fft_inv(pl, FI, grid, F, st));
+    return SHX_OK;
+}
+
+int sh_forward(const shx_plan* pl, int F, const double* grid, double* spec, void* ws, size_t wsb,
+               shx_stream_t stream) {
+    if (!pl || F < 1 || !spec || !grid || !aligned16(spec) || !aligned16(grid)) return SHX_EINVAL;
+    if (!ws || wsb < shx_workspace_bytes(pl, F)) return SHX_EWORKSPACE;
+    Carve c{static_cast<char*>(ws)};
+    double2* cout = c.take<double2>((size_t)pl->nspec_e * F);
+    double2* G = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
+    hipStream_t st = S(stream);
+    HIPCHK(launch_fft_fwd(pl, grid, G, F, st));
+    HIPCHK(launch_leg_an(pl, G, cout, F, 1, pl->N, st));
+    HIPCHK(launch_ext_to_spec(pl, cout, reinterpret_cast<double2*>(spec), F, st));
+    return SHX_OK;
+}
+
+size_t swe_workspace_bytes(const shx_plan* pl, int nstate) {
+    if (!pl || nstate < 1) return 0;
+    return tend_bytes(pl, nstate);
+}
+
+int swe_tendency(const shx_plan* pl, const swe_params* prm, int nst, const double* state, double* fi,
+                 double* fe, void* ws, size_t wsb, shx_stream_t stream) {
+    if (!pl || !valid_params(prm) || nst < 1 || !state || !aligned16(state) || !aligned16(fi) ||
+        !aligned16(fe) || !aligned16(ws))
+        return SHX_EINVAL;
+    if (!alias_free(pl)) return SHX_ESHAPE;
+    if (fe && (!ws || wsb < tend_bytes(pl, nst))) return SHX_EWORKSPACE;
+    if (!fi && !fe) return SHX_OK;
+    Carve c{static_cast<char*>(ws)};
+    TendWS t = carve_tend(c, pl, nst);
+    return tendency_impl(pl, *prm, nst, reinterpret_cast<const double2*>(state),
+                         reinterpret_cast<double2*>(fi), reinterpret_cast<double2*>(fe), t, S(stream));
+}
+
+int imex_solve(const shx_plan* pl, const swe_params* prm, int nst, double h, const double* rhs, double* out,
+               shx_stream_t stream) {
+    if (!pl || !valid_params(prm) || nst < 1 || !rhs || !out || !(h >= 0.0) || !aligned16(rhs) ||
+        !aligned16(out))
+        return SHX_EINVAL;
+    HIPCHK(launch_imex_solve(pl, *prm, h, reinterpret_cast<const double2*>(rhs), reinterpret_cast<double2*>(out),
+                             nst, S(stream)));
+    return SHX_OK;
+}
+
+int sdc_level_create(const shx_plan* pl, const swe_params* prm, int kind, int nnodes, sdc_level** out) {
+    if (!out) return SHX_EINVAL;
+    *out = nullptr;
+    if (!pl || !valid_params(prm) || (kind != SDC_GAUSS_LOBATTO && kind != SDC_RADAU_RIGHT) || nnodes < 2 ||
+        nnodes > 9)
+        return SHX_EINVAL;
+    if (kind == SDC_RADAU_RIGHT && nnodes < 3) return SHX_EINVAL;
+    sdc_level* lv = new (std::nothrow) sdc_level();
+    if (!lv) return SHX_EINVAL;
+    lv->plan = pl;
+    lv->p = *prm;
+    lv->kind = kind;
+    lv->nnodes = nnodes;
+    if (shx_host_sdc(kind, nnodes, lv->tau, lv->Q, lv->QE, lv->QD)) {
+        delete lv;
+        return SHX_EINVAL;
+    }
+    *out = lv;
+    return SHX_OK;
+}
+
+void sdc_level_destroy(sdc_level* lv) { delete lv; }
+
+int sdc_level_matrices(const sdc_level* lv, double* tau, double* Q, double* QE, double* QD) {
+    if (!lv) return SHX_EINVAL;
+    const int n = lv->nnodes;
+    for (int i = 0; i < n; ++i) {
+        if (tau) tau[i] = lv->tau[i];
+        for (int j = 0; j < n; ++j) {
+            if (Q) Q[i * n + j] = lv->Q[i * n + j];
+            if (QE) QE[i * n + j] = lv->QE[i * n + j];
+            if (QD) QD[i * n + j] = lv->QD[i * n + j];
+        }
+    }
+    return SHX_OK;
+}
+
+size_t sdc_sweep_workspace_bytes(const sdc_level* lv) {
+    if (!lv) return 0;
+    Carve c{nullptr};
+    carve_sweep(c, lv);
+    return c.used;
+}
+
+int sdc_sweep(const sdc_level* lv, double dt, double* th, double* fi, double* fe, const double* tau, void* ws,
+              size_t wsb, shx_stream_t stream) {
+    if (!lv || !th || !fi || !fe || !(dt > 0.0) || !aligned16(th) || !aligned16(fi) || !aligned16(fe) ||
+        !aligned16(tau) || !aligned16(ws))
+        return SHX_EINVAL;
+    if (!alias_free(lv->plan)) return SHX_ESHAPE;
+    if (!ws || wsb < sdc_sweep_workspace_bytes(lv)) return SHX_EWORKSPACE;
+    Carve c{static_cast<char*>(ws)};
+    SweepWS w = carve_sweep(c, lv);
+    return sweep_impl(lv, dt, reinterpret_cast<double2*>(th), reinterpret_cast<double2*>(fi),
+                      reinterpret_cast<double2*>(fe), reinterpret_cast<const double2*>(tau), w, S(stream));
+}
+
+size_t mlsdc_workspace_bytes(const sdc_level* f, const sdc_level* c, const mlsdc_opts* o) {
+    if (!f) return 0;
+    Carve cv{nullptr};
+    carve_step(cv, f, c, o);
+    return cv.used;
+}
+
+int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, double dt, const double* theta_n,
+               double* theta_np1, double* status, void* ws, size_t wsb, shx_stream_t stream) {
+    if (!fl || !o || !theta_n || !theta_np1 || !(dt > 0.0) || o->niter < 0 || o->nsweep_fine < 1 ||
+        (cl && o->nsweep_coarse < 1) || !aligned16(theta_n) || !aligned16(theta_np1) || !aligned16(ws) ||
+        !aligned16(status))
+        return SHX_EINVAL;
+    if (cl && (cl->kind != fl->kind || cl->plan->N >= fl->plan->N || cl->nnodes > fl->nnodes))
+        return SHX_EINVAL;
+    if (!alias_free(fl->plan) || (cl && !alias_free(cl->plan))) return SHX_ESHAPE;
+    if (!ws || wsb < mlsdc_workspace_bytes(fl, cl, o)) return SHX_EWORKSPACE;
+    Carve cv{static_cast<char*>(ws)};
+    StepWS w = carve_step(cv, fl, cl, o);
+    hipStream_t st = S(stream);
+    const shx_plan* pf = fl->plan;
+    const int Mf = fl->nnodes - 1;
+    const size_t nsf3 = 3 * (size_t)pf->nspec;
+    const double2* th_n = reinterpret_cast<const double2*>(theta_n);
+    // spread: Theta and F at every fine node equal those of Theta^n
+    HIPCHK(hipMemcpyAsync(w.thf, th_n, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    int rc = tendency_impl(pf, fl->p, 1, w.thf, w.fif, w.fef, w.swf.t, st);
+    if (rc) return rc;
+    for (int m = 1; m <= Mf; ++m) {
+        HIPCHK(hipMemcpyAsync(w.thf + m * nsf3, w.thf, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(w.fif + m * nsf3, w.fif, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(w.fef + m * nsf3, w.fef, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    }
+    Mat9x9 Pcf{}, Pfc{}, PQ{}, Qc{};
+    int Mc = 0;
+    size_t nsc3 = 0;
+    const shx_plan* pc = cl ? cl->plan : nullptr;
+    if (cl) {
+        Mc = cl->nnodes - 1;
+        nsc3 = 3 * (size_t)pc->nspec;
+        double a[81], b[81];
+        if (shx_host_transfer(fl->kind, fl->nnodes, cl->nnodes, a)) return SHX_EINVAL;   // [nc][nf]
+        if (shx_host_transfer(fl->kind, cl->nnodes, fl->nnodes, b)) return SHX_EINVAL;   // [nf][nc]
+        Pcf = to_mat(a, cl->nnodes * fl->nnodes);
+        Pfc = to_mat(b, fl->nnodes * cl->nnodes);
+        // Pi^c_f Q_f  [nc][nf]
+        for (int i = 0; i < cl->nnodes; ++i)
+            for (int j = 0; j < fl->nnodes; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < fl->nnodes; ++k) s += a[i * fl->nnodes + k] * fl->Q[k * fl->nnodes + j];
+                PQ.a[i * fl->nnodes + j] = s;
+            }
+        Qc = to_mat(cl->Q, cl->nnodes * cl->nnodes);
+        // coarse node 0: restricted initial value and its F, once per step
+        Mat9x9 e0{};
+        e0.a[0] = 1.0;
+        HIPCHK(launch_restrict(pf, pc, e0, 1, 0, 1, th_n, w.thc, st));
+        rc = tendency_impl(pc, cl->p, 1, w.thc, w.fic, w.fec, w.swc.t, st);
+        if (rc) return rc;
+    }
+    for (int k = 0; k < o->niter; ++k) {
+        // A) fine sweep(s)
+        for (int s = 0; s < o->nsweep_fine; ++s) {
+            rc = sweep_impl(fl, dt, w.thf, w.fif, w.fef, nullptr, w.swf, st);
+            if (rc) return rc;
+        }
+        if (!cl) continue;
+        // B) restrict nodes 1..Mc, evaluate, save the restriction
+        HIPCHK(launch_restrict(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.thf, w.thc, st));
+        rc = tendency_impl(pc, cl->p, Mc, w.thc + nsc3, w.fic + nsc3, w.fec + nsc3, w.tc, st);
+        if (rc) return rc;
+        const size_t cb = cl->nnodes * nsc3 * sizeof(double2);
+        HIPCHK(hipMemcpyAsync(w.thct, w.thc, cb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(w.fict, w.fic, cb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(w.fect, w.fec, cb, hipMemcpyDeviceToDevice, st));
+        // C) FAS correction and coarse sweep(s)
+        HIPCHK(launch_fas_tau(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.fif, w.fef, w.fic, w.fec, w.tau, st));
+        for (int s = 0; s < o->nsweep_coarse; ++s) {
+            rc = sweep_impl(cl, dt, w.thc, w.fic, w.fec, w.tau, w.swc, st);
+            if (rc) return rc;
+        }
+        // D) interpolate the coarse corrections of Theta, F_I, F_E
+        HIPCHK(launch_interp(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.thc, w.thct, w.fic, w.fict, w.fec, w.fect,
+                             w.thf, w.fif, w.fef, st));
+    }
+    double2* out = reinterpret_cast<double2*>(theta_np1);
+    HIPCHK(hipMemcpyAsync(out, w.thf + Mf * nsf3, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (status) {
+        const int nblk = residual_blocks(pf);
+        if (o->residual_check) {
+            rc = tendency_impl(pf, fl->p, fl->nnodes, w.thf, w.rfi, w.rfe, w.tr, st);
+            if (rc) return rc;
+            HIPCHK(launch_residual(pf, to_mat(fl->Q, fl->nnodes * fl->nnodes), Mf, dt, w.thf, w.rfi, w.rfe,
+                                   w.partial, nblk, st));
+        }
+        HIPCHK(launch_status(pf, w.partial, nblk, Mf, out, status, o->residual_check, st));
+    }
+    return SHX_OK;
+}
+
+}  // extern "C"

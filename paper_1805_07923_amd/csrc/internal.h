@@ -1,0 +1,118 @@
+// Internal types and device helpers of the MLSDC-SH library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/mlsdc_sh.h"
+
+// ------------------------------------------------------------------ layouts
+// Standard spectral layout (m = 0..N, n = m..N) and the extended layout used
+// inside the tendency (m = 0..N, n = m..N+1; the cos-weighted wind and the
+// flux analyses reach degree N+1).
+__host__ __device__ inline long long spec_idx(int N, int m, int n) {
+    return (long long)m * (2 * N + 3 - m) / 2 + (n - m);
+}
+__host__ __device__ inline long long ext_idx(int N, int m, int n) {
+    return (long long)m * (2 * N + 5 - m) / 2 + (n - m);
+}
+__host__ __device__ inline long long nspec_of(int N) { return (long long)(N + 1) * (N + 2) / 2; }
+__host__ __device__ inline long long nspec_ext_of(int N) { return (long long)(N + 1) * (N + 4) / 2; }
+
+// Rows of the parity block p (n - m = p mod 2) of order m for degrees <= nmax.
+__host__ __device__ inline int kcount(int nmax, int m, int p) {
+    return (nmax - m - p >= 0) ? (nmax - m - p) / 2 + 1 : 0;
+}
+
+// epsilon^m_n = sqrt((n^2 - m^2) / (4 n^2 - 1)), zero for n <= m.
+__host__ __device__ inline double eps_nm(int n, int m) {
+    if (n <= m) return 0.0;
+    const double nn = (double)n, mm = (double)m;
+    return sqrt((nn * nn - mm * mm) / (4.0 * nn * nn - 1.0));
+}
+
+// -------------------------------------------------------------------- plans
+struct shx_plan {
+    int N = 0, J = 0, I = 0, prec = 0, dev = 0;
+    int nmax = 0;                   // N + 1: degree range of tables / ext layout
+    int Jh = 0;                     // J / 2 latitude pairs
+    long long nspec = 0, nspec_e = 0;
+    double* mu = nullptr;           // device [J]
+    double* sint = nullptr;         // device [J]
+    double* cos2 = nullptr;         // device [J], 1 - mu^2
+    double* w = nullptr;            // device [J]
+    double2* tw = nullptr;          // device [I], e^{-2 pi i t / I}
+    double* psyn = nullptr;         // FP64 table, [m][p][k][jp]
+    double* pan = nullptr;          // FP64 table, [m][p][jp][k]
+    long long* off = nullptr;       // device [(N+1)*2] table offsets (elements)
+    int* ord = nullptr;             // device [nspec] zonal order of each entry
+    int* deg = nullptr;             // device [nspec] degree of each entry
+    int* ord_e = nullptr;           // device [nspec_e]
+    int* deg_e = nullptr;           // device [nspec_e]
+    long long table_elems = 0;
+    std::vector<double> h_mu, h_sint, h_cos2, h_w;
+    std::vector<long long> h_off;
+};
+
+struct sdc_level {
+    const shx_plan* plan = nullptr;
+    swe_params p{};
+    int kind = 0, nnodes = 0;
+    double tau[9]{}, Q[81]{}, QE[81]{}, QD[81]{};
+};
+
+// Small matrices passed by value to kernels.
+struct NodeWeights {
+    double q[9];      // dt * Q[m+1][j]
+    double qe[9];     // dt * QE[m+1][j]
+    double qd[9];     // dt * QD[m+1][j]
+};
+struct Mat9x9 {
+    double a[81];
+};
+
+// ----------------------------------------------------- launch wrappers
+// legendre.hip
+hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st);
+hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, int F, int S,
+                          int nmax_use, hipStream_t st);
+hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
+                         int nmax_use, hipStream_t st);
+// fourier.hip
+hipError_t launch_fft_inv(const shx_plan* pl, const double2* FI, double* grid, int F, hipStream_t st);
+hipError_t launch_fft_fwd(const shx_plan* pl, const double* grid, double2* G, int F, hipStream_t st);
+hipError_t launch_swe_grid(const shx_plan* pl, const double2* FI, double2* G, int S, double omega,
+                           hipStream_t st);
+bool fft_length_supported(int L);
+// spectral.hip
+hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, hipStream_t st);
+hipError_t launch_ext_to_spec(const shx_plan* pl, const double2* cout, double2* spec, int F, hipStream_t st);
+hipError_t launch_swe_prep(const shx_plan* pl, double a, const double2* state, double2* cin, int S,
+                           hipStream_t st);
+hipError_t launch_swe_combine(const shx_plan* pl, const swe_params& p, const double2* cout,
+                              const double2* state, double2* fi, double2* fe, int S, hipStream_t st);
+hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, const double2* rhs,
+                             double2* out, int S, hipStream_t st);
+hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const double2* state,
+                             double2* fi, int S, hipStream_t st);
+hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
+                           double h, const double2* theta0, double2* theta, const double2* fi,
+                           const double2* fe, const double2* fi_old, const double2* fe_old,
+                           const double2* tau, hipStream_t st);
+hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc,
+                           int i0, int i1, const double2* src, double2* dst, hipStream_t st);
+hipError_t launch_fas_tau(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ,
+                          const Mat9x9& Qc, int nf, int nc, double dt, const double2* fi_f,
+                          const double2* fe_f, const double2* fi_c, const double2* fe_c,
+                          double2* tau, hipStream_t st);
+hipError_t launch_interp(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pfc, int nf,
+                         int nc, const double2* th_c, const double2* th_ct, const double2* fi_c,
+                         const double2* fi_ct, const double2* fe_c, const double2* fe_ct,
+                         double2* th_f, double2* fi_f, double2* fe_f, hipStream_t st);
+hipError_t launch_residual(const shx_plan* pl, const Mat9x9& Q, int M, double dt, const double2* theta,
+                           const double2* fi, const double2* fe, double* partial, int nblk,
+                           hipStream_t st);
+hipError_t launch_status(const shx_plan* pl, const double* partial, int nblk, int M,
+                         const double2* theta_new, double* status, int residual_on, hipStream_t st);
+int residual_blocks(const shx_plan* pl);

@@ -1,0 +1,225 @@
+// Legendre step of the SH transform pair (Sec. 3): per zonal order m, the
+// contraction between the normalised P^m_n(mu_j) and the Fourier
+// coefficients, eq. spectral_to_physical_space (synthesis) and eq.
+// legendre_transform (analysis), FP64.
+//
+// Hemisphere symmetry: P^m_n(-mu) = (-1)^{n-m} P^m_n(mu), so each order m
+// splits into an even (p = 0) and an odd (p = 1) block of degrees n = m+2k+p
+// and only the nlat/2 northern latitudes are tabulated:
+//   synthesis  E_m(mu_j) = sum_{p=0 rows} xi P,  O_m(mu_j) = sum_{p=1 rows} xi P,
+//              north = E + O, south = E - O;
+//   analysis   xi^m_n = sum_{j < J/2} P^m_n(mu_j) (g_north +/- g_south).
+// The tables are built once per plan by an FP64 recurrence on the device and
+// kept in two layouts so that both kernels read them with unit stride across
+// the 64 lanes of a wavefront: psyn[m][p][k][jp] (lanes = latitudes) and
+// pan[m][p][jp][k] (lanes = degrees).  The second operand of each
+// contraction (spectral coefficients resp. Fourier coefficients of one
+// latitude) is the same for every lane and is read through the scalar cache.
+#include "internal.h"
+
+namespace {
+
+constexpr int UNR = 8;
+
+// P^m_n(mu_j) for one (m, jp) by the standard recurrence of the orthonormal
+// functions: P^0_0 = 1/sqrt(2); P^m_m = sqrt((2m+1)/(2m)) sin(theta) P^{m-1}_{m-1};
+// P^m_{m+1} = sqrt(2m+3) mu P^m_m; eps^m_n P^m_n = mu P^m_{n-1} - eps^m_{n-1} P^m_{n-2}.
+__global__ void k_plm_table(const double* __restrict__ mu, const double* __restrict__ sint,
+                            const long long* __restrict__ off, double* __restrict__ psyn,
+                            double* __restrict__ pan, int N, int nmax, int Jh) {
+    const int jp = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (jp >= Jh) return;
+    const double x = mu[jp], s = sint[jp];
+    double pmm = 0.70710678118654752440;   // 1/sqrt(2)
+    for (int k = 1; k <= m; ++k) pmm *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+    const int K0 = kcount(nmax, m, 0), K1 = kcount(nmax, m, 1);
+    double* ps0 = psyn + off[2 * m];
+    double* ps1 = psyn + off[2 * m + 1];
+    double* pa0 = pan + off[2 * m];
+    double* pa1 = pan + off[2 * m + 1];
+    double p2 = 0.0, p1 = pmm;   // P_{n-2}, P_{n-1}
+    for (int n = m; n <= nmax; ++n) {
+        double pn;
+        if (n == m) pn = pmm;
+        else if (n == m + 1) pn = sqrt(2.0 * m + 3.0) * x * pmm;
+        else pn = (x * p1 - eps_nm(n - 1, m) * p2) / eps_nm(n, m);
+        if (n > m) { p2 = p1; p1 = pn; }
+        const int p = (n - m) & 1, k = (n - m) >> 1;
+        if (p == 0) {
+            ps0[(long long)k * Jh + jp] = pn;
+            pa0[(long long)jp * K0 + k] = pn;
+        } else {
+            ps1[(long long)k * Jh + jp] = pn;
+            pa1[(long long)jp * K1 + k] = pn;
+        }
+    }
+}
+
+// Synthesis: out[s][p][jp][m][f0+f] = sum_k P[m][p][k][jp] cin[s][ext(m, m+2k+p)][f0+f].
+// grid (ceil(Jh/64), N+1, 2), 64 lanes = latitudes.
+template <int NF>
+__global__ __launch_bounds__(64) void k_leg_syn(const double* __restrict__ psyn,
+                                                const long long* __restrict__ off,
+                                                const double2* __restrict__ cin,
+                                                double2* __restrict__ out, int N, int nmax_use,
+                                                int Jh, int F, int f0, int S, long long cin_stride,
+                                                long long out_stride) {
+    const int jp = blockIdx.x * 64 + threadIdx.x;
+    const int m = blockIdx.y, p = blockIdx.z;
+    if (jp >= Jh) return;
+    const int K = kcount(nmax_use, m, p);
+    const double* P = psyn + off[2 * m + p] + jp;
+    const long long e0 = ext_idx(N, m, m + p);
+    for (int s = 0; s < S; ++s) {
+        const double2* c = cin + s * cin_stride + e0 * F + f0;
+        double ar[NF], ai[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
+        int k = 0;
+        // UNR table loads in flight per lane before the FMAs consume them
+        for (; k + UNR <= K; k += UNR) {
+            double pv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(k + u) * Jh];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const double2* ck = c + (long long)(2 * (k + u)) * F;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    ar[f] = fma(pv[u], ck[f].x, ar[f]);
+                    ai[f] = fma(pv[u], ck[f].y, ai[f]);
+                }
+            }
+        }
+        for (; k < K; ++k) {
+            const double pv = P[(long long)k * Jh];
+            const double2* ck = c + (long long)(2 * k) * F;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                ar[f] = fma(pv, ck[f].x, ar[f]);
+                ai[f] = fma(pv, ck[f].y, ai[f]);
+            }
+        }
+        double2* o = out + s * out_stride + (((long long)p * Jh + jp) * (N + 1) + m) * F + f0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) o[f] = make_double2(ar[f], ai[f]);
+    }
+}
+
+// Analysis: cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
+// grid (ceil(K/64), N+1, 2), 64 lanes = degrees.
+template <int NF>
+__global__ __launch_bounds__(64) void k_leg_an(const double* __restrict__ pan,
+                                               const long long* __restrict__ off,
+                                               const double2* __restrict__ G,
+                                               double2* __restrict__ cout, int N, int nmax_tab,
+                                               int nmax_use, int J, int F, int f0, int S,
+                                               long long G_stride, long long cout_stride) {
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    const int m = blockIdx.y, p = blockIdx.z;
+    const int K = kcount(nmax_use, m, p);
+    if (k >= K) return;
+    const int Ktab = kcount(nmax_tab, m, p);
+    const int Jh = J / 2;
+    const double* P = pan + off[2 * m + p] + k;
+    const double sg = p ? -1.0 : 1.0;
+    const long long rowstride = (long long)(N + 1) * F;
+    for (int s = 0; s < S; ++s) {
+        const double2* g = G + s * G_stride + (long long)m * F + f0;
+        double ar[NF], ai[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
+        int jp = 0;
+        for (; jp + UNR <= Jh; jp += UNR) {
+            double pv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const double2* gn = g + (jp + u) * rowstride;
+                const double2* gs = g + (J - 1 - jp - u) * rowstride;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    ar[f] = fma(pv[u], gn[f].x + sg * gs[f].x, ar[f]);
+                    ai[f] = fma(pv[u], gn[f].y + sg * gs[f].y, ai[f]);
+                }
+            }
+        }
+        for (; jp < Jh; ++jp) {
+            const double pv = P[(long long)jp * Ktab];
+            const double2* gn = g + jp * rowstride;
+            const double2* gs = g + (J - 1 - jp) * rowstride;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                ar[f] = fma(pv, gn[f].x + sg * gs[f].x, ar[f]);
+                ai[f] = fma(pv, gn[f].y + sg * gs[f].y, ai[f]);
+            }
+        }
+        double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) o[f] = make_double2(ar[f], ai[f]);
+    }
+}
+
+template <int NF>
+void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S,
+               int nmax_use, hipStream_t st) {
+    dim3 grid((pl->Jh + 63) / 64, pl->N + 1, 2);
+    k_leg_syn<NF><<<grid, 64, 0, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F, f0, S,
+                                       pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F);
+}
+
+template <int NF>
+void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
+              hipStream_t st) {
+    const int kmax = kcount(nmax_use, 0, 0);
+    dim3 grid((kmax + 63) / 64, pl->N + 1, 2);
+    k_leg_an<NF><<<grid, 64, 0, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use, pl->J, F,
+                                      f0, S, (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F);
+}
+
+}  // namespace
+
+hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
+    dim3 grid((pl->Jh + 63) / 64, pl->N + 1);
+    k_plm_table<<<grid, 64, 0, st>>>(pl->mu, pl->sint, pl->off, pl->psyn, pl->pan, pl->N, pl->nmax, pl->Jh);
+    return hipGetLastError();
+}
+
+// Fields are processed in chunks of at most 8 (16 accumulators per lane).
+hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, int F, int S,
+                          int nmax_use, hipStream_t st) {
+    for (int f0 = 0; f0 < F; f0 += 8) {
+        const int nf = (F - f0 < 8) ? F - f0 : 8;
+        switch (nf) {
+            case 1: syn_chunk<1>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            case 2: syn_chunk<2>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            case 3: syn_chunk<3>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            case 4: syn_chunk<4>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            case 5: syn_chunk<5>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            case 6: syn_chunk<6>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            case 7: syn_chunk<7>(pl, cin, out, F, f0, S, nmax_use, st); break;
+            default: syn_chunk<8>(pl, cin, out, F, f0, S, nmax_use, st); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
+                         int nmax_use, hipStream_t st) {
+    for (int f0 = 0; f0 < F; f0 += 8) {
+        const int nf = (F - f0 < 8) ? F - f0 : 8;
+        switch (nf) {
+            case 1: an_chunk<1>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 2: an_chunk<2>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 3: an_chunk<3>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 4: an_chunk<4>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 5: an_chunk<5>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 6: an_chunk<6>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 7: an_chunk<7>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            default: an_chunk<8>(pl, G, cout, F, f0, S, nmax_use, st); break;
+        }
+    }
+    return hipGetLastError();
+}

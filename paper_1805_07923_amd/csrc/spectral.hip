@@ -1,0 +1,457 @@
+// Spectral-space kernels, FP64, one thread per coefficient (m, n):
+//   * wind coefficients and combine of the shallow-water tendency (Sec. 2-3);
+//   * the diagonal implicit solve (Sec. 4.4, eq. implicit_systems);
+//   * the node update of the IMEX SDC sweep (Sec. 4.2, eq.
+//     update_equation_sdcq_discrete_form; Sec. 4.3.1, eq.
+//     modified_update_equation_sdcq_discrete_form);
+//   * the FAS term (Sec. 4.3.1, eq. tau_term_level_l+1) and the space-time
+//     transfer by truncation / zero padding and Lagrange interpolation in time
+//     (Sec. 4.3.3);
+//   * the collocation residual (Sec. 4.2, eq. collocation_problem).
+// The spectral form of the right-hand side is derived from Sec. 2 (the paper
+// defers it to other work); with L_n = n (n+1) / a^2, psi = -zeta / L_n and
+// chi = -delta / L_n (zero at n = 0):
+//   U_n = [(n-1) eps_n psi_{n-1} - (n+2) eps_{n+1} psi_{n+1} + i m chi_n] / a,
+//   V_n = [i m psi_n - (n-1) eps_n chi_{n-1} + (n+2) eps_{n+1} chi_{n+1}] / a,
+// for the cos-weighted wind (U, V) = (u, v) cos(phi), and for the weighted
+// analyses X^, Y^ of a cos-weighted flux
+//   div_n  = [i m X^_n + n eps_{n+1} Y^_{n+1} - (n+1) eps_n Y^_{n-1}] / a,
+//   curl_n = [i m Y^_n - n eps_{n+1} X^_{n+1} + (n+1) eps_n X^_{n-1}] / a.
+#include "internal.h"
+
+namespace {
+
+constexpr int TB = 256;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 caxpy(double s, double2 a, double2 y) {
+    return make_double2(fma(s, a.x, y.x), fma(s, a.y, y.y));
+}
+// i * m * a
+__device__ __forceinline__ double2 cim(double m, double2 a) { return make_double2(-m * a.y, m * a.x); }
+
+__global__ void k_spec_to_ext(const int* __restrict__ ord_e, const int* __restrict__ deg_e,
+                              const double2* __restrict__ spec, double2* __restrict__ cin, int N,
+                              long long nspec, long long nspec_e, int F) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e >= nspec_e) return;
+    const int m = ord_e[e], n = deg_e[e];
+    for (int f = 0; f < F; ++f)
+        cin[e * F + f] = (n <= N) ? spec[f * nspec + spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+}
+
+__global__ void k_ext_to_spec(const int* __restrict__ ord, const int* __restrict__ deg,
+                              const double2* __restrict__ cout, double2* __restrict__ spec, int N,
+                              long long nspec, int F) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    if (i >= nspec) return;
+    const long long e = ext_idx(N, ord[i], deg[i]);
+    for (int f = 0; f < F; ++f) spec[f * nspec + i] = cout[e * F + f];
+}
+
+// cin[s][e][0..3] = (zeta, Phi', U, V) at (m, n = deg_e[e]), n <= N+1.
+__global__ void k_swe_prep(const int* __restrict__ ord_e, const int* __restrict__ deg_e,
+                           const double2* __restrict__ state, double2* __restrict__ cin, int N,
+                           long long nspec, long long nspec_e, double a, int S) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (e >= nspec_e || s >= S) return;
+    const int m = ord_e[e], n = deg_e[e];
+    const double2* phi = state + (long long)s * 3 * nspec;
+    const double2* zeta = phi + nspec;
+    const double2* delta = zeta + nspec;
+    const double a2 = a * a;
+    auto get = [&](const double2* x, int nn) -> double2 {
+        if (nn < m || nn > N || nn < 1) return make_double2(0.0, 0.0);
+        const double L = nn * (nn + 1.0) / a2;
+        const double2 v = x[spec_idx(N, m, nn)];
+        return make_double2(-v.x / L, -v.y / L);   // -x / L_n: psi or chi
+    };
+    const double c_dn = (n - 1.0) * eps_nm(n, m);
+    const double c_up = (n + 2.0) * eps_nm(n + 1, m);
+    const double2 psd = get(zeta, n - 1), ps0 = get(zeta, n), psu = get(zeta, n + 1);
+    const double2 chd = get(delta, n - 1), ch0 = get(delta, n), chu = get(delta, n + 1);
+    const double ia = 1.0 / a;
+    double2 U = cadd(make_double2(c_dn * psd.x - c_up * psu.x, c_dn * psd.y - c_up * psu.y), cim(m, ch0));
+    double2 V = cadd(cim(m, ps0), make_double2(-c_dn * chd.x + c_up * chu.x, -c_dn * chd.y + c_up * chu.y));
+    double2* o = cin + ((long long)s * nspec_e + e) * 4;
+    o[0] = (n <= N) ? zeta[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+    o[1] = (n <= N) ? phi[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+    o[2] = cscale(ia, U);
+    o[3] = cscale(ia, V);
+}
+
+// F_E, F_I from the weighted analyses (A, B, C, D, E) and the state.
+__global__ void k_swe_combine(const int* __restrict__ ord, const int* __restrict__ deg,
+                              const double2* __restrict__ cout, const double2* __restrict__ state,
+                              double2* __restrict__ fi, double2* __restrict__ fe, int N, long long nspec,
+                              long long nspec_e, swe_params p, int S) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= nspec || s >= S) return;
+    const int m = ord[i], n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    const double2* st = state + (long long)s * 3 * nspec;
+    if (fe) {
+        const double2* c = cout + (long long)s * nspec_e * 5;
+        const double2* x0 = c + ext_idx(N, m, n) * 5;
+        const double2* xu = c + ext_idx(N, m, n + 1) * 5;
+        const double2 zero = make_double2(0.0, 0.0);
+        const bool has_dn = (n - 1 >= m);
+        const double2* xd = has_dn ? c + ext_idx(N, m, n - 1) * 5 : nullptr;
+        const double cu = n * eps_nm(n + 1, m), cd = (n + 1.0) * eps_nm(n, m);
+        const double ia = 1.0 / p.a;
+        auto div = [&](int X, int Y) {
+            double2 r = cim(m, x0[X]);
+            r = caxpy(cu, xu[Y], r);
+            r = caxpy(-cd, has_dn ? xd[Y] : zero, r);
+            return cscale(ia, r);
+        };
+        auto curl = [&](int X, int Y) {
+            double2 r = cim(m, x0[Y]);
+            r = caxpy(-cu, xu[X], r);
+            r = caxpy(cd, has_dn ? xd[X] : zero, r);
+            return cscale(ia, r);
+        };
+        const double2 dcd = div(2, 3), dab = div(0, 1), cab = curl(0, 1);
+        double2* o = fe + (long long)s * 3 * nspec;
+        o[i] = make_double2(-dcd.x, -dcd.y);
+        o[nspec + i] = make_double2(-dab.x, -dab.y);
+        o[2 * nspec + i] = caxpy(L, x0[4], cab);
+    }
+    if (fi) {
+        const double2 ph = st[i], ze = st[nspec + i], de = st[2 * nspec + i];
+        double2* o = fi + (long long)s * 3 * nspec;
+        o[i] = make_double2(-p.phibar * de.x - p.nu * L * ph.x, -p.phibar * de.y - p.nu * L * ph.y);
+        o[nspec + i] = make_double2(-p.nu * L * ze.x, -p.nu * L * ze.y);
+        o[2 * nspec + i] = make_double2(L * ph.x - p.nu * L * de.x, L * ph.y - p.nu * L * de.y);
+    }
+}
+
+__device__ __forceinline__ void solve_one(double L, double h, const swe_params& p, double2 bp, double2 bz,
+                                          double2 bd, double2& xp, double2& xz, double2& xd) {
+    // (1 + h nu L) Phi' + h Phibar delta = b_Phi ; (1 + h nu L) delta - h L Phi' = b_delta
+    const double c = 1.0 + h * p.nu * L;
+    const double den = c * c + h * h * p.phibar * L;
+    xp = make_double2((c * bp.x - h * p.phibar * bd.x) / den, (c * bp.y - h * p.phibar * bd.y) / den);
+    xd = make_double2((bd.x + h * L * xp.x) / c, (bd.y + h * L * xp.y) / c);
+    xz = make_double2(bz.x / c, bz.y / c);
+}
+
+__global__ void k_imex_solve(const int* __restrict__ deg, const double2* rhs, double2* out, long long nspec,
+                             swe_params p, double h, int S) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= nspec || s >= S) return;
+    const int n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    const double2* b = rhs + (long long)s * 3 * nspec;
+    double2* x = out + (long long)s * 3 * nspec;
+    double2 xp, xz, xd;
+    solve_one(L, h, p, b[i], b[nspec + i], b[2 * nspec + i], xp, xz, xd);
+    x[i] = xp;
+    x[nspec + i] = xz;
+    x[2 * nspec + i] = xd;
+}
+
+__global__ void k_f_implicit(const int* __restrict__ deg, const double2* __restrict__ st,
+                             double2* __restrict__ fi, long long nspec, swe_params p, int S) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= nspec || s >= S) return;
+    const int n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    const double2* x = st + (long long)s * 3 * nspec;
+    double2* o = fi + (long long)s * 3 * nspec;
+    const double2 ph = x[i], ze = x[nspec + i], de = x[2 * nspec + i];
+    o[i] = make_double2(-p.phibar * de.x - p.nu * L * ph.x, -p.phibar * de.y - p.nu * L * ph.y);
+    o[nspec + i] = make_double2(-p.nu * L * ze.x, -p.nu * L * ze.y);
+    o[2 * nspec + i] = make_double2(L * ph.x - p.nu * L * de.x, L * ph.y - p.nu * L * de.y);
+}
+
+// Node update of the sweep for node m+1 (m = 0..M-1):
+//   b = Theta^0 + sum_j dtQ[m+1][j] (F_I + F_E)^{j,old}
+//       + sum_{j=1}^{m} [dtQE[m+1][j] dF_E^j + dtQD[m+1][j] dF_I^j]
+//       - h F_I^{m+1,old} + tau^{m+1},   Theta^{m+1} = solve(b, h).
+__global__ void k_sdc_node(const int* __restrict__ deg, long long nspec, swe_params p, int m, int M,
+                           NodeWeights wt, double h, const double2* __restrict__ th0,
+                           double2* __restrict__ theta, const double2* __restrict__ fi,
+                           const double2* __restrict__ fe, const double2* __restrict__ fi_old,
+                           const double2* __restrict__ fe_old, const double2* __restrict__ tau) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    if (i >= nspec) return;
+    const long long ns3 = 3 * nspec;
+    double2 b[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const long long o = c * nspec + i;
+        double2 acc = th0[o];
+        for (int j = 0; j <= M; ++j) {
+            const double2 f = cadd(fi_old[j * ns3 + o], fe_old[j * ns3 + o]);
+            acc = caxpy(wt.q[j], f, acc);
+        }
+        for (int j = 1; j <= m; ++j) {
+            acc = caxpy(wt.qe[j], csub(fe[j * ns3 + o], fe_old[j * ns3 + o]), acc);
+            acc = caxpy(wt.qd[j], csub(fi[j * ns3 + o], fi_old[j * ns3 + o]), acc);
+        }
+        acc = caxpy(-h, fi_old[(m + 1) * ns3 + o], acc);
+        if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + o]);
+        b[c] = acc;
+    }
+    const int n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    double2 xp, xz, xd;
+    solve_one(L, h, p, b[0], b[1], b[2], xp, xz, xd);
+    double2* out = theta + (m + 1) * ns3;
+    out[i] = xp;
+    out[nspec + i] = xz;
+    out[2 * nspec + i] = xd;
+}
+
+// dst[i][c] = sum_j Pi[i][j] src[j][map(c)], i in [i0, i1); c runs over the
+// coarse coefficients, map(c) is the fine index of the same (m, n).
+__global__ void k_restrict(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
+                           long long nsf, long long nsc, Mat9x9 Pi, int nsrc, int i0, int i1,
+                           const double2* __restrict__ src, double2* __restrict__ dst) {
+    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    if (c >= nsc) return;
+    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+    for (int i = i0; i < i1; ++i) {
+        for (int f = 0; f < 3; ++f) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = 0; j < nsrc; ++j) {
+                const double w = Pi.a[i * nsrc + j];
+                if (w != 0.0) acc = caxpy(w, src[(j * 3 + f) * nsf + fidx], acc);
+            }
+            dst[(i * 3 + f) * nsc + c] = acc;
+        }
+    }
+}
+
+// tau_c^i = dt [sum_j (Pi Q_f)_{ij} D(F_f^j) - sum_j (Q_c)_{ij} F_c^j], i = 0..nc-1.
+__global__ void k_fas_tau(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
+                          long long nsf, long long nsc, Mat9x9 PQ, Mat9x9 Qc, int nf, int nc, double dt,
+                          const double2* __restrict__ fi_f, const double2* __restrict__ fe_f,
+                          const double2* __restrict__ fi_c, const double2* __restrict__ fe_c,
+                          double2* __restrict__ tau) {
+    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    if (c >= nsc) return;
+    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+    for (int i = 0; i < nc; ++i) {
+        for (int f = 0; f < 3; ++f) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = 0; j < nf; ++j) {
+                const long long o = (j * 3 + f) * nsf + fidx;
+                acc = caxpy(PQ.a[i * nf + j], cadd(fi_f[o], fe_f[o]), acc);
+            }
+            for (int j = 0; j < nc; ++j) {
+                const long long o = (j * 3 + f) * nsc + c;
+                acc = caxpy(-Qc.a[i * nc + j], cadd(fi_c[o], fe_c[o]), acc);
+            }
+            tau[(i * 3 + f) * nsc + c] = cscale(dt, acc);
+        }
+    }
+}
+
+// For fine nodes m = 1..nf-1: X_f^m += Pad(sum_i Pfc[m][i] (X_c^i - X~_c^i)) for
+// X in {Theta, F_I, F_E}; only the coefficients with n <= N_c change.
+__global__ void k_interp(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
+                         long long nsf, long long nsc, Mat9x9 P, int nf, int nc,
+                         const double2* __restrict__ thc, const double2* __restrict__ thct,
+                         const double2* __restrict__ fic, const double2* __restrict__ fict,
+                         const double2* __restrict__ fec, const double2* __restrict__ fect,
+                         double2* __restrict__ thf, double2* __restrict__ fif, double2* __restrict__ fef) {
+    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    if (c >= nsc) return;
+    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+    for (int f = 0; f < 3; ++f) {
+        double2 dth[9], dfi[9], dfe[9];
+        for (int i = 0; i < nc; ++i) {
+            const long long o = (i * 3 + f) * nsc + c;
+            dth[i] = csub(thc[o], thct[o]);
+            dfi[i] = csub(fic[o], fict[o]);
+            dfe[i] = csub(fec[o], fect[o]);
+        }
+        for (int m = 1; m < nf; ++m) {
+            double2 a = make_double2(0.0, 0.0), b = a, d = a;
+            for (int i = 0; i < nc; ++i) {
+                const double w = P.a[m * nc + i];
+                a = caxpy(w, dth[i], a);
+                b = caxpy(w, dfi[i], b);
+                d = caxpy(w, dfe[i], d);
+            }
+            const long long o = (m * 3 + f) * nsf + fidx;
+            thf[o] = cadd(thf[o], a);
+            fif[o] = cadd(fif[o], b);
+            fef[o] = cadd(fef[o], d);
+        }
+    }
+}
+
+// Per-block partial sums for the residual: [blk][M+1] of ||r^m||^2 (m >= 1)
+// and slot 0 holds ||Theta^0||^2.  r^m = Theta^0 + dt sum_j Q[m][j] F^j - Theta^m.
+__global__ void k_residual(long long nspec, Mat9x9 Q, int M, double dt, const double2* __restrict__ th,
+                           const double2* __restrict__ fi, const double2* __restrict__ fe,
+                           double* __restrict__ partial) {
+    __shared__ double red[TB];
+    const long long ns3 = 3 * nspec;
+    double loc[10];
+    for (int m = 0; m <= M; ++m) loc[m] = 0.0;
+    for (long long o = (long long)blockIdx.x * TB + threadIdx.x; o < ns3; o += (long long)gridDim.x * TB) {
+        const double2 t0 = th[o];
+        loc[0] += t0.x * t0.x + t0.y * t0.y;
+        for (int m = 1; m <= M; ++m) {
+            double2 r = t0;
+            for (int j = 0; j <= M; ++j) r = caxpy(dt * Q.a[m * (M + 1) + j], cadd(fi[j * ns3 + o], fe[j * ns3 + o]), r);
+            r = csub(r, th[m * ns3 + o]);
+            loc[m] += r.x * r.x + r.y * r.y;
+        }
+    }
+    for (int m = 0; m <= M; ++m) {
+        red[threadIdx.x] = loc[m];
+        __syncthreads();
+        for (int w = TB / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x * (M + 1) + m] = red[0];
+        __syncthreads();
+    }
+}
+
+// status[0] = max_m sqrt(sum r^m) / sqrt(sum Theta^0) (or 0); status[1] = any non-finite.
+__global__ void k_status(const double* __restrict__ partial, int nblk, int M, const double2* __restrict__ th,
+                         long long n3, double* __restrict__ status, int residual_on) {
+    __shared__ int bad;
+    __shared__ double red[TB];
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    int lbad = 0;
+    for (long long o = threadIdx.x; o < n3; o += TB) {
+        const double2 v = th[o];
+        if (!isfinite(v.x) || !isfinite(v.y)) lbad = 1;
+    }
+    if (lbad) atomicOr(&bad, 1);
+    double res = 0.0;
+    if (residual_on) {
+        double s0 = 0.0;
+        for (int m = 0; m <= M; ++m) {
+            double loc = 0.0;
+            for (int b = threadIdx.x; b < nblk; b += TB) loc += partial[b * (M + 1) + m];
+            red[threadIdx.x] = loc;
+            __syncthreads();
+            for (int w = TB / 2; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            const double tot = red[0];
+            __syncthreads();
+            if (m == 0) s0 = tot;
+            else res = fmax(res, sqrt(tot));
+        }
+        res = (s0 > 0.0) ? res / sqrt(s0) : res;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        status[0] = res;
+        status[1] = bad ? 1.0 : 0.0;
+    }
+}
+
+inline unsigned nblocks(long long n) { return (unsigned)((n + TB - 1) / TB); }
+
+}  // namespace
+
+hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, hipStream_t st) {
+    k_spec_to_ext<<<nblocks(pl->nspec_e), TB, 0, st>>>(pl->ord_e, pl->deg_e, spec, cin, pl->N, pl->nspec,
+                                                        pl->nspec_e, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_ext_to_spec(const shx_plan* pl, const double2* cout, double2* spec, int F, hipStream_t st) {
+    k_ext_to_spec<<<nblocks(pl->nspec), TB, 0, st>>>(pl->ord, pl->deg, cout, spec, pl->N, pl->nspec, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_swe_prep(const shx_plan* pl, double a, const double2* state, double2* cin, int S,
+                           hipStream_t st) {
+    dim3 g(nblocks(pl->nspec_e), S);
+    k_swe_prep<<<g, TB, 0, st>>>(pl->ord_e, pl->deg_e, state, cin, pl->N, pl->nspec, pl->nspec_e, a, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_swe_combine(const shx_plan* pl, const swe_params& p, const double2* cout,
+                              const double2* state, double2* fi, double2* fe, int S, hipStream_t st) {
+    dim3 g(nblocks(pl->nspec), S);
+    k_swe_combine<<<g, TB, 0, st>>>(pl->ord, pl->deg, cout, state, fi, fe, pl->N, pl->nspec, pl->nspec_e, p, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, const double2* rhs,
+                             double2* out, int S, hipStream_t st) {
+    dim3 g(nblocks(pl->nspec), S);
+    k_imex_solve<<<g, TB, 0, st>>>(pl->deg, rhs, out, pl->nspec, p, h, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const double2* state, double2* fi,
+                             int S, hipStream_t st) {
+    dim3 g(nblocks(pl->nspec), S);
+    k_f_implicit<<<g, TB, 0, st>>>(pl->deg, state, fi, pl->nspec, p, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
+                           double h, const double2* theta0, double2* theta, const double2* fi,
+                           const double2* fe, const double2* fi_old, const double2* fe_old,
+                           const double2* tau, hipStream_t st) {
+    k_sdc_node<<<nblocks(pl->nspec), TB, 0, st>>>(pl->deg, pl->nspec, p, m, M, wts, h, theta0, theta, fi, fe,
+                                                   fi_old, fe_old, tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc, int i0,
+                           int i1, const double2* src, double2* dst, hipStream_t st) {
+    k_restrict<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
+                                                       coarse->nspec, Pi, nsrc, i0, i1, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fas_tau(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ, const Mat9x9& Qc,
+                          int nf, int nc, double dt, const double2* fi_f, const double2* fe_f,
+                          const double2* fi_c, const double2* fe_c, double2* tau, hipStream_t st) {
+    k_fas_tau<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
+                                                      coarse->nspec, PQ, Qc, nf, nc, dt, fi_f, fe_f, fi_c, fe_c,
+                                                      tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pfc, int nf, int nc,
+                         const double2* th_c, const double2* th_ct, const double2* fi_c, const double2* fi_ct,
+                         const double2* fe_c, const double2* fe_ct, double2* th_f, double2* fi_f,
+                         double2* fe_f, hipStream_t st) {
+    k_interp<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
+                                                     coarse->nspec, Pfc, nf, nc, th_c, th_ct, fi_c, fi_ct, fe_c,
+                                                     fe_ct, th_f, fi_f, fe_f);
+    return hipGetLastError();
+}
+
+int residual_blocks(const shx_plan* pl) {
+    long long n = 3 * pl->nspec;
+    long long b = (n + TB - 1) / TB;
+    return (int)(b < 512 ? b : 512);
+}
+
+hipError_t launch_residual(const shx_plan* pl, const Mat9x9& Q, int M, double dt, const double2* theta,
+                           const double2* fi, const double2* fe, double* partial, int nblk, hipStream_t st) {
+    k_residual<<<nblk, TB, 0, st>>>(pl->nspec, Q, M, dt, theta, fi, fe, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_status(const shx_plan* pl, const double* partial, int nblk, int M, const double2* theta_new,
+                         double* status, int residual_on, hipStream_t st) {
+    k_status<<<1, TB, 0, st>>>(partial, nblk, M, theta_new, 3 * pl->nspec, status, residual_on);
+    return hipGetLastError();
+}
