@@ -1,0 +1,259 @@
+"""Benchmark of the MLSDC-SH hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph]
+
+A step is one two-level MLSDC time step (Algorithm 1 of the paper) on the
+headline workload: fine level T255 on the 768 x 384 Gaussian grid with 5
+Gauss-Lobatto nodes, coarse level T127 on 384 x 192 with 3 nodes, 2 fine and
+2 coarse sweeps per iteration, 4 iterations, dt = 300 s, FP64, on seeded
+synthetic fields (spectra with variance ~ (n+1)^-3, max wind 40 m/s, max
+|Phi'| = 1 % of the mean geopotential) that stand in for the paper's
+R_f = 256 test cases.  Inputs are resident in HBM before timing.
+
+Prints one JSON line with the throughput (steps/s), the roofline of the
+dominant kernel (its launch durations measured with HIP events on its own
+stream during an instrumented pass over the same steps), the oracle timed on
+the host cores, and secondary figures (Legendre GFLOP/s of the 15-field T255
+transform pair, the paper's 1+1 sweep variant, the T127/T63 configuration).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLSDC-SH steps/s and Legendre GFLOP/s at T255, FP64 vs mixed; adjoint s/step"
+HBM_PEAK_GBS = 8000.0
+
+FINE = dict(N=255, J=384, I=768, nodes=5)
+COARSE = dict(N=127, J=192, I=384, nodes=3)
+C1_FINE = dict(N=127, J=192, I=384, nodes=5)
+C1_COARSE = dict(N=63, J=96, I=192, nodes=3)
+DT = 300.0
+NITER, NSWEEP = 4, 2
+SEED = 1005
+
+
+def kcount(nmax, m, p):
+    return (nmax - m - p) // 2 + 1 if nmax - m - p >= 0 else 0
+
+
+def legendre_bytes(N, J, F, nmax):
+    """Algorithmic HBM bytes of one Legendre launch with the FP64 tables:
+    the table rows for degrees <= nmax (read once), the F-field input and
+    the F-field output (each touched once)."""
+    Jh = J // 2
+    table = sum(kcount(nmax, m, p) for m in range(N + 1) for p in (0, 1)) * Jh * 8
+    ext = (N + 1) * (N + 4) // 2
+    fourier = J * (N + 1) * F * 16
+    return table + fourier + ext * F * 16, table
+
+
+def legendre_flops(N, J, F, nmax):
+    Jh = J // 2
+    rows = sum(kcount(nmax, m, p) for m in range(N + 1) for p in (0, 1))
+    return 4.0 * rows * Jh * F
+
+
+def make_stepper(pk, fine, coarse, niter, nsweep, residual=False):
+    par = pk.swe_params()
+    pf = pk.Plan(fine["N"], fine["J"], fine["I"])
+    lf = pk.Level(pf, par, pk.SDC_GAUSS_LOBATTO, fine["nodes"])
+    lc = None
+    if coarse:
+        pc = pk.Plan(coarse["N"], coarse["J"], coarse["I"])
+        lc = pk.Level(pc, par, pk.SDC_GAUSS_LOBATTO, coarse["nodes"])
+    return pk.Stepper(lf, lc, niter=niter, nsweep_fine=nsweep, nsweep_coarse=nsweep, residual_check=residual)
+
+
+def run_steps(torch, stepper, x0, steps, warmup, graph):
+    """Returns (seconds for `steps` steps, final state)."""
+    a = x0.clone()
+    b = torch.empty_like(a)
+    for _ in range(warmup):
+        stepper.step(DT, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            stepper.step(DT, a, b)           # workspaces exist before capture
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                stepper.step(DT, a, b)
+                # copy back so that each replay advances the state by one step
+                a.copy_(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, a
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stepper.step(DT, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, a
+
+
+def cpu_baseline(state_np):
+    """The oracle's MLSDC step on the host cores: one step of the same workload."""
+    import torch
+    from oracle import sdc as OS
+    from oracle import swe as OW
+    pf = OW.SWEProblem(FINE["N"], FINE["J"], FINE["I"])
+    pc = OW.SWEProblem(COARSE["N"], COARSE["J"], COARSE["I"])
+    lf = OS.Level(pf, "lobatto", FINE["nodes"])
+    lc = OS.Level(pc, "lobatto", COARSE["nodes"])
+    R, P = OS.spectral_transfer(FINE["N"], COARSE["N"])
+    x = torch.tensor(state_np)
+    t0 = time.perf_counter()
+    OS.mlsdc_step(lf, lc, DT, x, niter=NITER, nsweep_fine=NSWEEP, nsweep_coarse=NSWEEP,
+                  restrict_space=R, interp_space=P)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "1 step of the same T255/T127 (2,2)x4 workload (plain FP64 torch-CPU oracle), "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "
+              "across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1805_07923_amd as pk
+    import workload
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    pk.lib()
+    torch.cuda.set_device(0)
+    state_np = workload.state(FINE["N"], SEED)
+    x0 = torch.tensor(state_np, device="cuda")
+
+    stepper = make_stepper(pk, FINE, COARSE, NITER, NSWEEP)
+    graph = not args.no_graph
+    secs, xk = run_steps(torch, stepper, x0, args.steps, args.warmup, graph)
+    value = args.steps / secs
+    finite = bool(torch.isfinite(torch.view_as_real(xk)).all().item())
+
+    # instrumented pass: durations of the dominant kernel (Legendre analysis of
+    # the fine-level tendencies) measured with events on the launch stream
+    evals_fine = 1 + NITER * NSWEEP * (FINE["nodes"] - 1)
+    evals_coarse = 1 + NITER * (COARSE["nodes"] - 1) * (1 + NSWEEP)
+    per_step_launches = evals_fine + evals_coarse
+    kinds = {}
+    for name, kc in (("legendre_analysis", pk.KC_LEGENDRE_AN), ("legendre_synthesis", pk.KC_LEGENDRE_SYN),
+                     ("grid_fft_products", pk.KC_GRID), ("sdc_node", pk.KC_SDC_NODE)):
+        cap = per_step_launches * 2 + 16
+        a = x0.clone()
+        b = torch.empty_like(a)
+        with pk.KernelTimer(kc, cap) as kt:
+            stepper.step(DT, a, b)
+            torch.cuda.synchronize()
+        kinds[name] = kt.ms
+    # the fine-level launches are the first one and those of the fine sweeps;
+    # separate them by their duration class: the fine kernels process ~8x the data
+    an = np.array(kinds["legendre_analysis"])
+    # order of evaluations in a step: fine spread, coarse node 0, then per iteration
+    # NSWEEP*(Mf) fine, one batched coarse (Mc states), NSWEEP*Mc coarse
+    order = ["f", "c"]
+    for _ in range(NITER):
+        order += ["f"] * (NSWEEP * (FINE["nodes"] - 1)) + ["cB"] + ["c"] * (NSWEEP * (COARSE["nodes"] - 1))
+    fine_idx = [i for i, o in enumerate(order) if o == "f" and i < len(an)]
+    fine_ms = float(np.mean(an[fine_idx]))
+    abytes, table_bytes = legendre_bytes(FINE["N"], FINE["J"], 5, FINE["N"] + 1)
+    achieved = abytes / (fine_ms * 1e-3) / 1e9
+    kernel_totals = {k: float(np.sum(v)) for k, v in kinds.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "two-level MLSDC-SH step: fine T255 on 768x384 Gaussian grid, 5 Gauss-Lobatto nodes; "
+                        "coarse T127 on 384x192, 3 nodes; 2 fine + 2 coarse sweeps per iteration, 4 iterations, "
+                        "dt=300 s; seeded (n+1)^-3 spectra, max wind 40 m/s, |Phi'| 1% of 2.94e4",
+            "fine": "T255 768x384 GL5", "coarse": "T127 384x192 GL3", "niter": NITER,
+            "nsweep_fine": NSWEEP, "nsweep_coarse": NSWEEP, "dt_s": DT, "precision": "fp64",
+            "hip_graph": graph, "parallelism": "single GPU",
+            "evaluations_per_step": {"fine": evals_fine, "coarse": evals_coarse},
+        },
+        "roofline": {
+            "kernel": "k_leg_an (Legendre analysis, fine level, 5 fields)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": fine_ms * 1e3, "algorithmic_bytes_per_launch": abytes,
+            "table_bytes": table_bytes,
+        },
+        "kernel_ms_per_step": kernel_totals,
+        "final_state_finite": finite,
+    }
+    if not args.no_extra:
+        extra = {}
+        # paper's variant: one fine and one coarse sweep per iteration
+        st11 = make_stepper(pk, FINE, COARSE, NITER, 1)
+        s11, _ = run_steps(torch, st11, x0, max(5, args.steps // 2), 2, graph)
+        extra["steps_per_s_T255_T127_sweeps_1_1"] = max(5, args.steps // 2) / s11
+        # T127/T63 configuration
+        x1 = torch.tensor(workload.state(127, 1001), device="cuda")
+        stc1 = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
+        s1, _ = run_steps(torch, stc1, x1, max(5, args.steps), 2, graph)
+        extra["steps_per_s_T127_T63_sweeps_2_2"] = max(5, args.steps) / s1
+        # Legendre GFLOP/s, T255, 15 fields, FP64 (synthesis and analysis)
+        plan = pk.Plan(255, 384, 768)
+        spec = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1), device="cuda")
+        grid = plan.inverse(spec)
+        plan.forward(grid)
+        torch.cuda.synchronize()
+        reps = 20
+        with pk.KernelTimer(pk.KC_LEGENDRE_SYN, reps) as ks:
+            for _ in range(reps):
+                plan.inverse(spec, grid)
+            torch.cuda.synchronize()
+        with pk.KernelTimer(pk.KC_LEGENDRE_AN, reps) as ka:
+            for _ in range(reps):
+                plan.forward(grid, spec)
+            torch.cuda.synchronize()
+        fl = legendre_flops(255, 384, 15, 255)
+        extra["legendre_T255_F15_fp64"] = {
+            "synthesis_gflops": fl / (np.mean(ks.ms) * 1e-3) / 1e9 if ks.ms else None,
+            "analysis_gflops": fl / (np.mean(ka.ms) * 1e-3) / 1e9 if ka.ms else None,
+            "flop_per_direction": fl, "synthesis_us": float(np.mean(ks.ms) * 1e3) if ks.ms else None,
+            "analysis_us": float(np.mean(ka.ms) * 1e3) if ka.ms else None,
+        }
+        out["extra"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(state_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -193,6 +193,27 @@ int mlsdc_step(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts*
                double dt, const double* theta_n_dev, double* theta_np1_dev,
                double* status_dev, void* ws_dev, size_t ws_bytes, shx_stream_t stream);
 
+/* ------------------------------------------------------------ profiling */
+
+/* Kernel classes for the timer below. */
+enum shx_kernel_class {
+    SHX_KC_LEGENDRE_SYN = 0, /* Legendre synthesis (swe_tendency, sh_inverse)   */
+    SHX_KC_LEGENDRE_AN = 1,  /* Legendre analysis (swe_tendency, sh_forward)    */
+    SHX_KC_GRID = 2,         /* FFTs + grid products inside swe_tendency        */
+    SHX_KC_SDC_NODE = 3      /* node update (quadrature + implicit solve)       */
+};
+
+/* Start timing kernel class kclass: the next `capacity` launches of that
+ * class (by any call, on its stream) are bracketed by HIP events recorded on
+ * the launch stream.  Process-global and not thread safe; a new start
+ * discards an unfinished timing.  Host-only bookkeeping plus event creation. */
+int shx_kernel_timer_start(int kclass, int capacity);
+
+/* Stop timing: waits for the recorded events and writes the duration of each
+ * recorded launch in milliseconds to ms[0..count-1] (ms may be NULL to
+ * discard); *count (may be NULL) receives the number recorded. */
+int shx_kernel_timer_stop(float* ms, int* count);
+
 /* Text for a status code. */
 const char* shx_strerror(int status);
 

@@ -49,7 +49,10 @@ _SIGS = {
     "sdc_sweep": (_I, [_P, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "mlsdc_workspace_bytes": (_SZ, [_P, _P, ctypes.POINTER(MlsdcOpts)]),
     "mlsdc_step": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P, _SZ, _P]),
+    "shx_kernel_timer_start": (_I, [_I, _I]),
+    "shx_kernel_timer_stop": (_I, [_P, ctypes.POINTER(_I)]),
 }
+KC_LEGENDRE_SYN, KC_LEGENDRE_AN, KC_GRID, KC_SDC_NODE = 0, 1, 2, 3
 EXPORTS = tuple(_SIGS)
 
 
@@ -96,6 +99,26 @@ def _need(t, dtype, numel, name):
 
 def nspec(N):
     return int(lib().shx_nspec(N))
+
+
+class KernelTimer:
+    """Times every launch of one kernel class with HIP events on its stream."""
+
+    def __init__(self, kclass, capacity):
+        self.kclass, self.capacity = kclass, capacity
+
+    def __enter__(self):
+        _check(lib().shx_kernel_timer_start(self.kclass, self.capacity), "shx_kernel_timer_start")
+        self.ms = []
+        return self
+
+    def __exit__(self, *exc):
+        import numpy as np
+        buf = np.zeros(self.capacity, dtype=np.float32)
+        n = ctypes.c_int(0)
+        _check(lib().shx_kernel_timer_stop(buf.ctypes.data, ctypes.byref(n)), "shx_kernel_timer_stop")
+        self.ms = buf[: n.value].astype(float).tolist()
+        return False
 
 
 class Workspace:

@@ -77,13 +77,32 @@ bool alias_free(const shx_plan* pl) {
     return pl->I >= 3 * pl->N + 1 && 2 * pl->J >= 3 * pl->N + 1;
 }
 
+// Kernel timer (profiling hook): events recorded on the launch stream around
+// each launch of one kernel class.  Process-global, not thread safe.
+struct KernelTimer {
+    int kclass = -1, cap = 0, n = 0;
+    std::vector<hipEvent_t> ev0, ev1;
+} g_timer;
+
+template <class F>
+hipError_t timed(int kclass, hipStream_t st, F launch) {
+    const bool on = g_timer.kclass == kclass && g_timer.n < g_timer.cap;
+    if (on && hipEventRecord(g_timer.ev0[g_timer.n], st) != hipSuccess) return hipErrorUnknown;
+    hipError_t e = launch();
+    if (on && e == hipSuccess) {
+        e = hipEventRecord(g_timer.ev1[g_timer.n], st);
+        ++g_timer.n;
+    }
+    return e;
+}
+
 int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double2* state, double2* fi,
                   double2* fe, const TendWS& t, hipStream_t st) {
     if (fe) {
         HIPCHK(launch_swe_prep(pl, p.a, state, t.cin, nst, st));
-        HIPCHK(launch_leg_syn(pl, t.cin, t.FI, 4, nst, pl->nmax, st));
-        HIPCHK(launch_swe_grid(pl, t.FI, t.G, nst, p.omega, st));
-        HIPCHK(launch_leg_an(pl, t.G, t.cout, 5, nst, pl->nmax, st));
+        HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn(pl, t.cin, t.FI, 4, nst, pl->nmax, st); }));
+        HIPCHK(timed(SHX_KC_GRID, st, [&] { return launch_swe_grid(pl, t.FI, t.G, nst, p.omega, st); }));
+        HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] { return launch_leg_an(pl, t.G, t.cout, 5, nst, pl->nmax, st); }));
     }
     HIPCHK(launch_swe_combine(pl, p, t.cout, state, fi, fe, nst, st));
     return SHX_OK;
@@ -120,7 +139,9 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, double2* fi, double2
             wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
         }
         const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
-        HIPCHK(launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi, fe, w.fi_old, w.fe_old, tau, st));
+        HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
+            return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi, fe, w.fi_old, w.fe_old, tau, st);
+        }));
         const size_t o = (size_t)(m + 1) * ns3;
         int rc = tendency_impl(pl, lv->p, 1, th + o, fi + o, fe + o, w.t, st);
         if (rc) return rc;
@@ -185,6 +206,43 @@ bool valid_params(const swe_params* p) {
 extern "C" {
 
 size_t shx_nspec(int ntrunc) { return ntrunc < 0 ? 0 : (size_t)nspec_of(ntrunc); }
+
+int shx_kernel_timer_start(int kclass, int capacity) {
+    if (kclass < 0 || kclass > SHX_KC_SDC_NODE || capacity < 1) return SHX_EINVAL;
+    shx_kernel_timer_stop(nullptr, nullptr);
+    g_timer.ev0.resize(capacity);
+    g_timer.ev1.resize(capacity);
+    for (int i = 0; i < capacity; ++i) {
+        if (hipEventCreate(&g_timer.ev0[i]) != hipSuccess || hipEventCreate(&g_timer.ev1[i]) != hipSuccess) {
+            g_timer.cap = i;
+            shx_kernel_timer_stop(nullptr, nullptr);
+            return SHX_EHIP;
+        }
+    }
+    g_timer.cap = capacity;
+    g_timer.n = 0;
+    g_timer.kclass = kclass;
+    return SHX_OK;
+}
+
+int shx_kernel_timer_stop(float* ms, int* count) {
+    int rc = SHX_OK;
+    if (count) *count = g_timer.n;
+    for (int i = 0; i < g_timer.n && ms; ++i) {
+        if (hipEventSynchronize(g_timer.ev1[i]) != hipSuccess ||
+            hipEventElapsedTime(&ms[i], g_timer.ev0[i], g_timer.ev1[i]) != hipSuccess)
+            rc = SHX_EHIP;
+    }
+    for (int i = 0; i < g_timer.cap; ++i) {
+        (void)hipEventDestroy(g_timer.ev0[i]);
+        (void)hipEventDestroy(g_timer.ev1[i]);
+    }
+    g_timer.ev0.clear();
+    g_timer.ev1.clear();
+    g_timer.kclass = -1;
+    g_timer.cap = g_timer.n = 0;
+    return rc;
+}
 
 const char* shx_strerror(int s) {
     switch (s) {
@@ -308,7 +366,7 @@ int sh_inverse(const shx_plan* pl, int F, const double* spec, double* grid, void
     double2* FI = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
     hipStream_t st = S(stream);
     HIPCHK(launch_spec_to_ext(pl, reinterpret_cast<const double2*>(spec), cin, F, st));
-    HIPCHK(launch_leg_syn(pl, cin, FI, F, 1, pl->N, st));
+    HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn(pl, cin, FI, F, 1, pl->N, st); }));
     HIPCHK(launch_fft_inv(pl, FI, grid, F, st));
     return SHX_OK;
 }
@@ -322,7 +380,7 @@ int sh_forward(const shx_plan* pl, int F, const double* grid, double* spec, void
     double2* G = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
     hipStream_t st = S(stream);
     HIPCHK(launch_fft_fwd(pl, grid, G, F, st));
-    HIPCHK(launch_leg_an(pl, G, cout, F, 1, pl->N, st));
+    HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] { return launch_leg_an(pl, G, cout, F, 1, pl->N, st); }));
     HIPCHK(launch_ext_to_spec(pl, cout, reinterpret_cast<double2*>(spec), F, st));
     return SHX_OK;
 }

@@ -57,28 +57,35 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
 }
 
 // Synthesis: out[s][p][jp][m][f0+f] = sum_k P[m][p][k][jp] cin[s][ext(m, m+2k+p)][f0+f].
-// grid (ceil(Jh/64), N+1, 2), 64 lanes = latitudes.
+// grid (ceil(Jh/64), N+1, 2), 256 threads: lane = latitude jp, the four
+// wavefronts split the degree sum into quarters; the coefficients are the
+// same for every lane and come through the scalar cache.  Wave 0 adds the
+// partial sums of waves 1..3 (LDS) in a fixed order.
 template <int NF>
-__global__ __launch_bounds__(64) void k_leg_syn(const double* __restrict__ psyn,
-                                                const long long* __restrict__ off,
-                                                const double2* __restrict__ cin,
-                                                double2* __restrict__ out, int N, int nmax_use,
-                                                int Jh, int F, int f0, int S, long long cin_stride,
-                                                long long out_stride) {
-    const int jp = blockIdx.x * 64 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn,
+                                                 const long long* __restrict__ off,
+                                                 const double2* __restrict__ cin,
+                                                 double2* __restrict__ out, int N, int nmax_use,
+                                                 int Jh, int F, int f0, int S, long long cin_stride,
+                                                 long long out_stride) {
+    __shared__ double red[3][2 * NF][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int jp = blockIdx.x * 64 + lane;
     const int m = blockIdx.y, p = blockIdx.z;
-    if (jp >= Jh) return;
+    const bool active = jp < Jh;
     const int K = kcount(nmax_use, m, p);
-    const double* P = psyn + off[2 * m + p] + jp;
+    const int kq = (K + 3) / 4;
+    const int k0 = min(K, wv * kq), k1 = min(K, k0 + kq);
+    const double* P = psyn + off[2 * m + p] + (active ? jp : 0);
     const long long e0 = ext_idx(N, m, m + p);
     for (int s = 0; s < S; ++s) {
         const double2* c = cin + s * cin_stride + e0 * F + f0;
         double ar[NF], ai[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        int k = 0;
+        int k = k0;
         // UNR table loads in flight per lane before the FMAs consume them
-        for (; k + UNR <= K; k += UNR) {
+        for (; k + UNR <= k1; k += UNR) {
             double pv[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(k + u) * Jh];
@@ -92,7 +99,7 @@ __global__ __launch_bounds__(64) void k_leg_syn(const double* __restrict__ psyn,
                 }
             }
         }
-        for (; k < K; ++k) {
+        for (; k < k1; ++k) {
             const double pv = P[(long long)k * Jh];
             const double2* ck = c + (long long)(2 * k) * F;
 #pragma unroll
@@ -101,64 +108,119 @@ __global__ __launch_bounds__(64) void k_leg_syn(const double* __restrict__ psyn,
                 ai[f] = fma(pv, ck[f].y, ai[f]);
             }
         }
-        double2* o = out + s * out_stride + (((long long)p * Jh + jp) * (N + 1) + m) * F + f0;
+        if (s > 0) __syncthreads();                     // wave 0 has read the previous partials
+        if (wv > 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) o[f] = make_double2(ar[f], ai[f]);
+            for (int f = 0; f < NF; ++f) {
+                red[wv - 1][2 * f][lane] = ar[f];
+                red[wv - 1][2 * f + 1][lane] = ai[f];
+            }
+        }
+        __syncthreads();
+        if (wv == 0 && active) {
+            double2* o = out + s * out_stride + (((long long)p * Jh + jp) * (N + 1) + m) * F + f0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                double xr = ar[f], xi = ai[f];
+#pragma unroll
+                for (int w = 0; w < 3; ++w) {
+                    xr += red[w][2 * f][lane];
+                    xi += red[w][2 * f + 1][lane];
+                }
+                o[f] = make_double2(xr, xi);
+            }
+        }
     }
 }
 
 // Analysis: cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
-// grid (ceil(K/64), N+1, 2), 64 lanes = degrees.
+// grid (ceil(K/64), N+1, 2), 256 threads: lane = degree row k, the four
+// wavefronts split the latitude sum into quarters.  The combined Fourier
+// data g_jp = G_north +/- G_south of this (m, p) is staged in LDS once per
+// state (dynamic LDS: Jh * NF double2) and read by broadcast; the partial
+// sums of waves 1..3 are added by wave 0 through LDS.
 template <int NF>
-__global__ __launch_bounds__(64) void k_leg_an(const double* __restrict__ pan,
-                                               const long long* __restrict__ off,
-                                               const double2* __restrict__ G,
-                                               double2* __restrict__ cout, int N, int nmax_tab,
-                                               int nmax_use, int J, int F, int f0, int S,
-                                               long long G_stride, long long cout_stride) {
-    const int k = blockIdx.x * 64 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
+                                                const long long* __restrict__ off,
+                                                const double2* __restrict__ G,
+                                                double2* __restrict__ cout, int N, int nmax_tab,
+                                                int nmax_use, int J, int F, int f0, int S,
+                                                long long G_stride, long long cout_stride) {
+    extern __shared__ double2 gsh[];                    // [Jh][NF]
+    __shared__ double red[3][2 * NF][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + lane;
     const int m = blockIdx.y, p = blockIdx.z;
     const int K = kcount(nmax_use, m, p);
-    if (k >= K) return;
+    if (blockIdx.x * 64 >= K) return;                   // whole block idle (uniform)
+    const bool active = k < K;
     const int Ktab = kcount(nmax_tab, m, p);
     const int Jh = J / 2;
-    const double* P = pan + off[2 * m + p] + k;
+    const int jq = (Jh + 3) / 4;
+    const int j0 = wv * jq, j1 = min(Jh, j0 + jq);
+    const double* P = pan + off[2 * m + p] + (active ? k : 0);
     const double sg = p ? -1.0 : 1.0;
     const long long rowstride = (long long)(N + 1) * F;
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
+        __syncthreads();                                // previous state's readers are done
+        for (int i = threadIdx.x; i < Jh * NF; i += 256) {
+            const int jp = i / NF, f = i - jp * NF;
+            const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+            gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+        }
+        __syncthreads();
         double ar[NF], ai[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        int jp = 0;
-        for (; jp + UNR <= Jh; jp += UNR) {
+        int jp = j0;
+        for (; jp + UNR <= j1; jp += UNR) {
             double pv[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
-                const double2* gn = g + (jp + u) * rowstride;
-                const double2* gs = g + (J - 1 - jp - u) * rowstride;
+                const double2* gg = gsh + (jp + u) * NF;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    ar[f] = fma(pv[u], gn[f].x + sg * gs[f].x, ar[f]);
-                    ai[f] = fma(pv[u], gn[f].y + sg * gs[f].y, ai[f]);
+                    const double2 x = gg[f];
+                    ar[f] = fma(pv[u], x.x, ar[f]);
+                    ai[f] = fma(pv[u], x.y, ai[f]);
                 }
             }
         }
-        for (; jp < Jh; ++jp) {
+        for (; jp < j1; ++jp) {
             const double pv = P[(long long)jp * Ktab];
-            const double2* gn = g + jp * rowstride;
-            const double2* gs = g + (J - 1 - jp) * rowstride;
+            const double2* gg = gsh + jp * NF;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                ar[f] = fma(pv, gn[f].x + sg * gs[f].x, ar[f]);
-                ai[f] = fma(pv, gn[f].y + sg * gs[f].y, ai[f]);
+                const double2 x = gg[f];
+                ar[f] = fma(pv, x.x, ar[f]);
+                ai[f] = fma(pv, x.y, ai[f]);
             }
         }
-        double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+        if (wv > 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) o[f] = make_double2(ar[f], ai[f]);
+            for (int f = 0; f < NF; ++f) {
+                red[wv - 1][2 * f][lane] = ar[f];
+                red[wv - 1][2 * f + 1][lane] = ai[f];
+            }
+        }
+        __syncthreads();
+        if (wv == 0 && active) {
+            double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                // fixed summation order: wave 0, 1, 2, 3
+                double xr = ar[f], xi = ai[f];
+#pragma unroll
+                for (int w = 0; w < 3; ++w) {
+                    xr += red[w][2 * f][lane];
+                    xi += red[w][2 * f + 1][lane];
+                }
+                o[f] = make_double2(xr, xi);
+            }
+        }
     }
 }
 
@@ -166,7 +228,7 @@ template <int NF>
 void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S,
                int nmax_use, hipStream_t st) {
     dim3 grid((pl->Jh + 63) / 64, pl->N + 1, 2);
-    k_leg_syn<NF><<<grid, 64, 0, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F, f0, S,
+    k_leg_syn<NF><<<grid, 256, 0, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F, f0, S,
                                        pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F);
 }
 
@@ -175,7 +237,8 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
               hipStream_t st) {
     const int kmax = kcount(nmax_use, 0, 0);
     dim3 grid((kmax + 63) / 64, pl->N + 1, 2);
-    k_leg_an<NF><<<grid, 64, 0, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use, pl->J, F,
+    const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
+    k_leg_an<NF><<<grid, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use, pl->J, F,
                                       f0, S, (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F);
 }
 
