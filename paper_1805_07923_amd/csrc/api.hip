@@ -108,8 +108,35 @@ int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double
     return SHX_OK;
 }
 
-// Sweep workspace: F_I and F_E of the previous iterate at all nodes, and
-// the tendency workspace for one state.
+// One IMEX SDC sweep reading F_I, F_E of the previous iterate at every node
+// from (fi_old, fe_old) and writing the new F at nodes 1..M to (fi_new,
+// fe_new); Theta is updated in place (node 0 read only).  Node 0 of the new
+// buffers is not touched.
+int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_old, const double2* fe_old,
+               double2* fi_new, double2* fe_new, const double2* tau, const TendWS& t, hipStream_t st) {
+    const shx_plan* pl = lv->plan;
+    const int M = lv->nnodes - 1, n1 = lv->nnodes;
+    const size_t ns3 = 3 * (size_t)pl->nspec;
+    for (int m = 0; m < M; ++m) {
+        NodeWeights wt;
+        for (int j = 0; j < 9; ++j) {
+            const bool in = j < n1;
+            wt.q[j] = in ? dt * lv->Q[(m + 1) * n1 + j] : 0.0;
+            wt.qe[j] = in ? dt * lv->QE[(m + 1) * n1 + j] : 0.0;
+            wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
+        }
+        const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
+        HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
+            return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi_new, fe_new, fi_old, fe_old, tau, st);
+        }));
+        const size_t o = (size_t)(m + 1) * ns3;
+        int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st);
+        if (rc) return rc;
+    }
+    return SHX_OK;
+}
+
+// Workspace of the in-place sdc_sweep entry point: a copy of the caller's F.
 struct SweepWS {
     double2 *fi_old, *fe_old;
     TendWS t;
@@ -123,32 +150,6 @@ SweepWS carve_sweep(Carve& c, const sdc_level* lv) {
     return w;
 }
 
-int sweep_impl(const sdc_level* lv, double dt, double2* th, double2* fi, double2* fe, const double2* tau,
-               const SweepWS& w, hipStream_t st) {
-    const shx_plan* pl = lv->plan;
-    const int M = lv->nnodes - 1, n1 = lv->nnodes;
-    const size_t ns3 = 3 * (size_t)pl->nspec;
-    HIPCHK(hipMemcpyAsync(w.fi_old, fi, n1 * ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(w.fe_old, fe, n1 * ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    for (int m = 0; m < M; ++m) {
-        NodeWeights wt;
-        for (int j = 0; j < 9; ++j) {
-            const bool in = j < n1;
-            wt.q[j] = in ? dt * lv->Q[(m + 1) * n1 + j] : 0.0;
-            wt.qe[j] = in ? dt * lv->QE[(m + 1) * n1 + j] : 0.0;
-            wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
-        }
-        const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
-        HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
-            return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi, fe, w.fi_old, w.fe_old, tau, st);
-        }));
-        const size_t o = (size_t)(m + 1) * ns3;
-        int rc = tendency_impl(pl, lv->p, 1, th + o, fi + o, fe + o, w.t, st);
-        if (rc) return rc;
-    }
-    return SHX_OK;
-}
-
 Mat9x9 to_mat(const double* a, int n) {
     Mat9x9 r;
     std::memset(&r, 0, sizeof(r));
@@ -156,34 +157,39 @@ Mat9x9 to_mat(const double* a, int n) {
     return r;
 }
 
-// MLSDC workspace.
+// MLSDC workspace.  Fine F in two buffers used alternately by the sweeps
+// (old -> new); coarse F: the values at the restricted states (saved for the
+// FAS term and step D) and two sweep buffers.
 struct StepWS {
-    double2 *thf, *fif, *fef;                          // fine [Mf+1][3][nsf]
-    double2 *thc, *fic, *fec, *thct, *fict, *fect, *tau;  // coarse [Mc+1][3][nsc]
-    double2 *rfi, *rfe;                                // residual re-evaluation [Mf+1][3][nsf]
+    double2 *thf, *fif[2], *fef[2];                     // fine [Mf+1][3][nsf]
+    double2 *thc, *thct, *fict, *fect, *fic[2], *fec[2], *tau;  // coarse [Mc+1][3][nsc]
+    double2 *rfi, *rfe;                                 // residual re-evaluation [Mf+1][3][nsf]
     double* partial;
-    SweepWS swf, swc;
-    TendWS tc;                                         // coarse, Mc states
-    TendWS tr;                                         // fine, Mf+1 states (residual)
+    TendWS tf;                                          // fine, 1 state
+    TendWS tc;                                          // coarse, Mc states
+    TendWS tr;                                          // fine, Mf+1 states (residual)
 };
 StepWS carve_step(Carve& c, const sdc_level* f, const sdc_level* cl, const mlsdc_opts* o) {
     StepWS w{};
     const size_t nf = (size_t)f->nnodes * 3 * f->plan->nspec;
     w.thf = c.take<double2>(nf);
-    w.fif = c.take<double2>(nf);
-    w.fef = c.take<double2>(nf);
-    w.swf = carve_sweep(c, f);
+    for (int b = 0; b < 2; ++b) {
+        w.fif[b] = c.take<double2>(nf);
+        w.fef[b] = c.take<double2>(nf);
+    }
+    w.tf = carve_tend(c, f->plan, 1);
     if (cl) {
         const size_t nc = (size_t)cl->nnodes * 3 * cl->plan->nspec;
         w.thc = c.take<double2>(nc);
-        w.fic = c.take<double2>(nc);
-        w.fec = c.take<double2>(nc);
         w.thct = c.take<double2>(nc);
         w.fict = c.take<double2>(nc);
         w.fect = c.take<double2>(nc);
+        for (int b = 0; b < 2; ++b) {
+            w.fic[b] = c.take<double2>(nc);
+            w.fec[b] = c.take<double2>(nc);
+        }
         w.tau = c.take<double2>(nc);
-        w.swc = carve_sweep(c, cl);
-        w.tc = carve_tend(c, cl->plan, cl->nnodes - 1);
+        w.tc = carve_tend(c, cl->plan, cl->nnodes - 1 > 1 ? cl->nnodes - 1 : 1);
     }
     if (o && o->residual_check) {
         w.rfi = c.take<double2>(nf);
@@ -467,8 +473,12 @@ int sdc_sweep(const sdc_level* lv, double dt, double* th, double* fi, double* fe
     if (!ws || wsb < sdc_sweep_workspace_bytes(lv)) return SHX_EWORKSPACE;
     Carve c{static_cast<char*>(ws)};
     SweepWS w = carve_sweep(c, lv);
-    return sweep_impl(lv, dt, reinterpret_cast<double2*>(th), reinterpret_cast<double2*>(fi),
-                      reinterpret_cast<double2*>(fe), reinterpret_cast<const double2*>(tau), w, S(stream));
+    hipStream_t st = S(stream);
+    const size_t nb = (size_t)lv->nnodes * 3 * lv->plan->nspec * sizeof(double2);
+    HIPCHK(hipMemcpyAsync(w.fi_old, fi, nb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.fe_old, fe, nb, hipMemcpyDeviceToDevice, st));
+    return sweep_impl(lv, dt, reinterpret_cast<double2*>(th), w.fi_old, w.fe_old, reinterpret_cast<double2*>(fi),
+                      reinterpret_cast<double2*>(fe), reinterpret_cast<const double2*>(tau), w.t, st);
 }
 
 size_t mlsdc_workspace_bytes(const sdc_level* f, const sdc_level* c, const mlsdc_opts* o) {
@@ -497,13 +507,18 @@ int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, do
     const double2* th_n = reinterpret_cast<const double2*>(theta_n);
     // spread: Theta and F at every fine node equal those of Theta^n
     HIPCHK(hipMemcpyAsync(w.thf, th_n, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    int rc = tendency_impl(pf, fl->p, 1, w.thf, w.fif, w.fef, w.swf.t, st);
+    int rc = tendency_impl(pf, fl->p, 1, w.thf, w.fif[0], w.fef[0], w.tf, st);
     if (rc) return rc;
-    for (int m = 1; m <= Mf; ++m) {
-        HIPCHK(hipMemcpyAsync(w.thf + m * nsf3, w.thf, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(w.fif + m * nsf3, w.fif, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(w.fef + m * nsf3, w.fef, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    {
+        NodeCopies nc{};
+        nc.add(w.thf, w.thf, 1, Mf);
+        nc.add(w.fif[0], w.fif[0], 1, Mf);
+        nc.add(w.fef[0], w.fef[0], 1, Mf);
+        nc.add(w.fif[0], w.fif[1], 0, 0);
+        nc.add(w.fef[0], w.fef[1], 0, 0);
+        HIPCHK(launch_node_copies(nc, (long long)nsf3, st));
     }
+    int fcur = 0;                                        // fine F buffer holding the current iterate
     Mat9x9 Pcf{}, Pfc{}, PQ{}, Qc{};
     int Mc = 0;
     size_t nsc3 = 0;
@@ -519,42 +534,50 @@ int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, do
         // Pi^c_f Q_f  [nc][nf]
         for (int i = 0; i < cl->nnodes; ++i)
             for (int j = 0; j < fl->nnodes; ++j) {
-                double s = 0.0;
-                for (int k = 0; k < fl->nnodes; ++k) s += a[i * fl->nnodes + k] * fl->Q[k * fl->nnodes + j];
-                PQ.a[i * fl->nnodes + j] = s;
+                double sum = 0.0;
+                for (int k = 0; k < fl->nnodes; ++k) sum += a[i * fl->nnodes + k] * fl->Q[k * fl->nnodes + j];
+                PQ.a[i * fl->nnodes + j] = sum;
             }
         Qc = to_mat(cl->Q, cl->nnodes * cl->nnodes);
         // coarse node 0: restricted initial value and its F, once per step
         Mat9x9 e0{};
         e0.a[0] = 1.0;
-        HIPCHK(launch_restrict(pf, pc, e0, 1, 0, 1, th_n, w.thc, st));
-        rc = tendency_impl(pc, cl->p, 1, w.thc, w.fic, w.fec, w.swc.t, st);
+        HIPCHK(launch_restrict(pf, pc, e0, 1, 0, 1, th_n, w.thc, w.thct, st));
+        rc = tendency_impl(pc, cl->p, 1, w.thct, w.fict, w.fect, w.tc, st);
         if (rc) return rc;
+        NodeCopies nc{};
+        for (int b2 = 0; b2 < 2; ++b2) {
+            nc.add(w.fict, w.fic[b2], 0, 0);
+            nc.add(w.fect, w.fec[b2], 0, 0);
+        }
+        HIPCHK(launch_node_copies(nc, (long long)nsc3, st));
     }
     for (int k = 0; k < o->niter; ++k) {
-        // A) fine sweep(s)
-        for (int s = 0; s < o->nsweep_fine; ++s) {
-            rc = sweep_impl(fl, dt, w.thf, w.fif, w.fef, nullptr, w.swf, st);
+        // A) fine sweep(s), old -> new buffers
+        for (int s2 = 0; s2 < o->nsweep_fine; ++s2) {
+            rc = sweep_impl(fl, dt, w.thf, w.fif[fcur], w.fef[fcur], w.fif[1 - fcur], w.fef[1 - fcur], nullptr,
+                            w.tf, st);
             if (rc) return rc;
+            fcur = 1 - fcur;
         }
         if (!cl) continue;
-        // B) restrict nodes 1..Mc, evaluate, save the restriction
-        HIPCHK(launch_restrict(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.thf, w.thc, st));
-        rc = tendency_impl(pc, cl->p, Mc, w.thc + nsc3, w.fic + nsc3, w.fec + nsc3, w.tc, st);
+        // B) restrict nodes 1..Mc (kept twice: iterate and saved copy), evaluate
+        HIPCHK(launch_restrict(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.thf, w.thc, w.thct, st));
+        rc = tendency_impl(pc, cl->p, Mc, w.thct + nsc3, w.fict + nsc3, w.fect + nsc3, w.tc, st);
         if (rc) return rc;
-        const size_t cb = cl->nnodes * nsc3 * sizeof(double2);
-        HIPCHK(hipMemcpyAsync(w.thct, w.thc, cb, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(w.fict, w.fic, cb, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(w.fect, w.fec, cb, hipMemcpyDeviceToDevice, st));
-        // C) FAS correction and coarse sweep(s)
-        HIPCHK(launch_fas_tau(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.fif, w.fef, w.fic, w.fec, w.tau, st));
-        for (int s = 0; s < o->nsweep_coarse; ++s) {
-            rc = sweep_impl(cl, dt, w.thc, w.fic, w.fec, w.tau, w.swc, st);
+        // C) FAS correction and coarse sweep(s): the first reads the saved F
+        HIPCHK(launch_fas_tau(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.fif[fcur], w.fef[fcur], w.fict, w.fect,
+                              w.tau, st));
+        const double2 *ci = w.fict, *ce = w.fect;
+        for (int s2 = 0; s2 < o->nsweep_coarse; ++s2) {
+            rc = sweep_impl(cl, dt, w.thc, ci, ce, w.fic[s2 & 1], w.fec[s2 & 1], w.tau, w.tc, st);
             if (rc) return rc;
+            ci = w.fic[s2 & 1];
+            ce = w.fec[s2 & 1];
         }
         // D) interpolate the coarse corrections of Theta, F_I, F_E
-        HIPCHK(launch_interp(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.thc, w.thct, w.fic, w.fict, w.fec, w.fect,
-                             w.thf, w.fif, w.fef, st));
+        HIPCHK(launch_interp(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.thc, w.thct, ci, w.fict, ce, w.fect, w.thf,
+                             w.fif[fcur], w.fef[fcur], st));
     }
     double2* out = reinterpret_cast<double2*>(theta_np1);
     HIPCHK(hipMemcpyAsync(out, w.thf + Mf * nsf3, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));

@@ -120,7 +120,7 @@ __device__ __forceinline__ void fft_stages(double2* buf, const double2* __restri
 template <int L>
 struct FftCfg {
     static constexpr int L2 = L / 2;
-    static constexpr int T0 = L2 / 4 < 64 ? 64 : (L2 / 4 > 1024 ? 1024 : L2 / 4);
+    static constexpr int T0 = L2 / 2 < 64 ? 64 : (L2 / 2 > 1024 ? 1024 : L2 / 2);
     static constexpr int T = (T0 + 63) / 64 * 64;
 };
 

@@ -101,7 +101,22 @@ hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M
                            const double2* fe, const double2* fi_old, const double2* fe_old,
                            const double2* tau, hipStream_t st);
 hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc,
-                           int i0, int i1, const double2* src, double2* dst, hipStream_t st);
+                           int i0, int i1, const double2* src, double2* dst, double2* dst2, hipStream_t st);
+// Copies of node 0 of up to 6 node arrays to node ranges of (other) node arrays.
+struct NodeCopies {
+    const double2* src[6];
+    double2* dst[6];
+    int first[6], last[6];
+    int n = 0;
+    void add(const double2* s, double2* d, int f, int l) {
+        src[n] = s;
+        dst[n] = d;
+        first[n] = f;
+        last[n] = l;
+        ++n;
+    }
+};
+hipError_t launch_node_copies(const NodeCopies& nc, long long n3, hipStream_t st);
 hipError_t launch_fas_tau(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ,
                           const Mat9x9& Qc, int nf, int nc, double dt, const double2* fi_f,
                           const double2* fe_f, const double2* fi_c, const double2* fe_c,

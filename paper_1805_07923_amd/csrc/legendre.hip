@@ -58,9 +58,10 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
 
 // Synthesis: out[s][p][jp][m][f0+f] = sum_k P[m][p][k][jp] cin[s][ext(m, m+2k+p)][f0+f].
 // grid (ceil(Jh/64), N+1, 2), 256 threads: lane = latitude jp, the four
-// wavefronts split the degree sum into quarters; the coefficients are the
-// same for every lane and come through the scalar cache.  Wave 0 adds the
-// partial sums of waves 1..3 (LDS) in a fixed order.
+// wavefronts split the degree sum into quarters.  The coefficients of this
+// (m, p) are the same for every lane: they are staged in LDS (dynamic LDS:
+// K * NF double2) and read by broadcast.  Wave 0 adds the partial sums of
+// waves 1..3 (LDS) in a fixed order.
 template <int NF>
 __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn,
                                                  const long long* __restrict__ off,
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
                                                  double2* __restrict__ out, int N, int nmax_use,
                                                  int Jh, int F, int f0, int S, long long cin_stride,
                                                  long long out_stride) {
+    extern __shared__ double2 csh[];                    // [K][NF]
     __shared__ double red[3][2 * NF][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int jp = blockIdx.x * 64 + lane;
@@ -79,7 +81,14 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
     const double* P = psyn + off[2 * m + p] + (active ? jp : 0);
     const long long e0 = ext_idx(N, m, m + p);
     for (int s = 0; s < S; ++s) {
-        const double2* c = cin + s * cin_stride + e0 * F + f0;
+        const double2* cg = cin + s * cin_stride + e0 * F + f0;
+        if (s > 0) __syncthreads();                     // previous state's readers are done
+        for (int i = threadIdx.x; i < K * NF; i += 256) {
+            const int kk = i / NF, f = i - kk * NF;
+            csh[i] = cg[(long long)(2 * kk) * F + f];
+        }
+        __syncthreads();
+        const double2* c = csh;
         double ar[NF], ai[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
@@ -91,7 +100,7 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
             for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(k + u) * Jh];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
-                const double2* ck = c + (long long)(2 * (k + u)) * F;
+                const double2* ck = c + (k + u) * NF;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     ar[f] = fma(pv[u], ck[f].x, ar[f]);
@@ -101,14 +110,13 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
         }
         for (; k < k1; ++k) {
             const double pv = P[(long long)k * Jh];
-            const double2* ck = c + (long long)(2 * k) * F;
+            const double2* ck = c + k * NF;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 ar[f] = fma(pv, ck[f].x, ar[f]);
                 ai[f] = fma(pv, ck[f].y, ai[f]);
             }
         }
-        if (s > 0) __syncthreads();                     // wave 0 has read the previous partials
         if (wv > 0) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -228,7 +236,8 @@ template <int NF>
 void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S,
                int nmax_use, hipStream_t st) {
     dim3 grid((pl->Jh + 63) / 64, pl->N + 1, 2);
-    k_leg_syn<NF><<<grid, 256, 0, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F, f0, S,
+    const size_t lds = (size_t)kcount(nmax_use, 0, 0) * NF * sizeof(double2);
+    k_leg_syn<NF><<<grid, 256, lds, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F, f0, S,
                                        pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F);
 }
 

@@ -214,7 +214,8 @@ __global__ void k_sdc_node(const int* __restrict__ deg, long long nspec, swe_par
 // coarse coefficients, map(c) is the fine index of the same (m, n).
 __global__ void k_restrict(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
                            long long nsf, long long nsc, Mat9x9 Pi, int nsrc, int i0, int i1,
-                           const double2* __restrict__ src, double2* __restrict__ dst) {
+                           const double2* __restrict__ src, double2* __restrict__ dst,
+                           double2* __restrict__ dst2) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
     if (c >= nsc) return;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
@@ -226,7 +227,18 @@ __global__ void k_restrict(const int* __restrict__ ordc, const int* __restrict__
                 if (w != 0.0) acc = caxpy(w, src[(j * 3 + f) * nsf + fidx], acc);
             }
             dst[(i * 3 + f) * nsc + c] = acc;
+            if (dst2) dst2[(i * 3 + f) * nsc + c] = acc;
         }
+    }
+}
+
+// dst_p[m] = src_p[0] for nodes m = first_p..last_p (element-wise over n3).
+__global__ void k_node_copies(NodeCopies nc, long long n3) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e >= n3) return;
+    for (int q = 0; q < nc.n; ++q) {
+        const double2 v = nc.src[q][e];
+        for (int m = nc.first[q]; m <= nc.last[q]; ++m) nc.dst[q][m * n3 + e] = v;
     }
 }
 
@@ -413,9 +425,14 @@ hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M
 }
 
 hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc, int i0,
-                           int i1, const double2* src, double2* dst, hipStream_t st) {
+                           int i1, const double2* src, double2* dst, double2* dst2, hipStream_t st) {
     k_restrict<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
-                                                       coarse->nspec, Pi, nsrc, i0, i1, src, dst);
+                                                       coarse->nspec, Pi, nsrc, i0, i1, src, dst, dst2);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_copies(const NodeCopies& nc, long long n3, hipStream_t st) {
+    k_node_copies<<<nblocks(n3), TB, 0, st>>>(nc, n3);
     return hipGetLastError();
 }
 
