@@ -68,10 +68,16 @@ __device__ __forceinline__ void dft<3>(double2* v, double sg) {
 
 // Stockham stages for NR complex rows of length L held in LDS (row stride L),
 // T threads; Ns is the length of the sub-transforms already done.
-// The twiddle table has length L * TWM (it is shared with the real-row
-// unpacking), so the factor e^{-2 pi i t / L} sits at index t * TWM.
+// Twiddles come from an LDS half table tws[t] = e^{-2 pi i t / (L TWM)},
+// t < L TWM / 2 (the other half is its negative), shared with the real-row
+// packing; the factor e^{-2 pi i t / L} sits at index t * TWM.
+__device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half) {
+    const double2 w = tws[idx < half ? idx : idx - half];
+    return idx < half ? w : make_double2(-w.x, -w.y);
+}
+
 template <int L, int T, int NR, int Ns, int TWM>
-__device__ __forceinline__ void fft_stages(double2* buf, const double2* __restrict__ tw, double sg) {
+__device__ __forceinline__ void fft_stages(double2* buf, const double2* tw, double sg) {
     constexpr int rem = L / Ns;
     if constexpr (rem > 1) {
         constexpr int R = (rem % 4 == 0) ? 4 : ((rem % 2 == 0) ? 2 : 3);
@@ -90,7 +96,7 @@ __device__ __forceinline__ void fft_stages(double2* buf, const double2* __restri
                 for (int r = 0; r < R; ++r) {
                     double2 x = b[j + r * NB];
                     if (Ns > 1 && r > 0) {
-                        double2 w = tw[r * k * TWS];
+                        double2 w = tw_half(tw, r * k * TWS, L * TWM / 2);
                         w.y *= -sg;
                         x = cmul(x, w);
                     }
@@ -127,8 +133,14 @@ struct FftCfg {
 // Build Z (length L/2) for the synthesis of one real row from its Fourier
 // coefficients X_m, m = 0..N (X_m = 0 above N; Im X_0 ignored).  `coef(m)`
 // returns X_m.  Caller syncs before the FFT.
+// LDS copy of tw[0..L/2) (e^{-2 pi i t / L}); caller syncs.
+template <int L>
+__device__ __forceinline__ void load_twiddles(double2* tws, const double2* __restrict__ tw) {
+    for (int t = threadIdx.x; t < L / 2; t += FftCfg<L>::T) tws[t] = tw[t];
+}
+
 template <int L, class Coef>
-__device__ __forceinline__ void pack_synthesis(double2* row, const double2* __restrict__ tw, int N, Coef coef) {
+__device__ __forceinline__ void pack_synthesis(double2* row, const double2* tw, int N, Coef coef) {
     constexpr int L2 = L / 2, T = FftCfg<L>::T;
     for (int m = threadIdx.x; m < L2; m += T) {
         double2 A = make_double2(0.0, 0.0), B = A;
@@ -150,7 +162,7 @@ __device__ __forceinline__ void pack_synthesis(double2* row, const double2* __re
 
 // X_m (m <= N) of the real row whose half-length FFT is in `row`.
 template <int L>
-__device__ __forceinline__ double2 unpack_analysis(const double2* row, const double2* __restrict__ tw, int m) {
+__device__ __forceinline__ double2 unpack_analysis(const double2* row, const double2* tw, int m) {
     constexpr int L2 = L / 2;
     const double2 z = row[m];
     const double2 zc = row[(L2 - m) % L2];
@@ -169,6 +181,9 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_inv(const double2* __restr
                                                           int F) {
     constexpr int L2 = L / 2, T = FftCfg<L>::T;
     __shared__ double2 row[L2];
+    __shared__ double2 tws[L2];
+    load_twiddles<L>(tws, tw);
+    __syncthreads();
     const int j = blockIdx.x, f = blockIdx.y;
     const int Jh = J / 2;
     const int jp = (j < Jh) ? j : J - 1 - j;
@@ -179,9 +194,9 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_inv(const double2* __restr
         const double2 a = e[(long long)m * F], b = e[(long long)m * F + pstride];
         return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
     };
-    pack_synthesis<L>(row, tw, N, coef);
+    pack_synthesis<L>(row, tws, N, coef);
     __syncthreads();
-    fft_stages<L2, T, 1, 1, 2>(row, tw, 1.0);
+    fft_stages<L2, T, 1, 1, 2>(row, tws, 1.0);
     double2* g = reinterpret_cast<double2*>(grid + ((long long)f * J + j) * L);
     for (int k = threadIdx.x; k < L2; k += T) g[k] = row[k];
 }
@@ -195,15 +210,17 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_fwd(const double* __restri
                                                           int F) {
     constexpr int L2 = L / 2, T = FftCfg<L>::T;
     __shared__ double2 row[L2];
+    __shared__ double2 tws[L2];
+    load_twiddles<L>(tws, tw);
     const int j = blockIdx.x, f = blockIdx.y;
     const double2* g = reinterpret_cast<const double2*>(grid + ((long long)f * J + j) * L);
     for (int k = threadIdx.x; k < L2; k += T) row[k] = g[k];
     __syncthreads();
-    fft_stages<L2, T, 1, 1, 2>(row, tw, -1.0);
+    fft_stages<L2, T, 1, 1, 2>(row, tws, -1.0);
     const double sc = w[j] / L;
     double2* out = G + (long long)j * (N + 1) * F + f;
     for (int m = threadIdx.x; m <= N; m += T) {
-        const double2 X = unpack_analysis<L>(row, tw, m);
+        const double2 X = unpack_analysis<L>(row, tws, m);
         out[(long long)m * F] = make_double2(sc * X.x, sc * X.y);
     }
 }
@@ -221,6 +238,9 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_swe_grid(const double2* __rest
                                                            double two_omega) {
     constexpr int L2 = L / 2, T = FftCfg<L>::T;
     __shared__ double2 lds[5 * L2];
+    __shared__ double2 tws[L2];
+    load_twiddles<L>(tws, tw);
+    __syncthreads();
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
     const int jp = (j < Jh) ? j : J - 1 - j;
@@ -233,10 +253,10 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_swe_grid(const double2* __rest
             const double2 a = e[(long long)m * 4 + f], b = e[(long long)m * 4 + f + pstride];
             return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
         };
-        pack_synthesis<L>(lds + f * L2, tw, N, coef);
+        pack_synthesis<L>(lds + f * L2, tws, N, coef);
     }
     __syncthreads();
-    fft_stages<L2, T, 4, 1, 2>(lds, tw, 1.0);
+    fft_stages<L2, T, 4, 1, 2>(lds, tws, 1.0);
     const double fc = two_omega * mu[j];
     const double hk = 0.5 / cos2[j];
     for (int k = threadIdx.x; k < L2; k += T) {
@@ -250,7 +270,7 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_swe_grid(const double2* __rest
         lds[4 * L2 + k] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
     }
     __syncthreads();
-    fft_stages<L2, T, 5, 1, 2>(lds, tw, -1.0);
+    fft_stages<L2, T, 5, 1, 2>(lds, tws, -1.0);
     const double sv = w[j] / (L * cos2[j]);
     const double se = w[j] / L;
     double2* out = G + ((long long)s * J + j) * (N + 1) * 5;
@@ -258,7 +278,7 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_swe_grid(const double2* __rest
         double2* o = out + (long long)m * 5;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            const double2 X = unpack_analysis<L>(lds + f * L2, tw, m);
+            const double2 X = unpack_analysis<L>(lds + f * L2, tws, m);
             const double sc = (f < 4) ? sv : se;
             o[f] = make_double2(sc * X.x, sc * X.y);
         }
