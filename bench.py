@@ -60,6 +60,22 @@ def legendre_flops(N, J, F, nmax):
     return 4.0 * rows * Jh * F
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record, or None when the kernel source changed since it was taken."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "k_leg_an_T255_traffic.json")
+    try:
+        with open(rec) as f:
+            d = json.load(f)
+        with open(os.path.join(ROOT, d["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != d["source_sha256"]:
+                return None
+        return d["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def make_stepper(pk, fine, coarse, niter, nsweep, residual=False):
     par = pk.swe_params()
     pf = pk.Plan(fine["N"], fine["J"], fine["I"])
@@ -133,6 +149,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB once (a plain copy kernel of "
+                         "known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "
@@ -155,34 +174,40 @@ def main():
     value = args.steps / secs
     finite = bool(torch.isfinite(torch.view_as_real(xk)).all().item())
 
-    # instrumented pass: durations of the dominant kernel (Legendre analysis of
-    # the fine-level tendencies) measured with events on the launch stream
+    # kernel time per step by class (HIP events around each launch of one
+    # class, on the launch stream; includes a few us of event overhead each)
     evals_fine = 1 + NITER * NSWEEP * (FINE["nodes"] - 1)
     evals_coarse = 1 + NITER * (COARSE["nodes"] - 1) * (1 + NSWEEP)
-    per_step_launches = evals_fine + evals_coarse
     kinds = {}
     for name, kc in (("legendre_analysis", pk.KC_LEGENDRE_AN), ("legendre_synthesis", pk.KC_LEGENDRE_SYN),
                      ("grid_fft_products", pk.KC_GRID), ("sdc_node", pk.KC_SDC_NODE)):
-        cap = per_step_launches * 2 + 16
         a = x0.clone()
         b = torch.empty_like(a)
-        with pk.KernelTimer(kc, cap) as kt:
+        with pk.KernelTimer(kc, 2 * (evals_fine + evals_coarse) + 16) as kt:
             stepper.step(DT, a, b)
             torch.cuda.synchronize()
-        kinds[name] = kt.ms
-    # the fine-level launches are the first one and those of the fine sweeps;
-    # separate them by their duration class: the fine kernels process ~8x the data
-    an = np.array(kinds["legendre_analysis"])
-    # order of evaluations in a step: fine spread, coarse node 0, then per iteration
-    # NSWEEP*(Mf) fine, one batched coarse (Mc states), NSWEEP*Mc coarse
-    order = ["f", "c"]
-    for _ in range(NITER):
-        order += ["f"] * (NSWEEP * (FINE["nodes"] - 1)) + ["cB"] + ["c"] * (NSWEEP * (COARSE["nodes"] - 1))
-    fine_idx = [i for i, o in enumerate(order) if o == "f" and i < len(an)]
-    fine_ms = float(np.mean(an[fine_idx]))
+        kinds[name] = float(np.sum(kt.ms))
+
+    # dominant kernel: the Legendre analysis of a fine-level tendency (5
+    # fields, degrees <= N+1), timed over back-to-back launches of the same
+    # kernel in the same launch configuration on the same stream
+    pf = stepper.fine.plan
+    NF = FINE["N"]
+    ne = (NF + 1) * (NF + 4) // 2
+    g_in = torch.randn(FINE["J"] * (NF + 1) * 5, dtype=torch.complex128, device="cuda")
+    s_out = torch.empty(ne * 5, dtype=torch.complex128, device="cuda")
+    for _ in range(5):
+        pk.legendre_analysis(pf, 5, NF + 1, g_in, s_out)
+    reps = 200
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pk.legendre_analysis(pf, 5, NF + 1, g_in, s_out)
+    e1.record()
+    torch.cuda.synchronize()
+    an_us = e0.elapsed_time(e1) * 1e3 / reps
     abytes, table_bytes = legendre_bytes(FINE["N"], FINE["J"], 5, FINE["N"] + 1)
-    achieved = abytes / (fine_ms * 1e-3) / 1e9
-    kernel_totals = {k: float(np.sum(v)) for k, v in kinds.items()}
+    achieved = abytes / (an_us * 1e-6) / 1e9
 
     out = {
         "metric": METRIC,
@@ -209,11 +234,11 @@ def main():
         "roofline": {
             "kernel": "k_leg_an (Legendre analysis, fine level, 5 fields)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_us": fine_ms * 1e3, "algorithmic_bytes_per_launch": abytes,
-            "table_bytes": table_bytes,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+            "avg_launch_us": an_us, "algorithmic_bytes_per_launch": abytes,
+            "table_bytes": table_bytes, "timed_launches": reps,
         },
-        "kernel_ms_per_step": kernel_totals,
+        "kernel_ms_per_step": kinds,
         "final_state_finite": finite,
     }
     if not args.no_extra:
@@ -250,6 +275,14 @@ def main():
             "analysis_us": float(np.mean(ka.ms) * 1e3) if ka.ms else None,
         }
         out["extra"] = extra
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": n * 8, "bytes_written": n * 8}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(state_np)
     print(json.dumps(out), flush=True)

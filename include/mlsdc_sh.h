@@ -124,6 +124,24 @@ int sh_inverse(const shx_plan* plan, int nfield, const double* spec_dev, double*
 int sh_forward(const shx_plan* plan, int nfield, const double* grid_dev, double* spec_dev,
                void* ws_dev, size_t ws_bytes, shx_stream_t stream);
 
+/* The Legendre step alone, on the library's Fourier-space layouts (used by
+ * swe_tendency; exposed for callers that do their own longitude transform and
+ * for timing).  nmax = ntrunc or ntrunc + 1 is the highest degree.
+ *   The spectral side is field-interleaved in the extended layout: [nspec_ext][nfield] complex with
+ *     nspec_ext = (N+1)(N+4)/2, m-major, n = m..N+1 (entries n > nmax ignored
+ *     on input, not written on output).
+ *   Synthesis (eq. spectral_to_physical_space, the sum over n):
+ *     fourier_out [2][nlat/2][N+1][nfield] complex: even (p = 0) and odd
+ *     (p = 1) degree sums E, O at the northern latitudes; xi_m(mu_j) = E + O
+ *     in the north and E - O at the mirrored southern latitude.
+ *   Analysis (eq. legendre_transform): fourier_in [nlat][N+1][nfield] complex
+ *     holding w_j xi_m(mu_j) (weights already applied), all latitudes.
+ * Arrays are device memory, 16-byte aligned; nothing else is needed. */
+int sh_legendre_synthesis(const shx_plan* plan, int nfield, int nmax, const double* spec_ext_dev,
+                          double* fourier_out_dev, shx_stream_t stream);
+int sh_legendre_analysis(const shx_plan* plan, int nfield, int nmax, const double* fourier_in_dev,
+                         double* spec_ext_dev, shx_stream_t stream);
+
 /* ------------------------------------------------ SWE right-hand sides */
 
 /* Device workspace bytes for swe_tendency on nstate states. */

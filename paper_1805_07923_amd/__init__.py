@@ -39,6 +39,8 @@ _SIGS = {
     "shx_workspace_bytes": (_SZ, [_P, _I]),
     "sh_inverse": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
     "sh_forward": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
+    "sh_legendre_synthesis": (_I, [_P, _I, _I, _P, _P, _P]),
+    "sh_legendre_analysis": (_I, [_P, _I, _I, _P, _P, _P]),
     "swe_workspace_bytes": (_SZ, [_P, _I]),
     "swe_tendency": (_I, [_P, ctypes.POINTER(SwePar), _I, _P, _P, _P, _P, _SZ, _P]),
     "imex_solve": (_I, [_P, ctypes.POINTER(SwePar), _I, _D, _P, _P, _P]),
@@ -187,6 +189,28 @@ class Plan:
         ws = self.ws.get(nb)
         _check(lib().sh_forward(self.h, F, _ptr(grid), _ptr(spec), _ptr(ws), nb, _stream()), "sh_forward")
         return spec
+
+
+def legendre_synthesis(plan, nfield, nmax, spec_ext, fourier_out):
+    """Legendre step of the synthesis on the library layouts (see the C header)."""
+    import torch
+    ne = (plan.N + 1) * (plan.N + 4) // 2
+    _need(spec_ext, torch.complex128, ne * nfield, "spec_ext")
+    _need(fourier_out, torch.complex128, plan.nlat * (plan.N + 1) * nfield, "fourier_out")
+    _check(lib().sh_legendre_synthesis(plan.h, nfield, nmax, _ptr(spec_ext), _ptr(fourier_out), _stream()),
+           "sh_legendre_synthesis")
+    return fourier_out
+
+
+def legendre_analysis(plan, nfield, nmax, fourier_in, spec_ext):
+    """Legendre step of the analysis on the library layouts (see the C header)."""
+    import torch
+    ne = (plan.N + 1) * (plan.N + 4) // 2
+    _need(fourier_in, torch.complex128, plan.nlat * (plan.N + 1) * nfield, "fourier_in")
+    _need(spec_ext, torch.complex128, ne * nfield, "spec_ext")
+    _check(lib().sh_legendre_analysis(plan.h, nfield, nmax, _ptr(fourier_in), _ptr(spec_ext), _stream()),
+           "sh_legendre_analysis")
+    return spec_ext
 
 
 def swe_params(a=6.37122e6, omega=7.292e-5, g=9.80616, phibar=2.94e4, nu=1.0e5):

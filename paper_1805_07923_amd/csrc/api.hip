@@ -391,6 +391,32 @@ int sh_forward(const shx_plan* pl, int F, const double* grid, double* spec, void
     return SHX_OK;
 }
 
+int sh_legendre_synthesis(const shx_plan* pl, int F, int nmax, const double* spec_ext, double* fourier,
+                          shx_stream_t stream) {
+    if (!pl || F < 1 || !spec_ext || !fourier || !aligned16(spec_ext) || !aligned16(fourier) ||
+        (nmax != pl->N && nmax != pl->N + 1))
+        return SHX_EINVAL;
+    hipStream_t st = S(stream);
+    HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] {
+        return launch_leg_syn(pl, reinterpret_cast<const double2*>(spec_ext), reinterpret_cast<double2*>(fourier), F,
+                              1, nmax, st);
+    }));
+    return SHX_OK;
+}
+
+int sh_legendre_analysis(const shx_plan* pl, int F, int nmax, const double* fourier, double* spec_ext,
+                         shx_stream_t stream) {
+    if (!pl || F < 1 || !spec_ext || !fourier || !aligned16(spec_ext) || !aligned16(fourier) ||
+        (nmax != pl->N && nmax != pl->N + 1))
+        return SHX_EINVAL;
+    hipStream_t st = S(stream);
+    HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] {
+        return launch_leg_an(pl, reinterpret_cast<const double2*>(fourier), reinterpret_cast<double2*>(spec_ext), F,
+                             1, nmax, st);
+    }));
+    return SHX_OK;
+}
+
 size_t swe_workspace_bytes(const shx_plan* pl, int nstate) {
     if (!pl || nstate < 1) return 0;
     return tend_bytes(pl, nstate);

@@ -100,6 +100,38 @@ def test_sh_pair(pk, N, J, I, F):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("N,J,I,F,nmax_plus", [(31, 48, 96, 5, 1), (63, 96, 192, 3, 0)])
+def test_legendre_steps(pk, N, J, I, F, nmax_plus):
+    """The Legendre-only entry points on their documented layouts."""
+    print_case("legendre steps", N, J, I, F)
+    nmax = N + nmax_plus
+    g = ogrid(N, J, I)
+    plan = pk.Plan(N, J, I)
+    gen = torch.Generator().manual_seed(5)
+    ne = OH.nspec(N, N + 1)
+    spec = torch.randn(ne, F, dtype=torch.complex128, generator=gen)
+    spec[torch.tensor([m == 0 for m in OH.orders(N, N + 1).tolist()])] = spec[
+        torch.tensor([m == 0 for m in OH.orders(N, N + 1).tolist()])].real.to(torch.complex128)
+    keep = (OH.degrees(N, N + 1) <= nmax)[:, None]
+    spec = torch.where(keep, spec, torch.zeros_like(spec))
+    four = torch.empty(2, J // 2, N + 1, F, dtype=torch.complex128, device="cuda")
+    pk.legendre_synthesis(plan, F, nmax, dev(spec), four)
+    four = four.cpu()
+    north = four[0] + four[1]
+    south = (four[0] - four[1]).flip(0)
+    got = torch.cat([north, south], dim=0)                       # [J][N+1][F]
+    for f in range(F):
+        ref = g.legendre_synthesis(spec[:, f], N + 1)            # [J][N+1]
+        assert relerr(got[:, :, f], ref) < TOL, f
+    fin = torch.randn(J, N + 1, F, dtype=torch.complex128, generator=gen)
+    out = torch.zeros(ne, F, dtype=torch.complex128, device="cuda")
+    pk.legendre_analysis(plan, F, nmax, dev(fin), out)
+    out = out.cpu()
+    for f in range(F):
+        ref = g.legendre_analysis(fin[:, :, f], torch.ones(J, dtype=torch.float64), N + 1)
+        assert relerr(out[:, f][keep[:, 0]], ref[keep[:, 0]]) < TOL, f
+
+
 def test_sh_deterministic(pk):
     print_case("sh_deterministic")
     plan = pk.Plan(63, 96, 192)
