@@ -29,6 +29,12 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->tw);
     (void)hipFree(p->psyn);
     (void)hipFree(p->pan);
+    (void)hipFree(p->psyn32);
+    (void)hipFree(p->pan32);
+    (void)hipFree(p->an16);
+    (void)hipFree(p->syn16);
+    (void)hipFree(p->off_an16);
+    (void)hipFree(p->off_syn16);
     (void)hipFree(p->off);
     (void)hipFree(p->ord);
     (void)hipFree(p->deg);
@@ -207,6 +213,48 @@ bool valid_params(const swe_params* p) {
     return p && p->a > 0.0;
 }
 
+// Round / split the FP64 tables into the plan's working precision and free
+// the FP64 copies.  Synchronous (plan creation).
+bool convert_tables(shx_plan* p) {
+    const int N = p->N, nb = 2 * (N + 1);
+    bool ok = true;
+    if (p->prec == SHX_FP32) {
+        ok = dalloc(&p->psyn32, p->table_elems) == hipSuccess && dalloc(&p->pan32, p->table_elems) == hipSuccess;
+        ok = ok && launch_tables_to_f32(p, 0) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    } else {
+        const int NP = p->prec == SHX_SPLIT_BF16_2 ? 2 : 3;
+        const int Jhp = (p->Jh + 15) / 16 * 16;
+        std::vector<int> ra(nb), ca(nb), cpa(nb), rs(nb), cs(nb), cps(nb);
+        std::vector<long long> oa(nb), os(nb);
+        long long sa = 0, ss = 0;
+        for (int m = 0; m <= N; ++m)
+            for (int q = 0; q < 2; ++q) {
+                const int b = 2 * m + q, K = kcount(p->nmax, m, q), Kp = (K + 15) / 16 * 16;
+                ra[b] = K; ca[b] = p->Jh; cpa[b] = Jhp; oa[b] = sa; sa += (long long)K * Jhp;   // [k][jp]
+                rs[b] = p->Jh; cs[b] = K; cps[b] = Kp; os[b] = ss; ss += (long long)p->Jh * Kp;  // [jp][k]
+            }
+        p->an16_plane = (sa + 15) / 16 * 16;
+        p->syn16_plane = (ss + 15) / 16 * 16;
+        int* d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        std::vector<int>* h[6] = {&ra, &ca, &cpa, &rs, &cs, &cps};
+        ok = dalloc(&p->an16, NP * p->an16_plane) == hipSuccess &&
+             dalloc(&p->syn16, NP * p->syn16_plane) == hipSuccess && dalloc(&p->off_an16, nb) == hipSuccess &&
+             dalloc(&p->off_syn16, nb) == hipSuccess;
+        for (int i = 0; i < 6 && ok; ++i)
+            ok = dalloc(&d[i], nb) == hipSuccess &&
+                 hipMemcpy(d[i], h[i]->data(), nb * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(p->off_an16, oa.data(), nb * 8, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(p->off_syn16, os.data(), nb * 8, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && launch_tables_to_bf16(p, d[0], d[1], d[2], d[3], d[4], d[5], 0) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+        for (int i = 0; i < 6; ++i) (void)hipFree(d[i]);
+    }
+    (void)hipFree(p->psyn);
+    (void)hipFree(p->pan);
+    p->psyn = p->pan = nullptr;
+    return ok;
+}
+
 }  // namespace
 
 extern "C" {
@@ -265,7 +313,7 @@ const char* shx_strerror(int s) {
 int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
     if (!out || N < 1 || J < 2 || I < 2) return SHX_EINVAL;
     *out = nullptr;
-    if (prec != SHX_FP64) return SHX_EUNSUPPORTED;
+    if (prec < SHX_FP64 || prec > SHX_SPLIT_BF16_3) return SHX_EUNSUPPORTED;
     if ((J & 1) || I <= 2 * N || J <= N) return SHX_ESHAPE;
     if (!fft_length_supported(I)) return SHX_EUNSUPPORTED;
     shx_plan* p = new (std::nothrow) shx_plan();
@@ -329,6 +377,7 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
     ok = ok && hipMemcpy(p->deg_e, dege.data(), dege.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && launch_plm_table(p, 0) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
+    if (ok && prec != SHX_FP64) ok = convert_tables(p);
     if (!ok) {
         plan_free(p);
         return SHX_EHIP;
@@ -352,8 +401,35 @@ int shx_plan_latitudes(const shx_plan* pl, double* mu, double* st, double* w) {
 int shx_plan_legendre(const shx_plan* pl, int m, int n, double* out) {
     if (!pl || !out || m < 0 || m > pl->N || n < m || n > pl->nmax) return SHX_EINVAL;
     const int p = (n - m) & 1, k = (n - m) >> 1;
-    const double* src = pl->psyn + pl->h_off[2 * m + p] + (long long)k * pl->Jh;
-    if (hipMemcpy(out, src, pl->Jh * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return SHX_EHIP;
+    const long long o = pl->h_off[2 * m + p] + (long long)k * pl->Jh;   // row k of the [k][jp] layout
+    if (pl->prec == SHX_FP64) {
+        if (hipMemcpy(out, pl->psyn + o, pl->Jh * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return SHX_EHIP;
+    } else if (pl->prec == SHX_FP32) {
+        std::vector<float> t(pl->Jh);
+        if (hipMemcpy(t.data(), pl->psyn32 + o, pl->Jh * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+            return SHX_EHIP;
+        for (int j = 0; j < pl->Jh; ++j) out[j] = t[j];
+    } else {
+        // analysis planes hold [k][jp pad 16] per (m, p): sum of the split planes
+        const int NP = pl->prec == SHX_SPLIT_BF16_2 ? 2 : 3;
+        const int Jhp = (pl->Jh + 15) / 16 * 16;
+        long long o16 = 0;
+        for (int b = 0; b < 2 * m + p; ++b) o16 += (long long)kcount(pl->nmax, b / 2, b % 2) * Jhp;
+        o16 += (long long)k * Jhp;
+        for (int j = 0; j < pl->Jh; ++j) out[j] = 0.0;
+        std::vector<unsigned short> t(pl->Jh);
+        for (int q = 0; q < NP; ++q) {
+            if (hipMemcpy(t.data(), pl->an16 + q * pl->an16_plane + o16, pl->Jh * 2, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return SHX_EHIP;
+            for (int j = 0; j < pl->Jh; ++j) {
+                const unsigned u = (unsigned)t[j] << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                out[j] += f;
+            }
+        }
+    }
     return SHX_OK;
 }
 

@@ -43,8 +43,15 @@ struct shx_plan {
     double* cos2 = nullptr;         // device [J], 1 - mu^2
     double* w = nullptr;            // device [J]
     double2* tw = nullptr;          // device [I], e^{-2 pi i t / I}
-    double* psyn = nullptr;         // FP64 table, [m][p][k][jp]
-    double* pan = nullptr;          // FP64 table, [m][p][jp][k]
+    double* psyn = nullptr;         // FP64 table, [m][p][k][jp] (FP64 plans)
+    double* pan = nullptr;          // FP64 table, [m][p][jp][k] (FP64 plans)
+    float* psyn32 = nullptr;        // FP32 tables (SHX_FP32 plans), same layouts
+    float* pan32 = nullptr;
+    unsigned short* an16 = nullptr;   // bf16 split planes for the analysis, [q][m][p][k][jp pad 16]
+    unsigned short* syn16 = nullptr;  // bf16 split planes for the synthesis, [q][m][p][jp][k pad 16]
+    long long an16_plane = 0, syn16_plane = 0;
+    long long* off_an16 = nullptr;    // device [(N+1)*2] offsets into a bf16 plane
+    long long* off_syn16 = nullptr;
     long long* off = nullptr;       // device [(N+1)*2] table offsets (elements)
     int* ord = nullptr;             // device [nspec] zonal order of each entry
     int* deg = nullptr;             // device [nspec] degree of each entry
@@ -79,6 +86,15 @@ hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, 
                           int nmax_use, hipStream_t st);
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
                          int nmax_use, hipStream_t st);
+// legendre_mixed.hip (plans with a reduced working precision)
+hipError_t launch_leg_an_mixed(const shx_plan* pl, const double2* G, double2* cout, int F, int S, int nmax_use,
+                               hipStream_t st);
+hipError_t launch_leg_syn_mixed(const shx_plan* pl, const double2* cin, double2* out, int F, int S, int nmax_use,
+                                hipStream_t st);
+hipError_t launch_tables_to_f32(const shx_plan* pl, hipStream_t st);
+hipError_t launch_tables_to_bf16(const shx_plan* pl, const int* d_rows_an, const int* d_cols_an,
+                                 const int* d_colsp_an, const int* d_rows_syn, const int* d_cols_syn,
+                                 const int* d_colsp_syn, hipStream_t st);
 // fourier.hip
 hipError_t launch_fft_inv(const shx_plan* pl, const double2* FI, double* grid, int F, hipStream_t st);
 hipError_t launch_fft_fwd(const shx_plan* pl, const double* grid, double2* G, int F, hipStream_t st);

@@ -262,6 +262,7 @@ hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
 // Fields are processed in chunks of at most 8 (16 accumulators per lane).
 hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, int F, int S,
                           int nmax_use, hipStream_t st) {
+    if (pl->prec != SHX_FP64) return launch_leg_syn_mixed(pl, cin, out, F, S, nmax_use, st);
     for (int f0 = 0; f0 < F; f0 += 8) {
         const int nf = (F - f0 < 8) ? F - f0 : 8;
         switch (nf) {
@@ -280,6 +281,7 @@ hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, 
 
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
                          int nmax_use, hipStream_t st) {
+    if (pl->prec != SHX_FP64) return launch_leg_an_mixed(pl, G, cout, F, S, nmax_use, st);
     for (int f0 = 0; f0 < F; f0 += 8) {
         const int nf = (F - f0 < 8) ? F - f0 : 8;
         switch (nf) {
