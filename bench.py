@@ -76,13 +76,13 @@ def measured_traffic():
         return None
 
 
-def make_stepper(pk, fine, coarse, niter, nsweep, residual=False):
+def make_stepper(pk, fine, coarse, niter, nsweep, residual=False, precision=0):
     par = pk.swe_params()
-    pf = pk.Plan(fine["N"], fine["J"], fine["I"])
+    pf = pk.Plan(fine["N"], fine["J"], fine["I"], precision)
     lf = pk.Level(pf, par, pk.SDC_GAUSS_LOBATTO, fine["nodes"])
     lc = None
     if coarse:
-        pc = pk.Plan(coarse["N"], coarse["J"], coarse["I"])
+        pc = pk.Plan(coarse["N"], coarse["J"], coarse["I"], precision)
         lc = pk.Level(pc, par, pk.SDC_GAUSS_LOBATTO, coarse["nodes"])
     return pk.Stepper(lf, lc, niter=niter, nsweep_fine=nsweep, nsweep_coarse=nsweep, residual_check=residual)
 
@@ -252,28 +252,59 @@ def main():
         stc1 = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
         s1, _ = run_steps(torch, stc1, x1, max(5, args.steps), 2, graph)
         extra["steps_per_s_T127_T63_sweeps_2_2"] = max(5, args.steps) / s1
-        # Legendre GFLOP/s, T255, 15 fields, FP64 (synthesis and analysis)
-        plan = pk.Plan(255, 384, 768)
-        spec = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1), device="cuda")
-        grid = plan.inverse(spec)
-        plan.forward(grid)
-        torch.cuda.synchronize()
-        reps = 20
-        with pk.KernelTimer(pk.KC_LEGENDRE_SYN, reps) as ks:
-            for _ in range(reps):
-                plan.inverse(spec, grid)
-            torch.cuda.synchronize()
-        with pk.KernelTimer(pk.KC_LEGENDRE_AN, reps) as ka:
-            for _ in range(reps):
-                plan.forward(grid, spec)
-            torch.cuda.synchronize()
+        # Legendre GFLOP/s, T255, 15 fields (one launch per direction), per precision
+        spec0 = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1), device="cuda")
         fl = legendre_flops(255, 384, 15, 255)
-        extra["legendre_T255_F15_fp64"] = {
-            "synthesis_gflops": fl / (np.mean(ks.ms) * 1e-3) / 1e9 if ks.ms else None,
-            "analysis_gflops": fl / (np.mean(ka.ms) * 1e-3) / 1e9 if ka.ms else None,
-            "flop_per_direction": fl, "synthesis_us": float(np.mean(ks.ms) * 1e3) if ks.ms else None,
-            "analysis_us": float(np.mean(ka.ms) * 1e3) if ka.ms else None,
-        }
+        ref_grid = None
+        for pname, prec in (("fp64", 0), ("fp32", 1), ("bf16x2", 2), ("bf16x3", 3)):
+            plan = pk.Plan(255, 384, 768, prec)
+            spec = spec0.clone()
+            grid = plan.inverse(spec)
+            spec_b = plan.forward(grid)
+            torch.cuda.synchronize()
+            if ref_grid is None:
+                ref_grid, ref_spec = grid.clone(), spec_b.clone()
+            reps = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            cin = torch.zeros((256 * 259 // 2) * 15, dtype=torch.complex128, device="cuda")
+            four = torch.zeros(384 * 256 * 15, dtype=torch.complex128, device="cuda")
+            pk.legendre_synthesis(plan, 15, 255, cin, four)
+            e0.record()
+            for _ in range(reps):
+                pk.legendre_synthesis(plan, 15, 255, cin, four)
+            e1.record()
+            torch.cuda.synchronize()
+            syn_us = e0.elapsed_time(e1) * 1e3 / reps
+            e0.record()
+            for _ in range(reps):
+                pk.legendre_analysis(plan, 15, 255, four, cin)
+            e1.record()
+            torch.cuda.synchronize()
+            an_us = e0.elapsed_time(e1) * 1e3 / reps
+            err_g = max((torch.linalg.vector_norm(grid[f] - ref_grid[f]) / torch.linalg.vector_norm(ref_grid[f])).item()
+                        for f in range(15))
+            err_s = max((torch.linalg.vector_norm(spec_b[f] - ref_spec[f]) / torch.linalg.vector_norm(ref_spec[f])).item()
+                        for f in range(15))
+            extra[f"legendre_T255_F15_{pname}"] = {
+                "synthesis_gflops": fl / (syn_us * 1e-6) / 1e9, "analysis_gflops": fl / (an_us * 1e-6) / 1e9,
+                "synthesis_us": syn_us, "analysis_us": an_us, "flop_per_direction": fl,
+                "max_rel_err_vs_fp64_inverse": err_g, "max_rel_err_vs_fp64_roundtrip": err_s,
+            }
+            del plan
+        # the benchmark step with reduced-precision Legendre contractions
+        ref_state = None
+        for pname, prec in (("fp64", 0), ("fp32", 1), ("bf16x2", 2), ("bf16x3", 3)):
+            stp = make_stepper(pk, FINE, COARSE, NITER, NSWEEP, precision=prec)
+            one = stp.step(DT, x0.clone())
+            torch.cuda.synchronize()
+            if ref_state is None:
+                ref_state = one.clone()
+            sp, _ = run_steps(torch, stp, x0, max(5, args.steps // 2), 2, graph)
+            errs = [(torch.linalg.vector_norm(one[f] - ref_state[f]) / torch.linalg.vector_norm(ref_state[f])).item()
+                    for f in range(3)]
+            extra[f"steps_per_s_T255_T127_{pname}"] = {"value": max(5, args.steps // 2) / sp,
+                                                       "one_step_rel_err_vs_fp64": errs}
+            del stp
         out["extra"] = extra
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib * (1 << 20) // 8

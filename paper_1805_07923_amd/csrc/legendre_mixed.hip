@@ -25,6 +25,9 @@
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int U4 = 8;     // FP32 MFMA: chunks of 4 reduction elements per batch of loads
+constexpr int U16 = 2;    // bf16 MFMA: chunks of 16 reduction elements per batch of loads
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short f2bf(float x) {
@@ -121,9 +124,8 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
         __syncthreads();
         // stage g: FP32 as [jp][CW]; bf16 planes as [q][c][Jhp]
         for (int i = threadIdx.x; i < Jhp * CW; i += 256) {
-            int jp, c;
-            if constexpr (MODE == 1) { jp = i / CW; c = i - jp * CW; }
-            else { c = i / Jhp; jp = i - c * Jhp; }
+            // columns fastest: consecutive threads read consecutive fields
+            const int jp = i / CW, c = i - jp * CW;
             double v = 0.0;
             if (jp < Jh && c < 2 * NF) {
                 const double2 a = g[jp * rowstride + c / 2], b = g[(J - 1 - jp) * rowstride + c / 2];
@@ -135,7 +137,8 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
                 unsigned short h[NP];
                 split_bf16<NP>(v, h);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) reinterpret_cast<unsigned short*>(smem)[q * Jhp * CW + i] = h[q];
+                for (int q = 0; q < NP; ++q)
+                    reinterpret_cast<unsigned short*>(smem)[q * Jhp * CW + c * Jhp + jp] = h[q];
             }
         }
         __syncthreads();
@@ -151,35 +154,53 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
         if constexpr (MODE == 1) {
             const float* P = static_cast<const float*>(tab) + off[2 * m + p] + (row_ok ? row : 0);
             const float* gs = reinterpret_cast<const float*>(smem);
-            for (int jp0 = 0; jp0 < Jh; jp0 += 4) {
-                const int jp = jp0 + (lane >> 4);
-                const float a = (row_ok && jp < Jh) ? P[(long long)jp * Ktab] : 0.f;
+            // U4 chunks of 4 latitudes: their table loads are issued before the MFMAs
+            for (int jc = 0; jc < Jh; jc += 4 * U4) {
+                float a[U4];
 #pragma unroll
-                for (int t = 0; t < NCT; ++t) {
-                    const float b = (jp < Jh) ? gs[jp * CW + 16 * t + (lane & 15)] : 0.f;
-                    acc0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc0[t], 0, 0, 0);
+                for (int u = 0; u < U4; ++u) {
+                    const int jp = jc + 4 * u + (lane >> 4);
+                    a[u] = (row_ok && jp < Jh) ? P[(long long)jp * Ktab] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < U4; ++u) {
+                    const int jp = jc + 4 * u + (lane >> 4);
+#pragma unroll
+                    for (int t = 0; t < NCT; ++t) {
+                        const float b = (jp < Jh) ? gs[jp * CW + 16 * t + (lane & 15)] : 0.f;
+                        acc0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc0[t], 0, 0, 0);
+                    }
                 }
             }
         } else {
             const unsigned short* P = static_cast<const unsigned short*>(tab);
             const long long base = off[2 * m + p] + (long long)(row_ok ? row : 0) * Jhp;
             const unsigned short* gs = reinterpret_cast<const unsigned short*>(smem);
-            for (int jp0 = 0; jp0 < Jhp; jp0 += 16) {
-                const int q4 = jp0 + 4 * (lane >> 4);
-                shortx4 a[NP];
+            for (int jc = 0; jc < Jhp; jc += 16 * U16) {
+                shortx4 a[U16][NP];
 #pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const shortx4 v = *reinterpret_cast<const shortx4*>(P + q * plane + base + q4);
-                    a[q] = row_ok ? v : shortx4{0, 0, 0, 0};
+                for (int u = 0; u < U16; ++u) {
+                    const int q4 = jc + 16 * u + 4 * (lane >> 4);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        const shortx4 v = (q4 < Jhp) ? *reinterpret_cast<const shortx4*>(P + q * plane + base + q4)
+                                                     : shortx4{0, 0, 0, 0};
+                        a[u][q] = row_ok ? v : shortx4{0, 0, 0, 0};
+                    }
                 }
 #pragma unroll
-                for (int t = 0; t < NCT; ++t) {
-                    shortx4 b[NP];
-                    const int c = 16 * t + (lane & 15);
+                for (int u = 0; u < U16; ++u) {
+                    const int q4 = jc + 16 * u + 4 * (lane >> 4);
+                    if (jc + 16 * u >= Jhp) break;
 #pragma unroll
-                    for (int q = 0; q < NP; ++q)
-                        b[q] = *reinterpret_cast<const shortx4*>(gs + q * Jhp * CW + c * Jhp + q4);
-                    mfma_split<MODE>(a, b, acc0[t], acc1[t]);
+                    for (int t = 0; t < NCT; ++t) {
+                        shortx4 b[NP];
+                        const int c = 16 * t + (lane & 15);
+#pragma unroll
+                        for (int q = 0; q < NP; ++q)
+                            b[q] = *reinterpret_cast<const shortx4*>(gs + q * Jhp * CW + c * Jhp + q4);
+                        mfma_split<MODE>(a[u], b, acc0[t], acc1[t]);
+                    }
                 }
             }
         }
@@ -226,9 +247,8 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
         __syncthreads();
         // stage C: FP32 as [k][CW]; bf16 planes as [q][c][Kp]
         for (int i = threadIdx.x; i < KL * CW; i += 256) {
-            int k, cc;
-            if constexpr (MODE == 1) { k = i / CW; cc = i - k * CW; }
-            else { cc = i / Kp; k = i - cc * Kp; }
+            // columns fastest: consecutive threads read consecutive fields
+            const int k = i / CW, cc = i - k * CW;
             double v = 0.0;
             if (k < K && cc < 2 * NF) {
                 const double2 x = c[(long long)(2 * k) * F + cc / 2];
@@ -240,7 +260,8 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
                 unsigned short h[NP];
                 split_bf16<NP>(v, h);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) reinterpret_cast<unsigned short*>(smem)[q * Kp * CW + i] = h[q];
+                for (int q = 0; q < NP; ++q)
+                    reinterpret_cast<unsigned short*>(smem)[q * Kp * CW + cc * Kp + k] = h[q];
             }
         }
         __syncthreads();
@@ -256,35 +277,52 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
         if constexpr (MODE == 1) {
             const float* P = static_cast<const float*>(tab) + off[2 * m + p] + (j_ok ? jr : 0);
             const float* cs = reinterpret_cast<const float*>(smem);
-            for (int kk0 = 0; kk0 < K; kk0 += 4) {
-                const int k = kk0 + (lane >> 4);
-                const float a = (j_ok && k < K) ? P[(long long)k * Jh] : 0.f;
+            for (int kc = 0; kc < K; kc += 4 * U4) {
+                float a[U4];
 #pragma unroll
-                for (int t = 0; t < NCT; ++t) {
-                    const float b = (k < K) ? cs[k * CW + 16 * t + (lane & 15)] : 0.f;
-                    acc0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc0[t], 0, 0, 0);
+                for (int u = 0; u < U4; ++u) {
+                    const int k = kc + 4 * u + (lane >> 4);
+                    a[u] = (j_ok && k < K) ? P[(long long)k * Jh] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < U4; ++u) {
+                    const int k = kc + 4 * u + (lane >> 4);
+#pragma unroll
+                    for (int t = 0; t < NCT; ++t) {
+                        const float b = (k < K) ? cs[k * CW + 16 * t + (lane & 15)] : 0.f;
+                        acc0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc0[t], 0, 0, 0);
+                    }
                 }
             }
         } else {
             const unsigned short* P = static_cast<const unsigned short*>(tab);
             const long long base = off[2 * m + p] + (long long)(j_ok ? jr : 0) * Kp;
             const unsigned short* cs = reinterpret_cast<const unsigned short*>(smem);
-            for (int kk0 = 0; kk0 < K; kk0 += 16) {
-                const int q4 = kk0 + 4 * (lane >> 4);
-                shortx4 a[NP];
+            for (int kc = 0; kc < K; kc += 16 * U16) {
+                shortx4 a[U16][NP];
 #pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const shortx4 v = *reinterpret_cast<const shortx4*>(P + q * plane + base + q4);
-                    a[q] = j_ok ? v : shortx4{0, 0, 0, 0};
+                for (int u = 0; u < U16; ++u) {
+                    const int q4 = kc + 16 * u + 4 * (lane >> 4);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        const shortx4 v = (q4 < Kp) ? *reinterpret_cast<const shortx4*>(P + q * plane + base + q4)
+                                                    : shortx4{0, 0, 0, 0};
+                        a[u][q] = j_ok ? v : shortx4{0, 0, 0, 0};
+                    }
                 }
 #pragma unroll
-                for (int t = 0; t < NCT; ++t) {
-                    shortx4 b[NP];
-                    const int cc = 16 * t + (lane & 15);
+                for (int u = 0; u < U16; ++u) {
+                    const int q4 = kc + 16 * u + 4 * (lane >> 4);
+                    if (kc + 16 * u >= K) break;
 #pragma unroll
-                    for (int q = 0; q < NP; ++q)
-                        b[q] = *reinterpret_cast<const shortx4*>(cs + q * Kp * CW + cc * Kp + q4);
-                    mfma_split<MODE>(a, b, acc0[t], acc1[t]);
+                    for (int t = 0; t < NCT; ++t) {
+                        shortx4 b[NP];
+                        const int cc = 16 * t + (lane & 15);
+#pragma unroll
+                        for (int q = 0; q < NP; ++q)
+                            b[q] = *reinterpret_cast<const shortx4*>(cs + q * Kp * CW + cc * Kp + q4);
+                        mfma_split<MODE>(a[u], b, acc0[t], acc1[t]);
+                    }
                 }
             }
         }
