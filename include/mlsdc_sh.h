@@ -211,6 +211,50 @@ int mlsdc_step(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts*
                double dt, const double* theta_n_dev, double* theta_np1_dev,
                double* status_dev, void* ws_dev, size_t ws_bytes, shx_stream_t stream);
 
+/* -------------------------------------------------------------- adjoints
+ * Transposes of the Jacobians above (reverse mode), FP64.  Inner products:
+ * spectral arrays <x, y> = sum over the stored coefficients of
+ * Re x Re y + Im x Im y; grids sum_ij x_ij y_ij.  So a cotangent returned for
+ * a spectral input is the gradient with respect to its real and imaginary
+ * parts.  Transforms with nlon = 2048 or 3072 are not supported here
+ * (SHX_EUNSUPPORTED). */
+
+/* spec_cot = S^T grid_cot for the synthesis S of sh_inverse:
+ *   spec_cot^m_n = c_m sum_j P^m_n(mu_j) sum_i grid_cot_ij e^{-i m lambda_i}, c_0 = 1, c_m = 2.
+ * Workspace: shx_workspace_bytes(plan, nfield). */
+int sh_inverse_adj(const shx_plan* plan, int nfield, const double* grid_cot_dev, double* spec_cot_dev,
+                   void* ws_dev, size_t ws_bytes, shx_stream_t stream);
+
+/* grid_cot = A^T spec_cot for the analysis A of sh_forward:
+ *   grid_cot_ij = (w_j / nlon) sum_{m >= 0} Re[(sum_n spec_cot^m_n P^m_n(mu_j)) e^{i m lambda_i}]. */
+int sh_forward_adj(const shx_plan* plan, int nfield, const double* spec_cot_dev, double* grid_cot_dev,
+                   void* ws_dev, size_t ws_bytes, shx_stream_t stream);
+
+size_t swe_adj_workspace_bytes(const shx_plan* plan, int nstate);
+
+/* lam_state += (dF_I/dTheta)^T lam_fi + (dF_E/dTheta)^T lam_fe, linearised at
+ * state (the products of F_E are linearised on the grid; the transforms are
+ * transposed as above).  lam_fi or lam_fe may be NULL.  All [nstate][3][nspec]. */
+int swe_tendency_adj(const shx_plan* plan, const swe_params* params, int nstate, const double* state_dev,
+                     const double* lam_fi_dev, const double* lam_fe_dev, double* lam_state_dev, void* ws_dev,
+                     size_t ws_bytes, shx_stream_t stream);
+
+/* lam_rhs = (I - h F_I)^{-T} lam_out (transpose of imex_solve). */
+int imex_solve_adj(const shx_plan* plan, const swe_params* params, int nstate, double h,
+                   const double* lam_out_dev, double* lam_rhs_dev, shx_stream_t stream);
+
+size_t mlsdc_adj_workspace_bytes(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts* opts);
+
+/* lam_n = (d Theta^{n+1} / d Theta^n)^T lam_np1 for one mlsdc_step from the
+ * checkpoint theta_n: the step is recomputed, recording every state at which
+ * F is evaluated, then Algorithm 1 is run backwards (step D, coarse sweeps,
+ * FAS term, restriction, fine sweeps, spread) with the transposed node
+ * updates, solves, transfers and tendencies.  residual_check is ignored.
+ * lam_n must not alias theta_n or lam_np1. */
+int mlsdc_step_adj(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts* opts, double dt,
+                   const double* theta_n_dev, const double* lam_np1_dev, double* lam_n_dev, void* ws_dev,
+                   size_t ws_bytes, shx_stream_t stream);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Kernel classes for the timer below. */

@@ -51,6 +51,13 @@ _SIGS = {
     "sdc_sweep": (_I, [_P, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "mlsdc_workspace_bytes": (_SZ, [_P, _P, ctypes.POINTER(MlsdcOpts)]),
     "mlsdc_step": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P, _SZ, _P]),
+    "sh_inverse_adj": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
+    "sh_forward_adj": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
+    "swe_adj_workspace_bytes": (_SZ, [_P, _I]),
+    "swe_tendency_adj": (_I, [_P, ctypes.POINTER(SwePar), _I, _P, _P, _P, _P, _P, _SZ, _P]),
+    "imex_solve_adj": (_I, [_P, ctypes.POINTER(SwePar), _I, _D, _P, _P, _P]),
+    "mlsdc_adj_workspace_bytes": (_SZ, [_P, _P, ctypes.POINTER(MlsdcOpts)]),
+    "mlsdc_step_adj": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P, _SZ, _P]),
     "shx_kernel_timer_start": (_I, [_I, _I]),
     "shx_kernel_timer_stop": (_I, [_P, ctypes.POINTER(_I)]),
 }
@@ -190,6 +197,34 @@ class Plan:
         _check(lib().sh_forward(self.h, F, _ptr(grid), _ptr(spec), _ptr(ws), nb, _stream()), "sh_forward")
         return spec
 
+    def inverse_adj(self, grid_cot, spec_cot=None):
+        """Transpose of inverse(): grid cotangent [F, nlat, nlon] -> spectral cotangent [F, nspec]."""
+        import torch
+        F = grid_cot.shape[0]
+        _need(grid_cot, torch.float64, F * self.nlat * self.nlon, "grid_cot")
+        if spec_cot is None:
+            spec_cot = torch.empty(F, self.nspec, dtype=torch.complex128, device=grid_cot.device)
+        _need(spec_cot, torch.complex128, F * self.nspec, "spec_cot")
+        nb = lib().shx_workspace_bytes(self.h, F)
+        ws = self.ws.get(nb)
+        _check(lib().sh_inverse_adj(self.h, F, _ptr(grid_cot), _ptr(spec_cot), _ptr(ws), nb, _stream()),
+               "sh_inverse_adj")
+        return spec_cot
+
+    def forward_adj(self, spec_cot, grid_cot=None):
+        """Transpose of forward(): spectral cotangent [F, nspec] -> grid cotangent [F, nlat, nlon]."""
+        import torch
+        F = spec_cot.shape[0]
+        _need(spec_cot, torch.complex128, F * self.nspec, "spec_cot")
+        if grid_cot is None:
+            grid_cot = torch.empty(F, self.nlat, self.nlon, dtype=torch.float64, device=spec_cot.device)
+        _need(grid_cot, torch.float64, F * self.nlat * self.nlon, "grid_cot")
+        nb = lib().shx_workspace_bytes(self.h, F)
+        ws = self.ws.get(nb)
+        _check(lib().sh_forward_adj(self.h, F, _ptr(spec_cot), _ptr(grid_cot), _ptr(ws), nb, _stream()),
+               "sh_forward_adj")
+        return grid_cot
+
 
 def legendre_synthesis(plan, nfield, nmax, spec_ext, fourier_out):
     """Legendre step of the synthesis on the library layouts (see the C header)."""
@@ -231,6 +266,37 @@ def tendency(plan, params, state, f_impl=None, f_expl=None, ws=None):
     _check(lib().swe_tendency(plan.h, ctypes.byref(params), S, _ptr(state), _ptr(f_impl), _ptr(f_expl),
                               _ptr(w), nb, _stream()), "swe_tendency")
     return f_impl, f_expl
+
+
+def tendency_adj(plan, params, state, lam_fi=None, lam_fe=None, lam_state=None, ws=None):
+    """lam_state (+)= (dF_I/dTheta)^T lam_fi + (dF_E/dTheta)^T lam_fe at `state` [S, 3, nspec]."""
+    import torch
+    S = state.shape[0] if state.dim() == 3 else 1
+    n = S * 3 * plan.nspec
+    _need(state, torch.complex128, n, "state")
+    for t, nm in ((lam_fi, "lam_fi"), (lam_fe, "lam_fe")):
+        if t is not None:
+            _need(t, torch.complex128, n, nm)
+    if lam_state is None:
+        lam_state = torch.zeros_like(state)
+    _need(lam_state, torch.complex128, n, "lam_state")
+    nb = lib().swe_adj_workspace_bytes(plan.h, S)
+    w = (ws or plan.ws).get(nb)
+    _check(lib().swe_tendency_adj(plan.h, ctypes.byref(params), S, _ptr(state), _ptr(lam_fi), _ptr(lam_fe),
+                                  _ptr(lam_state), _ptr(w), nb, _stream()), "swe_tendency_adj")
+    return lam_state
+
+
+def solve_adj(plan, params, h, lam_out, lam_rhs=None):
+    """Transpose of solve(): lam_rhs = (I - h F_I)^{-T} lam_out."""
+    import torch
+    S = lam_out.shape[0] if lam_out.dim() == 3 else 1
+    _need(lam_out, torch.complex128, S * 3 * plan.nspec, "lam_out")
+    if lam_rhs is None:
+        lam_rhs = torch.empty_like(lam_out)
+    _check(lib().imex_solve_adj(plan.h, ctypes.byref(params), S, float(h), _ptr(lam_out), _ptr(lam_rhs),
+                                _stream()), "imex_solve_adj")
+    return lam_rhs
 
 
 def solve(plan, params, h, rhs, out=None):
@@ -290,7 +356,25 @@ class Stepper:
         self.fine, self.coarse = fine, coarse
         self.opts = MlsdcOpts(niter, nsweep_fine, nsweep_coarse, int(bool(residual_check)))
         self.ws = Workspace()
+        self.adj_ws = Workspace()
         self.nbytes = lib().mlsdc_workspace_bytes(fine.h, coarse.h if coarse else None, ctypes.byref(self.opts))
+
+    def step_adj(self, dt, theta_n, lam_np1, lam_n=None):
+        """Transpose of the step's Jacobian at theta_n applied to lam_np1 (recomputes the step)."""
+        import torch
+        n = 3 * self.fine.plan.nspec
+        _need(theta_n, torch.complex128, n, "theta_n")
+        _need(lam_np1, torch.complex128, n, "lam_np1")
+        if lam_n is None:
+            lam_n = torch.empty_like(lam_np1)
+        _need(lam_n, torch.complex128, n, "lam_n")
+        nb = lib().mlsdc_adj_workspace_bytes(self.fine.h, self.coarse.h if self.coarse else None,
+                                             ctypes.byref(self.opts))
+        w = self.adj_ws.get(nb)
+        _check(lib().mlsdc_step_adj(self.fine.h, self.coarse.h if self.coarse else None, ctypes.byref(self.opts),
+                                    float(dt), _ptr(theta_n), _ptr(lam_np1), _ptr(lam_n), _ptr(w), nb, _stream()),
+               "mlsdc_step_adj")
+        return lam_n
 
     def step(self, dt, theta_n, theta_np1=None, status=None):
         import torch
@@ -306,3 +390,68 @@ class Stepper:
                                 float(dt), _ptr(theta_n), _ptr(theta_np1), _ptr(status), _ptr(w), self.nbytes,
                                 _stream()), "mlsdc_step")
         return theta_np1
+
+
+def _autograd():
+    import torch
+
+    class MLSDCIntegrate(torch.autograd.Function):
+        """Theta(T) after `nsteps` MLSDC steps from theta0; the backward pass
+        runs the hand-written adjoint step by step from per-step checkpoints."""
+
+        @staticmethod
+        def forward(ctx, theta0, stepper, dt, nsteps):
+            ckpt = [theta0.detach().contiguous()]
+            x = ckpt[0]
+            for _ in range(nsteps):
+                x = stepper.step(dt, x)
+                ckpt.append(x)
+            ctx.stepper, ctx.dt = stepper, dt
+            ctx.ckpt = ckpt[:-1]
+            return x.clone()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            lam = grad_out.contiguous()
+            for x in reversed(ctx.ckpt):
+                lam = ctx.stepper.step_adj(ctx.dt, x, lam)
+            return lam, None, None, None
+
+    class SHInverse(torch.autograd.Function):
+        """sh_inverse with its transpose as the backward pass."""
+
+        @staticmethod
+        def forward(ctx, spec, plan):
+            ctx.plan = plan
+            return plan.inverse(spec.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            return ctx.plan.inverse_adj(g.contiguous()), None
+
+    class SHForward(torch.autograd.Function):
+        """sh_forward with its transpose as the backward pass."""
+
+        @staticmethod
+        def forward(ctx, grid, plan):
+            ctx.plan = plan
+            return plan.forward(grid.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            return ctx.plan.forward_adj(g.contiguous()), None
+
+    return MLSDCIntegrate, SHInverse, SHForward
+
+
+def integrate(theta0, stepper, dt, nsteps):
+    """Differentiable MLSDC integration (torch.autograd)."""
+    return _autograd()[0].apply(theta0, stepper, dt, nsteps)
+
+
+def sh_inverse_fn(spec, plan):
+    return _autograd()[1].apply(spec, plan)
+
+
+def sh_forward_fn(grid, plan):
+    return _autograd()[2].apply(grid, plan)

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmlsdc_sh.so")
-HIP_SOURCES = ["legendre.hip", "legendre_mixed.hip", "fourier.hip", "spectral.hip", "api.hip"]
+HIP_SOURCES = ["legendre.hip", "legendre_mixed.hip", "fourier.hip", "spectral.hip", "adjoint.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -1,0 +1,585 @@
+// Adjoint (transposed-Jacobian) kernels of the MLSDC-SH step, FP64.
+//
+// Inner products: spectral arrays <x, y> = sum over the stored (m >= 0)
+// coefficients of Re x Re y + Im x Im y; grids <g, h> = sum_ij g_ij h_ij.
+// With these, for the transforms of Sec. 3 (eqs. spectral_to_physical_space,
+// fourier_transform, legendre_transform):
+//   synthesis S:  (S^T h)^m_n = c_m sum_j P^m_n(mu_j) sum_i h_ij e^{-i m lambda_i},
+//                 c_0 = 1, c_m = 2 (m >= 1);
+//   analysis A_W: (A_W^T s)_ij = (W_j / I) sum_{m >= 0} Re[(sum_n s^m_n P^m_n(mu_j)) e^{i m lambda_i}],
+// i.e. the analysis adjoint is a synthesis of the coefficients with those of
+// m >= 1 halved.  The tendency adjoint runs: combine^T (div/curl/Laplacian),
+// halving, Legendre synthesis of the cotangents, per latitude row the inverse
+// FFTs of state and cotangents, the linearised products^T, forward FFTs with
+// the factor c_m, the Legendre analysis with unit weights, and the wind^T
+// (Helmholtz) and F_I^T.  The step-level kernels transpose the linear parts of
+// the sweep node update, the FAS term and the space-time transfers.
+#include "internal.h"
+
+namespace {
+
+constexpr int TB = 256;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 caxpy(double s, double2 a, double2 y) {
+    return make_double2(fma(s, a.x, y.x), fma(s, a.y, y.y));
+}
+// i * m * a
+__device__ __forceinline__ double2 cim(double m, double2 a) { return make_double2(-m * a.y, m * a.x); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+inline unsigned nblocks(long long n) { return (unsigned)((n + TB - 1) / TB); }
+
+// Transpose of the combine step (F_E from the weighted analyses), then the
+// halving of m >= 1 that turns the analysis adjoint into a synthesis:
+// lam5[s][e][0..4] = adjoints of (A, B, C, D, E)^ at ext entry e.
+__global__ void k_combine_adj(const int* __restrict__ ord_e, const int* __restrict__ deg_e,
+                              const double2* __restrict__ lfe, double2* __restrict__ lam5, int N,
+                              long long nspec, long long nspec_e, double a, int S) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (e >= nspec_e || s >= S) return;
+    const int m = ord_e[e], n = deg_e[e];
+    const double2* lp = lfe + (long long)s * 3 * nspec;   // cotangent of F_E,Phi
+    const double2* lz = lp + nspec;                        // F_E,zeta
+    const double2* ld = lz + nspec;                        // F_E,delta
+    const double2 z = make_double2(0.0, 0.0);
+    auto get = [&](const double2* x, int k) { return (k >= m && k <= N) ? x[spec_idx(N, m, k)] : z; };
+    const double ia = 1.0 / a;
+    const double cdn = (n - 1.0) * eps_nm(n, m), cup = (n + 2.0) * eps_nm(n + 1, m);
+    // div(X, Y) with cotangent q: X_n += -i m q_n / a; Y_n += [(n-1) eps_n q_{n-1} - (n+2) eps_{n+1} q_{n+1}] / a
+    // curl(X, Y) with cotangent r: Y_n += -i m r_n / a; X_n += [-(n-1) eps_n r_{n-1} + (n+2) eps_{n+1} r_{n+1}] / a
+    // F_E = [-div(C, D), -div(A, B), curl(A, B) + L E^]: q_AB = -lz, q_CD = -lp, r_AB = ld
+    const double2 qab0 = cscale(-1.0, get(lz, n)), qabd = cscale(-1.0, get(lz, n - 1)),
+                  qabu = cscale(-1.0, get(lz, n + 1));
+    const double2 qcd0 = cscale(-1.0, get(lp, n)), qcdd = cscale(-1.0, get(lp, n - 1)),
+                  qcdu = cscale(-1.0, get(lp, n + 1));
+    const double2 r0 = get(ld, n), rd = get(ld, n - 1), ru = get(ld, n + 1);
+    double2 A = cim(-m, qab0);
+    A = caxpy(-cdn, rd, A);
+    A = caxpy(cup, ru, A);
+    double2 B = cim(-m, r0);
+    B = caxpy(cdn, qabd, B);
+    B = caxpy(-cup, qabu, B);
+    double2 C = cim(-m, qcd0);
+    double2 D = make_double2(0.0, 0.0);
+    D = caxpy(cdn, qcdd, D);
+    D = caxpy(-cup, qcdu, D);
+    const double L = n * (n + 1.0) / (a * a);
+    double2 E = (n <= N) ? cscale(L, r0) : z;
+    const double hm = (m == 0) ? ia : 0.5 * ia;             // 1/a and the halving for m >= 1
+    double2* o = lam5 + ((long long)s * nspec_e + e) * 5;
+    o[0] = cscale(hm, A);
+    o[1] = cscale(hm, B);
+    o[2] = cscale(hm, C);
+    o[3] = cscale(hm, D);
+    o[4] = cscale(m == 0 ? 1.0 : 0.5, E);
+}
+
+// Transpose of the wind coefficients and of F_I, accumulated into lam_state:
+// lam4[s][e] holds the adjoints of the synthesised (zeta, Phi', U, V) coefficients.
+__global__ void k_prep_adj(const int* __restrict__ ord, const int* __restrict__ deg,
+                           const double2* __restrict__ lam4, const double2* __restrict__ lfi,
+                           double2* __restrict__ lstate, int N, long long nspec, long long nspec_e, swe_params p,
+                           int S, int has_fe) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= nspec || s >= S) return;
+    const int m = ord[i], n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    double2 lphi = make_double2(0.0, 0.0), lzeta = lphi, ldelta = lphi;
+    if (has_fe) {
+        const double2* l4 = lam4 + (long long)s * nspec_e * 4;
+        const double2 z = make_double2(0.0, 0.0);
+        auto g4 = [&](int k, int f) { return (k >= m && k <= N + 1) ? l4[ext_idx(N, m, k) * 4 + f] : z; };
+        const double ia = 1.0 / p.a;
+        const double cu = n * eps_nm(n + 1, m), cd = (n + 1.0) * eps_nm(n, m);
+        // psi_n appears in U_{n+1} (n eps_{n+1}), U_{n-1} (-(n+1) eps_n), V_n (i m)
+        double2 lpsi = cim(-m, g4(n, 3));
+        lpsi = caxpy(cu, g4(n + 1, 2), lpsi);
+        lpsi = caxpy(-cd, g4(n - 1, 2), lpsi);
+        // chi_n appears in U_n (i m), V_{n+1} (-n eps_{n+1}), V_{n-1} ((n+1) eps_n)
+        double2 lchi = cim(-m, g4(n, 2));
+        lchi = caxpy(-cu, g4(n + 1, 3), lchi);
+        lchi = caxpy(cd, g4(n - 1, 3), lchi);
+        lpsi = cscale(ia, lpsi);
+        lchi = cscale(ia, lchi);
+        lzeta = g4(n, 0);
+        lphi = g4(n, 1);
+        if (n >= 1) {
+            lzeta = caxpy(-1.0 / L, lpsi, lzeta);          // psi = -zeta / L
+            ldelta = caxpy(-1.0 / L, lchi, ldelta);        // chi = -delta / L
+        }
+    }
+    if (lfi) {
+        // F_I = [-Phibar delta - nu L Phi', -nu L zeta, L Phi' - nu L delta]
+        const double2* l = lfi + (long long)s * 3 * nspec;
+        const double2 a0 = l[i], a1 = l[nspec + i], a2 = l[2 * nspec + i];
+        lphi = caxpy(-p.nu * L, a0, lphi);
+        lphi = caxpy(L, a2, lphi);
+        lzeta = caxpy(-p.nu * L, a1, lzeta);
+        ldelta = caxpy(-p.phibar, a0, ldelta);
+        ldelta = caxpy(-p.nu * L, a2, ldelta);
+    }
+    double2* o = lstate + (long long)s * 3 * nspec;
+    o[i] = cadd(o[i], lphi);
+    o[nspec + i] = cadd(o[nspec + i], lzeta);
+    o[2 * nspec + i] = cadd(o[2 * nspec + i], ldelta);
+}
+
+// ------------------------------------------------------------ row FFTs (LDS)
+template <int R>
+__device__ __forceinline__ void dft(double2* v, double sg);
+template <>
+__device__ __forceinline__ void dft<2>(double2* v, double) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+template <>
+__device__ __forceinline__ void dft<4>(double2* v, double sg) {
+    const double2 s0 = cadd(v[0], v[2]), s1 = csub(v[0], v[2]), s2 = cadd(v[1], v[3]), s3 = csub(v[1], v[3]);
+    const double2 r3 = make_double2(-sg * s3.y, sg * s3.x);
+    v[0] = cadd(s0, s2);
+    v[2] = csub(s0, s2);
+    v[1] = cadd(s1, r3);
+    v[3] = csub(s1, r3);
+}
+template <>
+__device__ __forceinline__ void dft<3>(double2* v, double sg) {
+    const double c = 0.86602540378443864676;
+    const double2 t = cadd(v[1], v[2]), d = csub(v[1], v[2]), a = v[0];
+    const double2 mm = make_double2(a.x - 0.5 * t.x, a.y - 0.5 * t.y);
+    const double2 r = make_double2(-sg * c * d.y, sg * c * d.x);
+    v[0] = cadd(a, t);
+    v[1] = cadd(mm, r);
+    v[2] = csub(mm, r);
+}
+__device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half) {
+    const double2 w = tws[idx < half ? idx : idx - half];
+    return idx < half ? w : make_double2(-w.x, -w.y);
+}
+// In-LDS Stockham stages (same scheme as the forward transforms).
+template <int L, int T, int NR, int Ns>
+__device__ __forceinline__ void fft_stages(double2* buf, const double2* tw, double sg) {
+    constexpr int rem = L / Ns;
+    if constexpr (rem > 1) {
+        constexpr int R = (rem % 4 == 0) ? 4 : ((rem % 2 == 0) ? 2 : 3);
+        constexpr int NB = L / R, ITEMS = NR * NB, IPT = (ITEMS + T - 1) / T, TWS = L / (Ns * R) * 2;
+        double2 v[IPT][R];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = threadIdx.x + it * T;
+            if (ITEMS % T == 0 || item < ITEMS) {
+                const int row = item / NB, j = item - row * NB, k = j % Ns;
+                const double2* b = buf + row * L;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double2 x = b[j + r * NB];
+                    if (Ns > 1 && r > 0) {
+                        double2 w = tw_half(tw, r * k * TWS, L);
+                        w.y *= -sg;
+                        x = cmul(x, w);
+                    }
+                    v[it][r] = x;
+                }
+                dft<R>(v[it], sg);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = threadIdx.x + it * T;
+            if (ITEMS % T == 0 || item < ITEMS) {
+                const int row = item / NB, j = item - row * NB, k = j % Ns;
+                const int base = (j / Ns) * Ns * R + k;
+                double2* b = buf + row * L;
+#pragma unroll
+                for (int q = 0; q < R; ++q) b[base + q * Ns] = v[it][q];
+            }
+        }
+        __syncthreads();
+        fft_stages<L, T, NR, Ns * R>(buf, tw, sg);
+    }
+}
+template <int L>
+struct AdjCfg {
+    static constexpr int L2 = L / 2;
+    static constexpr int T0 = L2 / 2 < 64 ? 64 : (L2 / 2 > 1024 ? 1024 : L2 / 2);
+    static constexpr int T = (T0 + 63) / 64 * 64;
+};
+template <int L, class Coef>
+__device__ __forceinline__ void pack_synthesis(double2* row, const double2* tw, int N, Coef coef) {
+    constexpr int L2 = L / 2, T = AdjCfg<L>::T;
+    for (int m = threadIdx.x; m < L2; m += T) {
+        double2 A = make_double2(0.0, 0.0), B = A;
+        if (m <= N) A = coef(m);
+        if (m == 0) A.y = 0.0;
+        const int j = L2 - m;
+        if (m > 0 && j <= N) {
+            const double2 x = coef(j);
+            B = make_double2(x.x, -x.y);
+        }
+        const double2 s = cadd(A, B), d = csub(A, B);
+        const double2 e = make_double2(tw[m].x, -tw[m].y);
+        const double2 ed = cmul(e, d);
+        row[m] = make_double2(s.x - ed.y, s.y + ed.x);
+    }
+}
+template <int L>
+__device__ __forceinline__ double2 unpack_analysis(const double2* row, const double2* tw, int m) {
+    constexpr int L2 = L / 2;
+    const double2 z = row[m], zc = row[(L2 - m) % L2];
+    const double2 E = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+    const double2 O = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    return cadd(E, cmul(tw[m], O));
+}
+
+// Tendency adjoint, grid part: one workgroup per (latitude row j, state s).
+// FIs[s]: [2][Jh][N+1][4] state (zeta, Phi', U, V); FIl[s]: [2][Jh][N+1][5]
+// cotangents of (A, B, C, D, E)^ after combine^T and halving.  Output
+// Ga[s][j][m][4] = c_m * DFT_m of the grid cotangents of (zeta, Phi', U, V).
+template <int L>
+__global__ __launch_bounds__(AdjCfg<L>::T) void k_swe_grid_adj(const double2* __restrict__ FIs,
+                                                               const double2* __restrict__ FIl,
+                                                               const double2* __restrict__ tw,
+                                                               const double* __restrict__ mu,
+                                                               const double* __restrict__ cos2,
+                                                               const double* __restrict__ w,
+                                                               double2* __restrict__ Ga, int N, int J,
+                                                               double two_omega) {
+    constexpr int L2 = L / 2, T = AdjCfg<L>::T;
+    __shared__ double2 lds[9 * L2];
+    __shared__ double2 tws[L2];
+    for (int t = threadIdx.x; t < L2; t += T) tws[t] = tw[t];
+    __syncthreads();
+    const int j = blockIdx.x, s = blockIdx.y;
+    const int Jh = J / 2;
+    const int jp = (j < Jh) ? j : J - 1 - j;
+    const double sgn = (j < Jh) ? 1.0 : -1.0;
+    {
+        const long long ps = (long long)Jh * (N + 1) * 4;
+        const double2* e = FIs + (long long)s * J * (N + 1) * 4 + (long long)jp * (N + 1) * 4;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            auto coef = [&](int m) {
+                const double2 a = e[(long long)m * 4 + f], b = e[(long long)m * 4 + f + ps];
+                return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
+            };
+            pack_synthesis<L>(lds + f * L2, tws, N, coef);
+        }
+    }
+    {
+        const long long ps = (long long)Jh * (N + 1) * 5;
+        const double2* e = FIl + (long long)s * J * (N + 1) * 5 + (long long)jp * (N + 1) * 5;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            auto coef = [&](int m) {
+                const double2 a = e[(long long)m * 5 + f], b = e[(long long)m * 5 + f + ps];
+                return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
+            };
+            pack_synthesis<L>(lds + (4 + f) * L2, tws, N, coef);
+        }
+    }
+    __syncthreads();
+    fft_stages<L2, T, 9, 1>(lds, tws, 1.0);
+    const double fc = two_omega * mu[j];
+    const double ic2 = 1.0 / cos2[j];
+    const double wv = w[j] / (L * cos2[j]), we = w[j] / L;
+    for (int k = threadIdx.x; k < L2; k += T) {
+        const double2 z = lds[k], ph = lds[L2 + k], U = lds[2 * L2 + k], V = lds[3 * L2 + k];
+        const double2 lA = lds[4 * L2 + k], lB = lds[5 * L2 + k], lC = lds[6 * L2 + k], lD = lds[7 * L2 + k],
+                      lE = lds[8 * L2 + k];
+        const double2 eta = make_double2(z.x + fc, z.y + fc);
+        // A = eta U, B = eta V, C = Phi' U, D = Phi' V, E = (U^2 + V^2) / (2 cos^2 phi)
+        double2 gz, gp, gu, gv;
+        gz.x = wv * (lA.x * U.x + lB.x * V.x);
+        gz.y = wv * (lA.y * U.y + lB.y * V.y);
+        gp.x = wv * (lC.x * U.x + lD.x * V.x);
+        gp.y = wv * (lC.y * U.y + lD.y * V.y);
+        gu.x = wv * (lA.x * eta.x + lC.x * ph.x) + we * lE.x * U.x * ic2;
+        gu.y = wv * (lA.y * eta.y + lC.y * ph.y) + we * lE.y * U.y * ic2;
+        gv.x = wv * (lB.x * eta.x + lD.x * ph.x) + we * lE.x * V.x * ic2;
+        gv.y = wv * (lB.y * eta.y + lD.y * ph.y) + we * lE.y * V.y * ic2;
+        lds[k] = gz;
+        lds[L2 + k] = gp;
+        lds[2 * L2 + k] = gu;
+        lds[3 * L2 + k] = gv;
+    }
+    __syncthreads();
+    fft_stages<L2, T, 4, 1>(lds, tws, -1.0);
+    double2* out = Ga + ((long long)s * J + j) * (N + 1) * 4;
+    for (int m = threadIdx.x; m <= N; m += T) {
+        const double c = (m == 0) ? 1.0 : 2.0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const double2 X = unpack_analysis<L>(lds + f * L2, tws, m);
+            out[(long long)m * 4 + f] = cscale(c, X);
+        }
+    }
+}
+
+// Transposed implicit solve: lam_b = (I - h F_I)^{-T} lam_x per coefficient.
+__device__ __forceinline__ void solve_adj_one(double L, double h, const swe_params& p, double2 lp, double2 lz,
+                                              double2 ld, double2& yp, double2& yz, double2& yd) {
+    const double c = 1.0 + h * p.nu * L;
+    const double det = c * c + h * h * p.phibar * L;
+    yp = make_double2((c * lp.x + h * L * ld.x) / det, (c * lp.y + h * L * ld.y) / det);
+    yd = make_double2((c * ld.x - h * p.phibar * lp.x) / det, (c * ld.y - h * p.phibar * lp.y) / det);
+    yz = make_double2(lz.x / c, lz.y / c);
+}
+
+__global__ void k_imex_solve_adj(const int* __restrict__ deg, const double2* lx, double2* lb, long long nspec,
+                                 swe_params p, double h, int S) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= nspec || s >= S) return;
+    const int n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    const double2* x = lx + (long long)s * 3 * nspec;
+    double2* b = lb + (long long)s * 3 * nspec;
+    double2 yp, yz, yd;
+    solve_adj_one(L, h, p, x[i], x[nspec + i], x[2 * nspec + i], yp, yz, yd);
+    b[i] = yp;
+    b[nspec + i] = yz;
+    b[2 * nspec + i] = yd;
+}
+
+// Transpose of one sweep node update (node m+1) given lth[m+1] (already
+// including the tendency adjoint at that node): lam_b = solve^T(lth[m+1]),
+// lth[m+1] = 0, and lam_b is spread over the inputs of the quadrature.
+__global__ void k_sdc_node_adj(const int* __restrict__ deg, long long nspec, swe_params p, int m, int M,
+                               NodeWeights wt, double h, double2* __restrict__ lth, double2* __restrict__ lfi_new,
+                               double2* __restrict__ lfe_new, double2* __restrict__ lfi_in,
+                               double2* __restrict__ lfe_in, double2* __restrict__ ltau) {
+    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
+    if (i >= nspec) return;
+    const long long ns3 = 3 * nspec;
+    const int n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    double2* t = lth + (m + 1) * ns3;
+    double2 lb[3];
+    solve_adj_one(L, h, p, t[i], t[nspec + i], t[2 * nspec + i], lb[0], lb[1], lb[2]);
+    const double2 z = make_double2(0.0, 0.0);
+    t[i] = z;
+    t[nspec + i] = z;
+    t[2 * nspec + i] = z;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const long long o = c * nspec + i;
+        const double2 b = lb[c];
+        lth[o] = cadd(lth[o], b);
+        for (int j = 0; j <= M; ++j) {
+            lfi_in[j * ns3 + o] = caxpy(wt.q[j], b, lfi_in[j * ns3 + o]);
+            lfe_in[j * ns3 + o] = caxpy(wt.q[j], b, lfe_in[j * ns3 + o]);
+        }
+        for (int j = 1; j <= m; ++j) {
+            lfe_new[j * ns3 + o] = caxpy(wt.qe[j], b, lfe_new[j * ns3 + o]);
+            lfe_in[j * ns3 + o] = caxpy(-wt.qe[j], b, lfe_in[j * ns3 + o]);
+            lfi_new[j * ns3 + o] = caxpy(wt.qd[j], b, lfi_new[j * ns3 + o]);
+            lfi_in[j * ns3 + o] = caxpy(-wt.qd[j], b, lfi_in[j * ns3 + o]);
+        }
+        lfi_in[(m + 1) * ns3 + o] = caxpy(-h, b, lfi_in[(m + 1) * ns3 + o]);
+        if (ltau) ltau[(m + 1) * ns3 + o] = cadd(ltau[(m + 1) * ns3 + o], b);
+    }
+}
+
+// lf[j][map(c)] += sum_{i0 <= i < i1} Pi[i][j] lc[i][c]   (restriction^T = zero padding)
+__global__ void k_restrict_adj(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, long long nsf,
+                               long long nsc, Mat9x9 Pi, int nsrc, int i0, int i1, const double2* __restrict__ lc,
+                               double2* __restrict__ lf) {
+    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    if (c >= nsc) return;
+    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+    for (int f = 0; f < 3; ++f)
+        for (int j = 0; j < nsrc; ++j) {
+            double2 acc = lf[(j * 3 + f) * nsf + fidx];
+            for (int i = i0; i < i1; ++i) acc = caxpy(Pi.a[i * nsrc + j], lc[(i * 3 + f) * nsc + c], acc);
+            lf[(j * 3 + f) * nsf + fidx] = acc;
+        }
+}
+
+// Transpose of step D for Theta, F_I, F_E: for coarse node i,
+// q = sum_{m >= 1} Pfc[m][i] D(lf[m]); lc[i] += q; lct[i] -= q.
+__global__ void k_interp_adj(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, long long nsf,
+                             long long nsc, Mat9x9 P, int nf, int nc, const double2* __restrict__ lthf,
+                             const double2* __restrict__ lfif, const double2* __restrict__ lfef,
+                             double2* __restrict__ lthc, double2* __restrict__ lthct, double2* __restrict__ lfic,
+                             double2* __restrict__ lfict, double2* __restrict__ lfec, double2* __restrict__ lfect) {
+    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    if (c >= nsc) return;
+    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+    for (int f = 0; f < 3; ++f)
+        for (int i = 0; i < nc; ++i) {
+            double2 a = make_double2(0.0, 0.0), b = a, d = a;
+            for (int m = 1; m < nf; ++m) {
+                const double wgt = P.a[m * nc + i];
+                const long long o = (m * 3 + f) * nsf + fidx;
+                a = caxpy(wgt, lthf[o], a);
+                b = caxpy(wgt, lfif[o], b);
+                d = caxpy(wgt, lfef[o], d);
+            }
+            const long long o = (i * 3 + f) * nsc + c;
+            lthc[o] = cadd(lthc[o], a);
+            lthct[o] = csub(lthct[o], a);
+            lfic[o] = cadd(lfic[o], b);
+            lfict[o] = csub(lfict[o], b);
+            lfec[o] = cadd(lfec[o], d);
+            lfect[o] = csub(lfect[o], d);
+        }
+}
+
+// Transpose of the FAS term: lfi_f[j], lfe_f[j] += dt Pad(sum_i PQ[i][j] ltau[i]);
+// lfi_c[j], lfe_c[j] -= dt sum_i Qc[i][j] ltau[i].
+__global__ void k_fas_tau_adj(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, long long nsf,
+                              long long nsc, Mat9x9 PQ, Mat9x9 Qc, int nf, int nc, double dt,
+                              const double2* __restrict__ ltau, double2* __restrict__ lfif,
+                              double2* __restrict__ lfef, double2* __restrict__ lfic, double2* __restrict__ lfec) {
+    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    if (c >= nsc) return;
+    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+    for (int f = 0; f < 3; ++f) {
+        for (int j = 0; j < nf; ++j) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int i = 0; i < nc; ++i) acc = caxpy(PQ.a[i * nf + j], ltau[(i * 3 + f) * nsc + c], acc);
+            const long long o = (j * 3 + f) * nsf + fidx;
+            lfif[o] = caxpy(dt, acc, lfif[o]);
+            lfef[o] = caxpy(dt, acc, lfef[o]);
+        }
+        for (int j = 0; j < nc; ++j) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int i = 0; i < nc; ++i) acc = caxpy(Qc.a[i * nc + j], ltau[(i * 3 + f) * nsc + c], acc);
+            const long long o = (j * 3 + f) * nsc + c;
+            lfic[o] = caxpy(-dt, acc, lfic[o]);
+            lfec[o] = caxpy(-dt, acc, lfec[o]);
+        }
+    }
+}
+
+// y[e] (+)= sum_{m = 0}^{nn-1} x[m][e]  (node sums), acc != 0 adds to y.
+__global__ void k_node_sum(const double2* __restrict__ x, double2* __restrict__ y, long long n3, int nn, int acc) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e >= n3) return;
+    double2 s = acc ? y[e] : make_double2(0.0, 0.0);
+    for (int m = 0; m < nn; ++m) s = cadd(s, x[m * n3 + e]);
+    y[e] = s;
+}
+
+// y += x (elementwise over n complex values).
+__global__ void k_add(const double2* __restrict__ x, double2* __restrict__ y, long long n) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e < n) y[e] = cadd(y[e], x[e]);
+}
+
+// x = 0 over n complex values (a kernel, usable under graph capture).
+__global__ void k_zero(double2* __restrict__ x, long long n) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e < n) x[e] = make_double2(0.0, 0.0);
+}
+
+template <int L>
+hipError_t grid_adj_t(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S, double omega,
+                      hipStream_t st) {
+    dim3 g(pl->J, S);
+    k_swe_grid_adj<L><<<g, AdjCfg<L>::T, 0, st>>>(FIs, FIl, pl->tw, pl->mu, pl->cos2, pl->w, Ga, pl->N, pl->J,
+                                                   2.0 * omega);
+    return hipGetLastError();
+}
+
+#define SHX_ADJ_LENGTHS(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(48) X(96) X(192) X(384) X(768) X(1536)
+
+}  // namespace
+
+bool adjoint_length_supported(int L) {
+    switch (L) {
+#define CASE(n) case n:
+        SHX_ADJ_LENGTHS(CASE)
+#undef CASE
+        return true;
+        default: return false;
+    }
+}
+
+hipError_t launch_combine_adj(const shx_plan* pl, double a, const double2* lfe, double2* lam5, int S,
+                              hipStream_t st) {
+    dim3 g(nblocks(pl->nspec_e), S);
+    k_combine_adj<<<g, TB, 0, st>>>(pl->ord_e, pl->deg_e, lfe, lam5, pl->N, pl->nspec, pl->nspec_e, a, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double2* lam4, const double2* lfi,
+                           double2* lstate, int S, int has_fe, hipStream_t st) {
+    dim3 g(nblocks(pl->nspec), S);
+    k_prep_adj<<<g, TB, 0, st>>>(pl->ord, pl->deg, lam4, lfi, lstate, pl->N, pl->nspec, pl->nspec_e, p, S, has_fe);
+    return hipGetLastError();
+}
+
+hipError_t launch_swe_grid_adj(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S,
+                               double omega, hipStream_t st) {
+    switch (pl->I) {
+#define CASE(n) case n: return grid_adj_t<n>(pl, FIs, FIl, Ga, S, omega, st);
+        SHX_ADJ_LENGTHS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_imex_solve_adj(const shx_plan* pl, const swe_params& p, double h, const double2* lx,
+                                 double2* lb, int S, hipStream_t st) {
+    dim3 g(nblocks(pl->nspec), S);
+    k_imex_solve_adj<<<g, TB, 0, st>>>(pl->deg, lx, lb, pl->nspec, p, h, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_sdc_node_adj(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wt,
+                               double h, double2* lth, double2* lfi_new, double2* lfe_new, double2* lfi_in,
+                               double2* lfe_in, double2* ltau, hipStream_t st) {
+    k_sdc_node_adj<<<nblocks(pl->nspec), TB, 0, st>>>(pl->deg, pl->nspec, p, m, M, wt, h, lth, lfi_new, lfe_new,
+                                                       lfi_in, lfe_in, ltau);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc, int i0,
+                               int i1, const double2* lc, double2* lf, hipStream_t st) {
+    k_restrict_adj<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
+                                                           coarse->nspec, Pi, nsrc, i0, i1, lc, lf);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pfc, int nf, int nc,
+                             const double2* lthf, const double2* lfif, const double2* lfef, double2* lthc,
+                             double2* lthct, double2* lfic, double2* lfict, double2* lfec, double2* lfect,
+                             hipStream_t st) {
+    k_interp_adj<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
+                                                         coarse->nspec, Pfc, nf, nc, lthf, lfif, lfef, lthc, lthct,
+                                                         lfic, lfict, lfec, lfect);
+    return hipGetLastError();
+}
+
+hipError_t launch_fas_tau_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ, const Mat9x9& Qc,
+                              int nf, int nc, double dt, const double2* ltau, double2* lfif, double2* lfef,
+                              double2* lfic, double2* lfec, hipStream_t st) {
+    k_fas_tau_adj<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
+                                                          coarse->nspec, PQ, Qc, nf, nc, dt, ltau, lfif, lfef, lfic,
+                                                          lfec);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_sum(const double2* x, double2* y, long long n3, int nn, int acc, hipStream_t st) {
+    k_node_sum<<<nblocks(n3), TB, 0, st>>>(x, y, n3, nn, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const double2* x, double2* y, long long n, hipStream_t st) {
+    k_add<<<nblocks(n), TB, 0, st>>>(x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double2* x, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_zero<<<nblocks(n), TB, 0, st>>>(x, n);
+    return hipGetLastError();
+}

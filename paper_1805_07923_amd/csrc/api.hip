@@ -119,7 +119,8 @@ int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double
 // fe_new); Theta is updated in place (node 0 read only).  Node 0 of the new
 // buffers is not touched.
 int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_old, const double2* fe_old,
-               double2* fi_new, double2* fe_new, const double2* tau, const TendWS& t, hipStream_t st) {
+               double2* fi_new, double2* fe_new, const double2* tau, const TendWS& t, hipStream_t st,
+               double2* rec = nullptr) {
     const shx_plan* pl = lv->plan;
     const int M = lv->nnodes - 1, n1 = lv->nnodes;
     const size_t ns3 = 3 * (size_t)pl->nspec;
@@ -138,6 +139,7 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
         const size_t o = (size_t)(m + 1) * ns3;
         int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st);
         if (rc) return rc;
+        if (rec) HIPCHK(hipMemcpyAsync(rec + (size_t)m * ns3, th + o, ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
     }
     return SHX_OK;
 }
@@ -253,6 +255,246 @@ bool convert_tables(shx_plan* p) {
     (void)hipFree(p->pan);
     p->psyn = p->pan = nullptr;
     return ok;
+}
+
+}  // namespace
+
+// Tape of the states at which F is evaluated during a step (fine and
+// coarse, in evaluation order), for the adjoint.
+struct Tape {
+    double2* f;
+    double2* c;
+};
+size_t tape_fine_states(const sdc_level* fl, const mlsdc_opts* o) {
+    return 1 + (size_t)o->niter * o->nsweep_fine * (fl->nnodes - 1);
+}
+size_t tape_coarse_states(const sdc_level* cl, const mlsdc_opts* o) {
+    return cl ? 1 + (size_t)o->niter * (cl->nnodes - 1) * (1 + o->nsweep_coarse) : 0;
+}
+
+// One MLSDC step (validated arguments); optionally records the tape.
+int step_body(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, double dt, const double2* th_n,
+              double2* out, double* status, const StepWS& w, const Tape* tape, hipStream_t st) {
+    const shx_plan* pf = fl->plan;
+    const int Mf = fl->nnodes - 1;
+    const size_t nsf3 = 3 * (size_t)pf->nspec;
+    // spread: Theta and F at every fine node equal those of Theta^n
+    HIPCHK(hipMemcpyAsync(w.thf, th_n, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    int rc = tendency_impl(pf, fl->p, 1, w.thf, w.fif[0], w.fef[0], w.tf, st);
+    if (rc) return rc;
+    if (tape) HIPCHK(hipMemcpyAsync(tape->f, th_n, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    {
+        NodeCopies nc{};
+        nc.add(w.thf, w.thf, 1, Mf);
+        nc.add(w.fif[0], w.fif[0], 1, Mf);
+        nc.add(w.fef[0], w.fef[0], 1, Mf);
+        nc.add(w.fif[0], w.fif[1], 0, 0);
+        nc.add(w.fef[0], w.fef[1], 0, 0);
+        HIPCHK(launch_node_copies(nc, (long long)nsf3, st));
+    }
+    int fcur = 0;                                        // fine F buffer holding the current iterate
+    Mat9x9 Pcf{}, Pfc{}, PQ{}, Qc{};
+    int Mc = 0;
+    size_t nsc3 = 0;
+    const shx_plan* pc = cl ? cl->plan : nullptr;
+    if (cl) {
+        Mc = cl->nnodes - 1;
+        nsc3 = 3 * (size_t)pc->nspec;
+        double a[81], b[81];
+        if (shx_host_transfer(fl->kind, fl->nnodes, cl->nnodes, a)) return SHX_EINVAL;   // [nc][nf]
+        if (shx_host_transfer(fl->kind, cl->nnodes, fl->nnodes, b)) return SHX_EINVAL;   // [nf][nc]
+        Pcf = to_mat(a, cl->nnodes * fl->nnodes);
+        Pfc = to_mat(b, fl->nnodes * cl->nnodes);
+        // Pi^c_f Q_f  [nc][nf]
+        for (int i = 0; i < cl->nnodes; ++i)
+            for (int j = 0; j < fl->nnodes; ++j) {
+                double sum = 0.0;
+                for (int k = 0; k < fl->nnodes; ++k) sum += a[i * fl->nnodes + k] * fl->Q[k * fl->nnodes + j];
+                PQ.a[i * fl->nnodes + j] = sum;
+            }
+        Qc = to_mat(cl->Q, cl->nnodes * cl->nnodes);
+        // coarse node 0: restricted initial value and its F, once per step
+        Mat9x9 e0{};
+        e0.a[0] = 1.0;
+        HIPCHK(launch_restrict(pf, pc, e0, 1, 0, 1, th_n, w.thc, w.thct, st));
+        rc = tendency_impl(pc, cl->p, 1, w.thct, w.fict, w.fect, w.tc, st);
+        if (rc) return rc;
+        if (tape) HIPCHK(hipMemcpyAsync(tape->c, w.thct, nsc3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        NodeCopies nc{};
+        for (int b2 = 0; b2 < 2; ++b2) {
+            nc.add(w.fict, w.fic[b2], 0, 0);
+            nc.add(w.fect, w.fec[b2], 0, 0);
+        }
+        HIPCHK(launch_node_copies(nc, (long long)nsc3, st));
+    }
+    for (int k = 0; k < o->niter; ++k) {
+        // A) fine sweep(s), old -> new buffers
+        for (int s2 = 0; s2 < o->nsweep_fine; ++s2) {
+            double2* rec = tape ? tape->f + (1 + (size_t)(k * o->nsweep_fine + s2) * Mf) * nsf3 : nullptr;
+            rc = sweep_impl(fl, dt, w.thf, w.fif[fcur], w.fef[fcur], w.fif[1 - fcur], w.fef[1 - fcur], nullptr,
+                            w.tf, st, rec);
+            if (rc) return rc;
+            fcur = 1 - fcur;
+        }
+        if (!cl) continue;
+        // B) restrict nodes 1..Mc (kept twice: iterate and saved copy), evaluate
+        HIPCHK(launch_restrict(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.thf, w.thc, w.thct, st));
+        rc = tendency_impl(pc, cl->p, Mc, w.thct + nsc3, w.fict + nsc3, w.fect + nsc3, w.tc, st);
+        if (rc) return rc;
+        const size_t cbase = 1 + (size_t)k * (Mc + o->nsweep_coarse * Mc);
+        if (tape)
+            HIPCHK(hipMemcpyAsync(tape->c + cbase * nsc3, w.thct + nsc3, Mc * nsc3 * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, st));
+        // C) FAS correction and coarse sweep(s): the first reads the saved F
+        HIPCHK(launch_fas_tau(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.fif[fcur], w.fef[fcur], w.fict, w.fect,
+                              w.tau, st));
+        const double2 *ci = w.fict, *ce = w.fect;
+        for (int s2 = 0; s2 < o->nsweep_coarse; ++s2) {
+            double2* rec = tape ? tape->c + (cbase + Mc + (size_t)s2 * Mc) * nsc3 : nullptr;
+            rc = sweep_impl(cl, dt, w.thc, ci, ce, w.fic[s2 & 1], w.fec[s2 & 1], w.tau, w.tc, st, rec);
+            if (rc) return rc;
+            ci = w.fic[s2 & 1];
+            ce = w.fec[s2 & 1];
+        }
+        // D) interpolate the coarse corrections of Theta, F_I, F_E
+        HIPCHK(launch_interp(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.thc, w.thct, ci, w.fict, ce, w.fect, w.thf,
+                             w.fif[fcur], w.fef[fcur], st));
+    }
+    HIPCHK(hipMemcpyAsync(out, w.thf + Mf * nsf3, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (status) {
+        const int nblk = residual_blocks(pf);
+        if (o->residual_check) {
+            rc = tendency_impl(pf, fl->p, fl->nnodes, w.thf, w.rfi, w.rfe, w.tr, st);
+            if (rc) return rc;
+            HIPCHK(launch_residual(pf, to_mat(fl->Q, fl->nnodes * fl->nnodes), Mf, dt, w.thf, w.rfi, w.rfe,
+                                   w.partial, nblk, st));
+        }
+        HIPCHK(launch_status(pf, w.partial, nblk, Mf, out, status, o->residual_check, st));
+    }
+    return SHX_OK;
+}
+
+namespace {
+
+// ------------------------------------------------------------------ adjoint
+// Workspace of the tendency adjoint for S states.
+struct TendAdjWS {
+    double2 *cin4, *FIs, *lam5, *FIl, *Ga, *lam4;
+};
+TendAdjWS carve_tadj(Carve& c, const shx_plan* pl, int S) {
+    TendAdjWS t;
+    const size_t fj = (size_t)S * pl->J * (pl->N + 1);
+    t.cin4 = c.take<double2>((size_t)S * pl->nspec_e * 4);
+    t.FIs = c.take<double2>(fj * 4);
+    t.lam5 = c.take<double2>((size_t)S * pl->nspec_e * 5);
+    t.FIl = c.take<double2>(fj * 5);
+    t.Ga = c.take<double2>(fj * 4);
+    t.lam4 = c.take<double2>((size_t)S * pl->nspec_e * 4);
+    return t;
+}
+
+// lstate += (dF_I/dTheta)^T lfi + (dF_E/dTheta)^T lfe, linearised at `state`.
+int tendency_adj_impl(const shx_plan* pl, const swe_params& p, int S, const double2* state, const double2* lfi,
+                      const double2* lfe, double2* lstate, const TendAdjWS& t, hipStream_t st) {
+    if (lfe) {
+        HIPCHK(launch_swe_prep(pl, p.a, state, t.cin4, S, st));
+        HIPCHK(launch_leg_syn(pl, t.cin4, t.FIs, 4, S, pl->nmax, st));
+        HIPCHK(launch_combine_adj(pl, p.a, lfe, t.lam5, S, st));
+        HIPCHK(launch_leg_syn(pl, t.lam5, t.FIl, 5, S, pl->nmax, st));
+        HIPCHK(launch_swe_grid_adj(pl, t.FIs, t.FIl, t.Ga, S, p.omega, st));
+        HIPCHK(launch_leg_an(pl, t.Ga, t.lam4, 4, S, pl->nmax, st));
+    }
+    HIPCHK(launch_prep_adj(pl, p, t.lam4, lfi, lstate, S, lfe != nullptr, st));
+    return SHX_OK;
+}
+
+// Transpose of sweep_impl.  states: the M states at which the sweep evaluated
+// F (nodes 1..M).  In: lth (adjoint of the output Theta; node 0 accumulates),
+// lfi_out/lfe_out (adjoint of the output F; used as work).  Out: lfi_in/lfe_in
+// (adjoint of the input F; must be zero on entry), ltau accumulated.
+int sweep_adj_impl(const sdc_level* lv, double dt, const double2* states, double2* lth, double2* lfi_out,
+                   double2* lfe_out, double2* lfi_in, double2* lfe_in, double2* ltau, const TendAdjWS& t,
+                   hipStream_t st) {
+    const shx_plan* pl = lv->plan;
+    const int M = lv->nnodes - 1, n1 = lv->nnodes;
+    const size_t ns3 = 3 * (size_t)pl->nspec;
+    HIPCHK(launch_add(lfi_out, lfi_in, (long long)ns3, st));      // node 0 passes through
+    HIPCHK(launch_add(lfe_out, lfe_in, (long long)ns3, st));
+    for (int m = M - 1; m >= 0; --m) {
+        const size_t o = (size_t)(m + 1) * ns3;
+        int rc = tendency_adj_impl(pl, lv->p, 1, states + (size_t)m * ns3, lfi_out + o, lfe_out + o, lth + o, t, st);
+        if (rc) return rc;
+        NodeWeights wt;
+        for (int j = 0; j < 9; ++j) {
+            const bool in = j < n1;
+            wt.q[j] = in ? dt * lv->Q[(m + 1) * n1 + j] : 0.0;
+            wt.qe[j] = in ? dt * lv->QE[(m + 1) * n1 + j] : 0.0;
+            wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
+        }
+        const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
+        HIPCHK(launch_sdc_node_adj(pl, lv->p, m, M, wt, h, lth, lfi_out, lfe_out, lfi_in, lfe_in, ltau, st));
+    }
+    return SHX_OK;
+}
+
+// Transfer matrices of a level pair: Pcf [nc][nf], Pfc [nf][nc], PQ = Pcf Q_f, Qc.
+int level_pair_matrices(const sdc_level* fl, const sdc_level* cl, Mat9x9& Pcf, Mat9x9& Pfc, Mat9x9& PQ,
+                        Mat9x9& Qc) {
+    double a[81], b[81];
+    if (shx_host_transfer(fl->kind, fl->nnodes, cl->nnodes, a)) return SHX_EINVAL;
+    if (shx_host_transfer(fl->kind, cl->nnodes, fl->nnodes, b)) return SHX_EINVAL;
+    Pcf = to_mat(a, cl->nnodes * fl->nnodes);
+    Pfc = to_mat(b, fl->nnodes * cl->nnodes);
+    std::memset(&PQ, 0, sizeof(PQ));
+    for (int i = 0; i < cl->nnodes; ++i)
+        for (int j = 0; j < fl->nnodes; ++j) {
+            double sum = 0.0;
+            for (int k = 0; k < fl->nnodes; ++k) sum += a[i * fl->nnodes + k] * fl->Q[k * fl->nnodes + j];
+            PQ.a[i * fl->nnodes + j] = sum;
+        }
+    Qc = to_mat(cl->Q, cl->nnodes * cl->nnodes);
+    return SHX_OK;
+}
+
+struct StepAdjWS {
+    StepWS fw;
+    Tape tape;
+    double2 *lthf, *lff[2][2];                 // fine: Theta, F buffers [b][fi/fe], [Mf+1][3][nsf]
+    double2 *lthc, *lthct, *lfict, *lfect, *lfc[2][2], *ltau;   // coarse [Mc+1][3][nsc]
+    double2 *lthc0, *lfic0, *lfec0;           // coarse node 0 accumulators [3][nsc]
+    double2 *lsfi, *lsfe;                     // fine node sums [3][nsf]
+    TendAdjWS tf, tc;
+};
+StepAdjWS carve_step_adj(Carve& c, const sdc_level* f, const sdc_level* cl, const mlsdc_opts* o) {
+    StepAdjWS w{};
+    mlsdc_opts fo = *o;
+    fo.residual_check = 0;
+    w.fw = carve_step(c, f, cl, &fo);
+    const size_t nf3 = 3 * (size_t)f->plan->nspec, nf = (size_t)f->nnodes * nf3;
+    w.tape.f = c.take<double2>(tape_fine_states(f, o) * nf3);
+    w.lthf = c.take<double2>(nf);
+    for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 2; ++q) w.lff[b][q] = c.take<double2>(nf);
+    w.lsfi = c.take<double2>(nf3);
+    w.lsfe = c.take<double2>(nf3);
+    w.tf = carve_tadj(c, f->plan, 1);
+    w.tape.c = nullptr;
+    if (cl) {
+        const size_t nc3 = 3 * (size_t)cl->plan->nspec, nc = (size_t)cl->nnodes * nc3;
+        w.tape.c = c.take<double2>(tape_coarse_states(cl, o) * nc3);
+        w.lthc = c.take<double2>(nc);
+        w.lthct = c.take<double2>(nc);
+        w.lfict = c.take<double2>(nc);
+        w.lfect = c.take<double2>(nc);
+        for (int b = 0; b < 2; ++b)
+            for (int q = 0; q < 2; ++q) w.lfc[b][q] = c.take<double2>(nc);
+        w.ltau = c.take<double2>(nc);
+        w.lthc0 = c.take<double2>(nc3);
+        w.lfic0 = c.take<double2>(nc3);
+        w.lfec0 = c.take<double2>(nc3);
+        w.tc = carve_tadj(c, cl->plan, cl->nnodes - 1 > 1 ? cl->nnodes - 1 : 1);
+    }
+    return w;
 }
 
 }  // namespace
@@ -447,9 +689,9 @@ int sh_inverse(const shx_plan* pl, int F, const double* spec, double* grid, void
     double2* cin = c.take<double2>((size_t)pl->nspec_e * F);
     double2* FI = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
     hipStream_t st = S(stream);
-    HIPCHK(launch_spec_to_ext(pl, reinterpret_cast<const double2*>(spec), cin, F, st));
+    HIPCHK(launch_spec_to_ext(pl, reinterpret_cast<const double2*>(spec), cin, F, 0, st));
     HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn(pl, cin, FI, F, 1, pl->N, st); }));
-    HIPCHK(launch_fft_inv(pl, FI, grid, F, st));
+    HIPCHK(launch_fft_inv(pl, FI, grid, F, 0, st));
     return SHX_OK;
 }
 
@@ -461,9 +703,186 @@ int sh_forward(const shx_plan* pl, int F, const double* grid, double* spec, void
     double2* cout = c.take<double2>((size_t)pl->nspec_e * F);
     double2* G = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
     hipStream_t st = S(stream);
-    HIPCHK(launch_fft_fwd(pl, grid, G, F, st));
+    HIPCHK(launch_fft_fwd(pl, grid, G, F, 0, st));
     HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] { return launch_leg_an(pl, G, cout, F, 1, pl->N, st); }));
     HIPCHK(launch_ext_to_spec(pl, cout, reinterpret_cast<double2*>(spec), F, st));
+    return SHX_OK;
+}
+
+size_t swe_adj_workspace_bytes(const shx_plan* pl, int nstate) {
+    if (!pl || nstate < 1) return 0;
+    Carve c{nullptr};
+    carve_tadj(c, pl, nstate);
+    return c.used;
+}
+
+int swe_tendency_adj(const shx_plan* pl, const swe_params* prm, int nst, const double* state, const double* lfi,
+                     const double* lfe, double* lstate, void* ws, size_t wsb, shx_stream_t stream) {
+    if (!pl || !valid_params(prm) || nst < 1 || !state || !lstate || !aligned16(state) || !aligned16(lfi) ||
+        !aligned16(lfe) || !aligned16(lstate) || !aligned16(ws))
+        return SHX_EINVAL;
+    if (!alias_free(pl)) return SHX_ESHAPE;
+    if (lfe && !adjoint_length_supported(pl->I)) return SHX_EUNSUPPORTED;
+    if (!ws || wsb < swe_adj_workspace_bytes(pl, nst)) return SHX_EWORKSPACE;
+    Carve c{static_cast<char*>(ws)};
+    TendAdjWS t = carve_tadj(c, pl, nst);
+    return tendency_adj_impl(pl, *prm, nst, reinterpret_cast<const double2*>(state),
+                             reinterpret_cast<const double2*>(lfi), reinterpret_cast<const double2*>(lfe),
+                             reinterpret_cast<double2*>(lstate), t, S(stream));
+}
+
+int imex_solve_adj(const shx_plan* pl, const swe_params* prm, int nst, double h, const double* lam_out,
+                   double* lam_rhs, shx_stream_t stream) {
+    if (!pl || !valid_params(prm) || nst < 1 || !lam_out || !lam_rhs || !(h >= 0.0) || !aligned16(lam_out) ||
+        !aligned16(lam_rhs))
+        return SHX_EINVAL;
+    HIPCHK(launch_imex_solve_adj(pl, *prm, h, reinterpret_cast<const double2*>(lam_out),
+                                 reinterpret_cast<double2*>(lam_rhs), nst, S(stream)));
+    return SHX_OK;
+}
+
+int sh_inverse_adj(const shx_plan* pl, int F, const double* grid_cot, double* spec_cot, void* ws, size_t wsb,
+                   shx_stream_t stream) {
+    if (!pl || F < 1 || !grid_cot || !spec_cot || !aligned16(grid_cot) || !aligned16(spec_cot)) return SHX_EINVAL;
+    if (!ws || wsb < shx_workspace_bytes(pl, F)) return SHX_EWORKSPACE;
+    Carve c{static_cast<char*>(ws)};
+    double2* cout = c.take<double2>((size_t)pl->nspec_e * F);
+    double2* G = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
+    hipStream_t st = S(stream);
+    HIPCHK(launch_fft_fwd(pl, grid_cot, G, F, 1, st));
+    HIPCHK(launch_leg_an(pl, G, cout, F, 1, pl->N, st));
+    HIPCHK(launch_ext_to_spec(pl, cout, reinterpret_cast<double2*>(spec_cot), F, st));
+    return SHX_OK;
+}
+
+int sh_forward_adj(const shx_plan* pl, int F, const double* spec_cot, double* grid_cot, void* ws, size_t wsb,
+                   shx_stream_t stream) {
+    if (!pl || F < 1 || !grid_cot || !spec_cot || !aligned16(grid_cot) || !aligned16(spec_cot)) return SHX_EINVAL;
+    if (!ws || wsb < shx_workspace_bytes(pl, F)) return SHX_EWORKSPACE;
+    Carve c{static_cast<char*>(ws)};
+    double2* cin = c.take<double2>((size_t)pl->nspec_e * F);
+    double2* FI = c.take<double2>((size_t)pl->J * (pl->N + 1) * F);
+    hipStream_t st = S(stream);
+    HIPCHK(launch_spec_to_ext(pl, reinterpret_cast<const double2*>(spec_cot), cin, F, 1, st));
+    HIPCHK(launch_leg_syn(pl, cin, FI, F, 1, pl->N, st));
+    HIPCHK(launch_fft_inv(pl, FI, grid_cot, F, 1, st));
+    return SHX_OK;
+}
+
+size_t mlsdc_adj_workspace_bytes(const sdc_level* f, const sdc_level* c, const mlsdc_opts* o) {
+    if (!f || !o) return 0;
+    Carve cv{nullptr};
+    carve_step_adj(cv, f, c, o);
+    return cv.used;
+}
+
+int mlsdc_step_adj(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, double dt, const double* theta_n,
+                   const double* lam_np1, double* lam_n, void* ws, size_t wsb, shx_stream_t stream) {
+    if (!fl || !o || !theta_n || !lam_np1 || !lam_n || !(dt > 0.0) || o->niter < 0 || o->nsweep_fine < 1 ||
+        (cl && o->nsweep_coarse < 1) || !aligned16(theta_n) || !aligned16(lam_np1) || !aligned16(lam_n) ||
+        !aligned16(ws) || lam_n == lam_np1 || lam_n == theta_n)
+        return SHX_EINVAL;
+    if (cl && (cl->kind != fl->kind || cl->plan->N >= fl->plan->N || cl->nnodes > fl->nnodes))
+        return SHX_EINVAL;
+    if (!alias_free(fl->plan) || (cl && !alias_free(cl->plan))) return SHX_ESHAPE;
+    if (!adjoint_length_supported(fl->plan->I) || (cl && !adjoint_length_supported(cl->plan->I)))
+        return SHX_EUNSUPPORTED;
+    if (!ws || wsb < mlsdc_adj_workspace_bytes(fl, cl, o)) return SHX_EWORKSPACE;
+    Carve cv{static_cast<char*>(ws)};
+    StepAdjWS w = carve_step_adj(cv, fl, cl, o);
+    hipStream_t st = S(stream);
+    const shx_plan* pf = fl->plan;
+    const int Mf = fl->nnodes - 1, nsf = o->nsweep_fine;
+    const size_t nf3 = 3 * (size_t)pf->nspec, nfa = (size_t)fl->nnodes * nf3;
+    const double2* th_n = reinterpret_cast<const double2*>(theta_n);
+    double2* lout = reinterpret_cast<double2*>(lam_n);
+    // 1. forward recompute from the checkpoint, recording the tape (output into lam_n as scratch)
+    mlsdc_opts fo = *o;
+    fo.residual_check = 0;
+    int rc = step_body(fl, cl, &fo, dt, th_n, lout, nullptr, w.fw, &w.tape, st);
+    if (rc) return rc;
+    // 2. reverse pass
+    HIPCHK(launch_zero(w.lthf, (long long)nfa, st));
+    for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 2; ++q) HIPCHK(launch_zero(w.lff[b][q], (long long)nfa, st));
+    HIPCHK(hipMemcpyAsync(w.lthf + Mf * nf3, lam_np1, nf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    const shx_plan* pc = cl ? cl->plan : nullptr;
+    int Mc = 0, nsc = 0;
+    size_t nc3 = 0, nca = 0;
+    Mat9x9 Pcf{}, Pfc{}, PQ{}, Qc{};
+    if (cl) {
+        Mc = cl->nnodes - 1;
+        nsc = o->nsweep_coarse;
+        nc3 = 3 * (size_t)pc->nspec;
+        nca = (size_t)cl->nnodes * nc3;
+        if (level_pair_matrices(fl, cl, Pcf, Pfc, PQ, Qc)) return SHX_EINVAL;
+        HIPCHK(launch_zero(w.lthc0, (long long)nc3, st));
+        HIPCHK(launch_zero(w.lfic0, (long long)nc3, st));
+        HIPCHK(launch_zero(w.lfec0, (long long)nc3, st));
+    }
+    int fc = 0;
+    for (int k = o->niter - 1; k >= 0; --k) {
+        if (cl) {
+            int cc = 0;
+            HIPCHK(launch_zero(w.lthc, (long long)nca, st));
+            HIPCHK(launch_zero(w.lthct, (long long)nca, st));
+            HIPCHK(launch_zero(w.lfict, (long long)nca, st));
+            HIPCHK(launch_zero(w.lfect, (long long)nca, st));
+            HIPCHK(launch_zero(w.lfc[cc][0], (long long)nca, st));
+            HIPCHK(launch_zero(w.lfc[cc][1], (long long)nca, st));
+            HIPCHK(launch_zero(w.ltau, (long long)nca, st));
+            // D^T
+            HIPCHK(launch_interp_adj(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.lthf, w.lff[fc][0], w.lff[fc][1], w.lthc,
+                                     w.lthct, w.lfc[cc][0], w.lfict, w.lfc[cc][1], w.lfect, st));
+            // C^T: coarse sweeps in reverse
+            const size_t cbase = 1 + (size_t)k * (Mc + nsc * Mc);
+            for (int s2 = nsc - 1; s2 >= 0; --s2) {
+                HIPCHK(launch_zero(w.lfc[1 - cc][0], (long long)nca, st));
+                HIPCHK(launch_zero(w.lfc[1 - cc][1], (long long)nca, st));
+                rc = sweep_adj_impl(cl, dt, w.tape.c + (cbase + Mc + (size_t)s2 * Mc) * nc3, w.lthc, w.lfc[cc][0],
+                                    w.lfc[cc][1], w.lfc[1 - cc][0], w.lfc[1 - cc][1], w.ltau, w.tc, st);
+                if (rc) return rc;
+                cc = 1 - cc;
+            }
+            // adjoint of F at the restricted states: sweep input + saved copy
+            HIPCHK(launch_add(w.lfict, w.lfc[cc][0], (long long)nca, st));
+            HIPCHK(launch_add(w.lfect, w.lfc[cc][1], (long long)nca, st));
+            HIPCHK(launch_fas_tau_adj(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.ltau, w.lff[fc][0], w.lff[fc][1],
+                                      w.lfc[cc][0], w.lfc[cc][1], st));
+            // B^T: restricted Theta adjoint = lthc + lthct + F^T at the restricted states
+            HIPCHK(launch_add(w.lthc, w.lthct, (long long)nca, st));
+            rc = tendency_adj_impl(pc, cl->p, Mc, w.tape.c + cbase * nc3, w.lfc[cc][0] + nc3, w.lfc[cc][1] + nc3,
+                                   w.lthct + nc3, w.tc, st);
+            if (rc) return rc;
+            HIPCHK(launch_restrict_adj(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.lthct, w.lthf, st));
+            // coarse node 0 belongs to the whole step
+            HIPCHK(launch_add(w.lthct, w.lthc0, (long long)nc3, st));
+            HIPCHK(launch_add(w.lfc[cc][0], w.lfic0, (long long)nc3, st));
+            HIPCHK(launch_add(w.lfc[cc][1], w.lfec0, (long long)nc3, st));
+        }
+        // A^T: fine sweeps in reverse
+        for (int s2 = nsf - 1; s2 >= 0; --s2) {
+            HIPCHK(launch_zero(w.lff[1 - fc][0], (long long)nfa, st));
+            HIPCHK(launch_zero(w.lff[1 - fc][1], (long long)nfa, st));
+            rc = sweep_adj_impl(fl, dt, w.tape.f + (1 + (size_t)(k * nsf + s2) * Mf) * nf3, w.lthf, w.lff[fc][0],
+                                w.lff[fc][1], w.lff[1 - fc][0], w.lff[1 - fc][1], nullptr, w.tf, st);
+            if (rc) return rc;
+            fc = 1 - fc;
+        }
+    }
+    // 3. spread^T: every fine node and its F started from Theta^n
+    HIPCHK(launch_node_sum(w.lthf, lout, (long long)nf3, fl->nnodes, 0, st));
+    HIPCHK(launch_node_sum(w.lff[fc][0], w.lsfi, (long long)nf3, fl->nnodes, 0, st));
+    HIPCHK(launch_node_sum(w.lff[fc][1], w.lsfe, (long long)nf3, fl->nnodes, 0, st));
+    rc = tendency_adj_impl(pf, fl->p, 1, w.tape.f, w.lsfi, w.lsfe, lout, w.tf, st);
+    if (rc) return rc;
+    if (cl) {
+        rc = tendency_adj_impl(pc, cl->p, 1, w.tape.c, w.lfic0, w.lfec0, w.lthc0, w.tc, st);
+        if (rc) return rc;
+        Mat9x9 e0{};
+        e0.a[0] = 1.0;
+        HIPCHK(launch_restrict_adj(pf, pc, e0, 1, 0, 1, w.lthc0, lout, st));
+    }
     return SHX_OK;
 }
 
@@ -603,97 +1022,8 @@ int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, do
     Carve cv{static_cast<char*>(ws)};
     StepWS w = carve_step(cv, fl, cl, o);
     hipStream_t st = S(stream);
-    const shx_plan* pf = fl->plan;
-    const int Mf = fl->nnodes - 1;
-    const size_t nsf3 = 3 * (size_t)pf->nspec;
-    const double2* th_n = reinterpret_cast<const double2*>(theta_n);
-    // spread: Theta and F at every fine node equal those of Theta^n
-    HIPCHK(hipMemcpyAsync(w.thf, th_n, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    int rc = tendency_impl(pf, fl->p, 1, w.thf, w.fif[0], w.fef[0], w.tf, st);
-    if (rc) return rc;
-    {
-        NodeCopies nc{};
-        nc.add(w.thf, w.thf, 1, Mf);
-        nc.add(w.fif[0], w.fif[0], 1, Mf);
-        nc.add(w.fef[0], w.fef[0], 1, Mf);
-        nc.add(w.fif[0], w.fif[1], 0, 0);
-        nc.add(w.fef[0], w.fef[1], 0, 0);
-        HIPCHK(launch_node_copies(nc, (long long)nsf3, st));
-    }
-    int fcur = 0;                                        // fine F buffer holding the current iterate
-    Mat9x9 Pcf{}, Pfc{}, PQ{}, Qc{};
-    int Mc = 0;
-    size_t nsc3 = 0;
-    const shx_plan* pc = cl ? cl->plan : nullptr;
-    if (cl) {
-        Mc = cl->nnodes - 1;
-        nsc3 = 3 * (size_t)pc->nspec;
-        double a[81], b[81];
-        if (shx_host_transfer(fl->kind, fl->nnodes, cl->nnodes, a)) return SHX_EINVAL;   // [nc][nf]
-        if (shx_host_transfer(fl->kind, cl->nnodes, fl->nnodes, b)) return SHX_EINVAL;   // [nf][nc]
-        Pcf = to_mat(a, cl->nnodes * fl->nnodes);
-        Pfc = to_mat(b, fl->nnodes * cl->nnodes);
-        // Pi^c_f Q_f  [nc][nf]
-        for (int i = 0; i < cl->nnodes; ++i)
-            for (int j = 0; j < fl->nnodes; ++j) {
-                double sum = 0.0;
-                for (int k = 0; k < fl->nnodes; ++k) sum += a[i * fl->nnodes + k] * fl->Q[k * fl->nnodes + j];
-                PQ.a[i * fl->nnodes + j] = sum;
-            }
-        Qc = to_mat(cl->Q, cl->nnodes * cl->nnodes);
-        // coarse node 0: restricted initial value and its F, once per step
-        Mat9x9 e0{};
-        e0.a[0] = 1.0;
-        HIPCHK(launch_restrict(pf, pc, e0, 1, 0, 1, th_n, w.thc, w.thct, st));
-        rc = tendency_impl(pc, cl->p, 1, w.thct, w.fict, w.fect, w.tc, st);
-        if (rc) return rc;
-        NodeCopies nc{};
-        for (int b2 = 0; b2 < 2; ++b2) {
-            nc.add(w.fict, w.fic[b2], 0, 0);
-            nc.add(w.fect, w.fec[b2], 0, 0);
-        }
-        HIPCHK(launch_node_copies(nc, (long long)nsc3, st));
-    }
-    for (int k = 0; k < o->niter; ++k) {
-        // A) fine sweep(s), old -> new buffers
-        for (int s2 = 0; s2 < o->nsweep_fine; ++s2) {
-            rc = sweep_impl(fl, dt, w.thf, w.fif[fcur], w.fef[fcur], w.fif[1 - fcur], w.fef[1 - fcur], nullptr,
-                            w.tf, st);
-            if (rc) return rc;
-            fcur = 1 - fcur;
-        }
-        if (!cl) continue;
-        // B) restrict nodes 1..Mc (kept twice: iterate and saved copy), evaluate
-        HIPCHK(launch_restrict(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.thf, w.thc, w.thct, st));
-        rc = tendency_impl(pc, cl->p, Mc, w.thct + nsc3, w.fict + nsc3, w.fect + nsc3, w.tc, st);
-        if (rc) return rc;
-        // C) FAS correction and coarse sweep(s): the first reads the saved F
-        HIPCHK(launch_fas_tau(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.fif[fcur], w.fef[fcur], w.fict, w.fect,
-                              w.tau, st));
-        const double2 *ci = w.fict, *ce = w.fect;
-        for (int s2 = 0; s2 < o->nsweep_coarse; ++s2) {
-            rc = sweep_impl(cl, dt, w.thc, ci, ce, w.fic[s2 & 1], w.fec[s2 & 1], w.tau, w.tc, st);
-            if (rc) return rc;
-            ci = w.fic[s2 & 1];
-            ce = w.fec[s2 & 1];
-        }
-        // D) interpolate the coarse corrections of Theta, F_I, F_E
-        HIPCHK(launch_interp(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.thc, w.thct, ci, w.fict, ce, w.fect, w.thf,
-                             w.fif[fcur], w.fef[fcur], st));
-    }
-    double2* out = reinterpret_cast<double2*>(theta_np1);
-    HIPCHK(hipMemcpyAsync(out, w.thf + Mf * nsf3, nsf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    if (status) {
-        const int nblk = residual_blocks(pf);
-        if (o->residual_check) {
-            rc = tendency_impl(pf, fl->p, fl->nnodes, w.thf, w.rfi, w.rfe, w.tr, st);
-            if (rc) return rc;
-            HIPCHK(launch_residual(pf, to_mat(fl->Q, fl->nnodes * fl->nnodes), Mf, dt, w.thf, w.rfi, w.rfe,
-                                   w.partial, nblk, st));
-        }
-        HIPCHK(launch_status(pf, w.partial, nblk, Mf, out, status, o->residual_check, st));
-    }
-    return SHX_OK;
+    return step_body(fl, cl, o, dt, reinterpret_cast<const double2*>(theta_n), reinterpret_cast<double2*>(theta_np1),
+                     status, w, nullptr, st);
 }
 
 }  // extern "C"

@@ -177,8 +177,9 @@ __device__ __forceinline__ double2 unpack_analysis(const double2* row, const dou
 template <int L>
 __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_inv(const double2* __restrict__ FI,
                                                           const double2* __restrict__ tw,
+                                                          const double* __restrict__ w,
                                                           double* __restrict__ grid, int N, int J,
-                                                          int F) {
+                                                          int F, int mode) {
     constexpr int L2 = L / 2, T = FftCfg<L>::T;
     __shared__ double2 row[L2];
     __shared__ double2 tws[L2];
@@ -198,7 +199,8 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_inv(const double2* __restr
     __syncthreads();
     fft_stages<L2, T, 1, 1, 2>(row, tws, 1.0);
     double2* g = reinterpret_cast<double2*>(grid + ((long long)f * J + j) * L);
-    for (int k = threadIdx.x; k < L2; k += T) g[k] = row[k];
+    const double gs = mode ? w[j] / L : 1.0;
+    for (int k = threadIdx.x; k < L2; k += T) g[k] = make_double2(gs * row[k].x, gs * row[k].y);
 }
 
 // Forward: one workgroup per (latitude row j, field f); G[j][m][f] = w_j X_m / L.
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_fwd(const double* __restri
                                                           const double2* __restrict__ tw,
                                                           const double* __restrict__ w,
                                                           double2* __restrict__ G, int N, int J,
-                                                          int F) {
+                                                          int F, int mode) {
     constexpr int L2 = L / 2, T = FftCfg<L>::T;
     __shared__ double2 row[L2];
     __shared__ double2 tws[L2];
@@ -217,9 +219,9 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_fft_fwd(const double* __restri
     for (int k = threadIdx.x; k < L2; k += T) row[k] = g[k];
     __syncthreads();
     fft_stages<L2, T, 1, 1, 2>(row, tws, -1.0);
-    const double sc = w[j] / L;
     double2* out = G + (long long)j * (N + 1) * F + f;
     for (int m = threadIdx.x; m <= N; m += T) {
+        const double sc = mode ? (m == 0 ? 1.0 : 2.0) : w[j] / L;
         const double2 X = unpack_analysis<L>(row, tws, m);
         out[(long long)m * F] = make_double2(sc * X.x, sc * X.y);
     }
@@ -286,15 +288,15 @@ __global__ __launch_bounds__(FftCfg<L>::T) void k_swe_grid(const double2* __rest
 }
 
 template <int L>
-hipError_t inv_t(const shx_plan* pl, const double2* FI, double* grid, int F, hipStream_t st) {
+hipError_t inv_t(const shx_plan* pl, const double2* FI, double* grid, int F, int mode, hipStream_t st) {
     dim3 g(pl->J, F);
-    k_fft_inv<L><<<g, FftCfg<L>::T, 0, st>>>(FI, pl->tw, grid, pl->N, pl->J, F);
+    k_fft_inv<L><<<g, FftCfg<L>::T, 0, st>>>(FI, pl->tw, pl->w, grid, pl->N, pl->J, F, mode);
     return hipGetLastError();
 }
 template <int L>
-hipError_t fwd_t(const shx_plan* pl, const double* grid, double2* G, int F, hipStream_t st) {
+hipError_t fwd_t(const shx_plan* pl, const double* grid, double2* G, int F, int mode, hipStream_t st) {
     dim3 g(pl->J, F);
-    k_fft_fwd<L><<<g, FftCfg<L>::T, 0, st>>>(grid, pl->tw, pl->w, G, pl->N, pl->J, F);
+    k_fft_fwd<L><<<g, FftCfg<L>::T, 0, st>>>(grid, pl->tw, pl->w, G, pl->N, pl->J, F, mode);
     return hipGetLastError();
 }
 template <int L>
@@ -321,18 +323,18 @@ bool fft_length_supported(int L) {
     }
 }
 
-hipError_t launch_fft_inv(const shx_plan* pl, const double2* FI, double* grid, int F, hipStream_t st) {
+hipError_t launch_fft_inv(const shx_plan* pl, const double2* FI, double* grid, int F, int mode, hipStream_t st) {
     switch (pl->I) {
-#define CASE(n) case n: return inv_t<n>(pl, FI, grid, F, st);
+#define CASE(n) case n: return inv_t<n>(pl, FI, grid, F, mode, st);
         SHX_FFT_LENGTHS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fft_fwd(const shx_plan* pl, const double* grid, double2* G, int F, hipStream_t st) {
+hipError_t launch_fft_fwd(const shx_plan* pl, const double* grid, double2* G, int F, int mode, hipStream_t st) {
     switch (pl->I) {
-#define CASE(n) case n: return fwd_t<n>(pl, grid, G, F, st);
+#define CASE(n) case n: return fwd_t<n>(pl, grid, G, F, mode, st);
         SHX_FFT_LENGTHS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

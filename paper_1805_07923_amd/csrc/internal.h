@@ -96,13 +96,17 @@ hipError_t launch_tables_to_bf16(const shx_plan* pl, const int* d_rows_an, const
                                  const int* d_colsp_an, const int* d_rows_syn, const int* d_cols_syn,
                                  const int* d_colsp_syn, hipStream_t st);
 // fourier.hip
-hipError_t launch_fft_inv(const shx_plan* pl, const double2* FI, double* grid, int F, hipStream_t st);
-hipError_t launch_fft_fwd(const shx_plan* pl, const double* grid, double2* G, int F, hipStream_t st);
+// mode 0: the transforms; mode 1: their transposes' Fourier parts (inverse:
+// grid scaled by w_j / nlon; forward: coefficient m scaled by c_m = 1, 2, 2, ...)
+hipError_t launch_fft_inv(const shx_plan* pl, const double2* FI, double* grid, int F, int mode, hipStream_t st);
+hipError_t launch_fft_fwd(const shx_plan* pl, const double* grid, double2* G, int F, int mode, hipStream_t st);
 hipError_t launch_swe_grid(const shx_plan* pl, const double2* FI, double2* G, int S, double omega,
                            hipStream_t st);
 bool fft_length_supported(int L);
 // spectral.hip
-hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, hipStream_t st);
+// halve != 0 multiplies the coefficients of m >= 1 by 1/2 (analysis transpose)
+hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, int halve,
+                              hipStream_t st);
 hipError_t launch_ext_to_spec(const shx_plan* pl, const double2* cout, double2* spec, int F, hipStream_t st);
 hipError_t launch_swe_prep(const shx_plan* pl, double a, const double2* state, double2* cin, int S,
                            hipStream_t st);
@@ -147,3 +151,27 @@ hipError_t launch_residual(const shx_plan* pl, const Mat9x9& Q, int M, double dt
 hipError_t launch_status(const shx_plan* pl, const double* partial, int nblk, int M,
                          const double2* theta_new, double* status, int residual_on, hipStream_t st);
 int residual_blocks(const shx_plan* pl);
+// adjoint.hip
+bool adjoint_length_supported(int L);
+hipError_t launch_combine_adj(const shx_plan* pl, double a, const double2* lfe, double2* lam5, int S, hipStream_t st);
+hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double2* lam4, const double2* lfi,
+                           double2* lstate, int S, int has_fe, hipStream_t st);
+hipError_t launch_swe_grid_adj(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S,
+                               double omega, hipStream_t st);
+hipError_t launch_imex_solve_adj(const shx_plan* pl, const swe_params& p, double h, const double2* lx,
+                                 double2* lb, int S, hipStream_t st);
+hipError_t launch_sdc_node_adj(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wt,
+                               double h, double2* lth, double2* lfi_new, double2* lfe_new, double2* lfi_in,
+                               double2* lfe_in, double2* ltau, hipStream_t st);
+hipError_t launch_restrict_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc, int i0,
+                               int i1, const double2* lc, double2* lf, hipStream_t st);
+hipError_t launch_interp_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pfc, int nf, int nc,
+                             const double2* lthf, const double2* lfif, const double2* lfef, double2* lthc,
+                             double2* lthct, double2* lfic, double2* lfict, double2* lfec, double2* lfect,
+                             hipStream_t st);
+hipError_t launch_fas_tau_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ, const Mat9x9& Qc,
+                              int nf, int nc, double dt, const double2* ltau, double2* lfif, double2* lfef,
+                              double2* lfic, double2* lfec, hipStream_t st);
+hipError_t launch_node_sum(const double2* x, double2* y, long long n3, int nn, int acc, hipStream_t st);
+hipError_t launch_add(const double2* x, double2* y, long long n, hipStream_t st);
+hipError_t launch_zero(double2* x, long long n, hipStream_t st);

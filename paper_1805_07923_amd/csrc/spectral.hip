@@ -34,12 +34,13 @@ __device__ __forceinline__ double2 cim(double m, double2 a) { return make_double
 
 __global__ void k_spec_to_ext(const int* __restrict__ ord_e, const int* __restrict__ deg_e,
                               const double2* __restrict__ spec, double2* __restrict__ cin, int N,
-                              long long nspec, long long nspec_e, int F) {
+                              long long nspec, long long nspec_e, int F, int halve) {
     const long long e = (long long)blockIdx.x * TB + threadIdx.x;
     if (e >= nspec_e) return;
     const int m = ord_e[e], n = deg_e[e];
+    const double sc = (halve && m > 0) ? 0.5 : 1.0;
     for (int f = 0; f < F; ++f)
-        cin[e * F + f] = (n <= N) ? spec[f * nspec + spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+        cin[e * F + f] = (n <= N) ? cscale(sc, spec[f * nspec + spec_idx(N, m, n)]) : make_double2(0.0, 0.0);
 }
 
 __global__ void k_ext_to_spec(const int* __restrict__ ord, const int* __restrict__ deg,
@@ -376,9 +377,10 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + TB - 1) / TB); }
 
 }  // namespace
 
-hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, hipStream_t st) {
+hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, int halve,
+                              hipStream_t st) {
     k_spec_to_ext<<<nblocks(pl->nspec_e), TB, 0, st>>>(pl->ord_e, pl->deg_e, spec, cin, pl->N, pl->nspec,
-                                                        pl->nspec_e, F);
+                                                        pl->nspec_e, F, halve);
     return hipGetLastError();
 }
 

@@ -1,0 +1,238 @@
+"""Hand-written adjoint: transposes of the SH pair, the tendency, the solve and
+the whole MLSDC step, checked by dot-product identities, against torch
+autograd through the FP64 CPU oracle (the reference gradient), and against
+central finite differences on the 20-step T127/T63 integration."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workload
+from oracle import sdc as OS
+from oracle import sht as OH
+from oracle import swe as OW
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_07923_amd as pk
+    pk.lib()
+    return pk
+
+
+_G = {}
+
+
+def ogrid(N, J, I):
+    if (N, J, I) not in _G:
+        _G[(N, J, I)] = OH.Grid(N, J, I)
+    return _G[(N, J, I)]
+
+
+def rdot(a, b):
+    """Real inner product sum Re a Re b + Im a Im b (or sum a b for real)."""
+    a, b = a.detach().cpu(), b.detach().cpu()
+    if a.is_complex():
+        return (a.real * b.real + a.imag * b.imag).sum().item()
+    return (a * b).sum().item()
+
+
+def relerr(a, b):
+    a, b = a.detach().cpu(), b.detach().cpu()
+    return (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+
+
+def crandn(shape, gen):
+    return torch.randn(shape, dtype=torch.float64, generator=gen) + 1j * torch.randn(shape, dtype=torch.float64,
+                                                                                      generator=gen)
+
+
+def seeded(N, seed, scales=(100.0, 1e-5, 1e-5)):
+    raw = torch.tensor(workload.raw_spectrum(N, seed))
+    return raw * torch.tensor(scales, dtype=torch.float64)[:, None]
+
+
+@pytest.mark.parametrize("N,J,I,F", [(31, 48, 96, 2), (40, 64, 128, 3)])
+def test_sh_pair_adjoint_dot(pk, N, J, I, F):
+    print("CASE sh adjoint dot", N, J, I, F, flush=True)
+    gen = torch.Generator().manual_seed(N)
+    plan = pk.Plan(N, J, I)
+    x = crandn((F, OH.nspec(N)), gen).cuda()
+    h = torch.randn(F, J, I, dtype=torch.float64, generator=gen).cuda()
+    lhs = rdot(plan.inverse(x), h)
+    rhs = rdot(x, plan.inverse_adj(h))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs) * 10
+    s = crandn((F, OH.nspec(N)), gen).cuda()
+    lhs = rdot(plan.forward(h), s)
+    rhs = rdot(h, plan.forward_adj(s))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs) * 10
+
+
+@pytest.mark.parametrize("N,J,I,S", [(31, 48, 96, 1), (63, 96, 192, 2)])
+def test_tendency_adjoint_vs_autograd(pk, N, J, I, S):
+    """VJP of (F_I, F_E) against torch autograd through the oracle."""
+    print("CASE tendency adjoint", N, J, I, S, flush=True)
+    g = ogrid(N, J, I)
+    p = OW.SWEParams()
+    gen = torch.Generator().manual_seed(7 + N)
+    states = torch.stack([seeded(N, 90 + s) for s in range(S)])
+    lfi = crandn(states.shape, gen)
+    lfe = crandn(states.shape, gen)
+    plan = pk.Plan(N, J, I)
+    got = pk.tendency_adj(plan, pk.swe_params(), states.cuda(), lfi.cuda(), lfe.cuda())
+    for s in range(S):
+        x = states[s].clone().requires_grad_(True)
+        fi = OW.f_implicit(x, N, p)
+        fe = OW.f_explicit(x, g, p)
+        loss = (fi.real * lfi[s].real + fi.imag * lfi[s].imag).sum() + \
+               (fe.real * lfe[s].real + fe.imag * lfe[s].imag).sum()
+        loss.backward()
+        for f in range(3):
+            assert relerr(got[s, f], x.grad[f]) < 1e-12, (s, f, relerr(got[s, f], x.grad[f]))
+
+
+def test_solve_adjoint_dot(pk):
+    N = 63
+    gen = torch.Generator().manual_seed(3)
+    plan = pk.Plan(N, 96, 192)
+    par = pk.swe_params()
+    b = crandn((2, 3, OH.nspec(N)), gen).cuda()
+    y = crandn((2, 3, OH.nspec(N)), gen).cuda()
+    for h in (0.0, 150.0, 600.0):
+        lhs = rdot(pk.solve(plan, par, h, b), y)
+        rhs = rdot(b, pk.solve_adj(plan, par, h, y))
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs) * 10
+
+
+def _oracle_levels(specs):
+    lev = []
+    for (N, J, I, kind, nn) in specs:
+        prob = OW.SWEProblem.__new__(OW.SWEProblem)
+        prob.N, prob.grid, prob.p, prob.n_eval, prob.n_solve = N, ogrid(N, J, I), OW.SWEParams(), 0, 0
+        lev.append(OS.Level(prob, kind, nn))
+    return lev
+
+
+CASES = [
+    # (fine, coarse or None, niter, nsweep_fine, nsweep_coarse, dt)
+    ((31, 48, 96, "lobatto", 3), (15, 24, 48, "lobatto", 2), 2, 2, 2, 600.0),
+    ((31, 48, 96, "lobatto", 5), (15, 24, 48, "lobatto", 3), 2, 1, 1, 600.0),
+    ((31, 48, 96, "radau", 4), (15, 24, 48, "radau", 3), 2, 1, 2, 600.0),
+    ((31, 48, 96, "lobatto", 3), None, 3, 1, 1, 600.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_step_adjoint_vs_autograd(pk, case):
+    """lam_n = J^T lam_np1 of one MLSDC (or SDC) step against torch autograd
+    through the oracle's step (the FP64 CPU reference gradient)."""
+    fs, cs, niter, nsf, nsc, dt = CASES[case]
+    print("CASE step adjoint", fs, cs, niter, nsf, nsc, flush=True)
+    kinds = {"lobatto": pk.SDC_GAUSS_LOBATTO, "radau": pk.SDC_RADAU_RIGHT}
+    par = pk.swe_params()
+    lf = pk.Level(pk.Plan(*fs[:3]), par, kinds[fs[3]], fs[4])
+    lc = pk.Level(pk.Plan(*cs[:3]), par, kinds[cs[3]], cs[4]) if cs else None
+    stepper = pk.Stepper(lf, lc, niter=niter, nsweep_fine=nsf, nsweep_coarse=nsc)
+    gen = torch.Generator().manual_seed(11 + case)
+    st = torch.tensor(workload.state(31, 1000))
+    lam = crandn(st.shape, gen)
+    got = stepper.step_adj(dt, st.cuda(), lam.cuda())
+    levels = _oracle_levels([fs] + ([cs] if cs else []))
+    x = st.clone().requires_grad_(True)
+    if cs:
+        R, P = OS.spectral_transfer(fs[0], cs[0])
+        y = OS.mlsdc_step(levels[0], levels[1], dt, x, niter=niter, nsweep_fine=nsf, nsweep_coarse=nsc,
+                          restrict_space=R, interp_space=P)
+    else:
+        y = OS.mlsdc_step(levels[0], None, dt, x, niter=niter, nsweep_fine=nsf)
+    loss = (y.real * lam.real + y.imag * lam.imag).sum()
+    loss.backward()
+    for f in range(3):
+        e = relerr(got[f], x.grad[f])
+        print("step adjoint", case, f, e, flush=True)
+        assert e < 1e-11, (f, e)
+
+
+def _loss(theta):
+    """L = 0.5 sum_n [|Phi'^0_n|^2 + 2 sum_{m>=1} |Phi'^m_n|^2] = (1/4 pi) int Phi'^2 (unit sphere)."""
+    phi = theta[0]
+    N = int((math.isqrt(8 * phi.numel() + 1) - 3) // 2)
+    w = torch.where(OH.orders(N).to(phi.device) == 0, 1.0, 2.0).to(torch.float64)
+    return 0.5 * (w * (phi.real ** 2 + phi.imag ** 2)).sum()
+
+
+def _c3_stepper(pk):
+    par = pk.swe_params()
+    lf = pk.Level(pk.Plan(127, 192, 384), par, pk.SDC_GAUSS_LOBATTO, 5)
+    lc = pk.Level(pk.Plan(63, 96, 192), par, pk.SDC_GAUSS_LOBATTO, 3)
+    return pk.Stepper(lf, lc, niter=4, nsweep_fine=2, nsweep_coarse=2)
+
+
+def test_integrate_gradient_vs_finite_differences(pk):
+    """T127/T63, GL 5/3, 2+2 sweeps x 4, dt = 300 s, 20 steps with per-step
+    checkpoints; gradient of L(Phi'(T)) w.r.t. the initial vorticity against
+    central differences (eps = 1e-6 relative) in 32 seeded directions."""
+    print("CASE integrate FD", flush=True)
+    stepper = _c3_stepper(pk)
+    th0 = torch.tensor(workload.state(127, 1003)).cuda()
+    dt, nsteps = 300.0, 20
+    x = th0.clone().requires_grad_(True)
+    L = _loss(pk.integrate(x, stepper, dt, nsteps))
+    L.backward()
+    grad_z = x.grad[1].clone()
+    N = 127
+    m = OH.orders(N).cuda()
+    n = OH.degrees(N).cuda()
+    rng = np.random.default_rng(3000)
+    zn = torch.linalg.vector_norm(th0[1]).item()
+    eps = 1e-6
+    worst = 0.0
+    for k in range(32):
+        d = torch.tensor(rng.standard_normal(th0.shape[1]) + 1j * rng.standard_normal(th0.shape[1]),
+                         dtype=torch.complex128).cuda()
+        d = torch.where(m == 0, d.real.to(torch.complex128), d)
+        d = torch.where(n == 0, torch.zeros_like(d), d)
+        d = d * (zn / torch.linalg.vector_norm(d).item())
+        xp, xm = th0.clone(), th0.clone()
+        xp[1] += eps * d
+        xm[1] -= eps * d
+        for _ in range(nsteps):
+            xp = stepper.step(dt, xp)
+            xm = stepper.step(dt, xm)
+        fd = ((_loss(xp) - _loss(xm)) / (2 * eps)).item()
+        an = rdot(grad_z, d)
+        e = abs(fd - an) / max(abs(an), 1e-300)
+        worst = max(worst, e)
+    print("FD worst relative error", worst, flush=True)
+    assert worst < 1e-5
+
+
+def test_integrate_gradient_vs_cpu_reference(pk):
+    """The same gradient against torch autograd through the oracle (one step
+    at T127/T63, and three steps of the T31/T15 pair)."""
+    print("CASE integrate vs CPU gradient", flush=True)
+    for (fine, coarse, nsteps, dt, seed) in (((127, 192, 384), (63, 96, 192), 1, 300.0, 1003),
+                                            ((31, 48, 96), (15, 24, 48), 3, 600.0, 1000)):
+        par = pk.swe_params()
+        lf = pk.Level(pk.Plan(*fine), par, pk.SDC_GAUSS_LOBATTO, 5)
+        lc = pk.Level(pk.Plan(*coarse), par, pk.SDC_GAUSS_LOBATTO, 3)
+        stepper = pk.Stepper(lf, lc, niter=4, nsweep_fine=2, nsweep_coarse=2)
+        th0 = torch.tensor(workload.state(fine[0], seed))
+        x = th0.clone().cuda().requires_grad_(True)
+        _loss(pk.integrate(x, stepper, dt, nsteps)).backward()
+        levels = _oracle_levels([fine + ("lobatto", 5), coarse + ("lobatto", 3)])
+        R, P = OS.spectral_transfer(fine[0], coarse[0])
+        xo = th0.clone().requires_grad_(True)
+        y = xo
+        for _ in range(nsteps):
+            y = OS.mlsdc_step(levels[0], levels[1], dt, y, niter=4, nsweep_fine=2, nsweep_coarse=2,
+                              restrict_space=R, interp_space=P)
+        _loss(y).backward()
+        e = relerr(x.grad[1], xo.grad[1])
+        print("gradient vs CPU reference", fine, nsteps, e, flush=True)
+        assert e < 1e-10
