@@ -305,6 +305,31 @@ def main():
             extra[f"steps_per_s_T255_T127_{pname}"] = {"value": max(5, args.steps // 2) / sp,
                                                        "one_step_rel_err_vs_fp64": errs}
             del stp
+        # adjoint: T127/T63 levels as in the two-level configuration, 20 steps,
+        # per-step checkpoints, L = 0.5 ||Phi'(T)||^2, gradient w.r.t. Theta^0
+        x1 = torch.tensor(workload.state(127, 1003), device="cuda")
+        sa = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
+        nadj = 20
+        w = torch.ones(x1.shape[1], dtype=torch.float64, device="cuda")
+        w[(127 + 1):] = 2.0          # m >= 1 entries follow the (N+1) m = 0 entries
+        times = []
+        for rep in range(2):
+            x = x1.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            y = pk.integrate(x, sa, DT, nadj)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            (0.5 * (w * (y[0].real ** 2 + y[0].imag ** 2)).sum()).backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1))
+        fwd, bwd = times[-1]
+        extra["adjoint_T127_T63_20steps"] = {
+            "s_per_step": bwd / nadj, "forward_s_per_step": fwd / nadj,
+            "note": "backward = per-step recompute from the checkpoint + reverse sweep, FP64",
+            "grad_finite": bool(torch.isfinite(torch.view_as_real(x.grad)).all().item()),
+        }
         out["extra"] = extra
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib * (1 << 20) // 8

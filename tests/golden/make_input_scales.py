@@ -15,7 +15,8 @@ import workload  # noqa: E402
 from oracle.sht import Grid  # noqa: E402
 from oracle.swe import velocity_coeffs  # noqa: E402
 
-TARGETS = {"T31": ["sdc_T31"], "T127": ["mlsdc_T127", "adjoint_T127"], "T255": ["pair_T255", "mlsdc_T255"]}
+TARGETS = {"T31": ["sdc_T31"], "T127": ["mlsdc_T127", "adjoint_T127"], "T255": ["pair_T255", "mlsdc_T255"],
+           "T1023": ["mlsdc_T1023"]}
 
 
 def main():
