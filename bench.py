@@ -1,6 +1,7 @@
 """Benchmark of the MLSDC-SH hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph]
+                    [--no-extra] [--only legendre|mixed|adjoint|large]
 
 A step is one two-level MLSDC time step (Algorithm 1 of the paper) on the
 headline workload: fine level T255 on the 768 x 384 Gaussian grid with 5
@@ -13,8 +14,11 @@ R_f = 256 test cases.  Inputs are resident in HBM before timing.
 Prints one JSON line with the throughput (steps/s), the roofline of the
 dominant kernel (its launch durations measured with HIP events on its own
 stream during an instrumented pass over the same steps), the oracle timed on
-the host cores, and secondary figures (Legendre GFLOP/s of the 15-field T255
-transform pair, the paper's 1+1 sweep variant, the T127/T63 configuration).
+the host cores, and secondary figures: the paper's 1+1 sweep variant, the
+T127/T63 configuration, Legendre GFLOP/s of the 15-field T255 transform pair
+and steps/s per working precision with the error against FP64, the adjoint's
+seconds per step (T127/T63, 20 checkpointed steps) and the large
+T1023/T511 Gauss-Radau configuration per precision.
 """
 import argparse
 import json
@@ -37,6 +41,8 @@ C1_COARSE = dict(N=63, J=96, I=192, nodes=3)
 DT = 300.0
 NITER, NSWEEP = 4, 2
 SEED = 1005
+LARGE_DT = 60.0
+PRECISIONS = (("fp64", 0), ("fp32", 1), ("bf16x2", 2), ("bf16x3", 3))
 
 
 def kcount(nmax, m, p):
@@ -87,12 +93,12 @@ def make_stepper(pk, fine, coarse, niter, nsweep, residual=False, precision=0):
     return pk.Stepper(lf, lc, niter=niter, nsweep_fine=nsweep, nsweep_coarse=nsweep, residual_check=residual)
 
 
-def run_steps(torch, stepper, x0, steps, warmup, graph):
+def run_steps(torch, stepper, x0, steps, warmup, graph, dt=DT):
     """Returns (seconds for `steps` steps, final state)."""
     a = x0.clone()
     b = torch.empty_like(a)
     for _ in range(warmup):
-        stepper.step(DT, a, b)
+        stepper.step(dt, a, b)
         a, b = b, a
     torch.cuda.synchronize()
     if graph:
@@ -100,10 +106,10 @@ def run_steps(torch, stepper, x0, steps, warmup, graph):
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            stepper.step(DT, a, b)           # workspaces exist before capture
+            stepper.step(dt, a, b)           # workspaces exist before capture
             torch.cuda.synchronize()
             with torch.cuda.graph(g, stream=s):
-                stepper.step(DT, a, b)
+                stepper.step(dt, a, b)
                 # copy back so that each replay advances the state by one step
                 a.copy_(b)
         torch.cuda.synchronize()
@@ -115,7 +121,7 @@ def run_steps(torch, stepper, x0, steps, warmup, graph):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        stepper.step(DT, a, b)
+        stepper.step(dt, a, b)
         a, b = b, a
     torch.cuda.synchronize()
     return time.perf_counter() - t0, a
@@ -141,6 +147,138 @@ def cpu_baseline(state_np):
                       f"{dt:.1f} s wall"}
 
 
+def variants_extra(pk, torch, workload, x0, steps, graph):
+    extra = {}
+    # paper's variant: one fine and one coarse sweep per iteration
+    st11 = make_stepper(pk, FINE, COARSE, NITER, 1)
+    s11, _ = run_steps(torch, st11, x0, max(5, steps // 2), 2, graph)
+    extra["steps_per_s_T255_T127_sweeps_1_1"] = max(5, steps // 2) / s11
+    # T127/T63 configuration
+    x1 = torch.tensor(workload.state(127, 1001), device="cuda")
+    stc1 = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
+    s1, _ = run_steps(torch, stc1, x1, max(5, steps), 2, graph)
+    extra["steps_per_s_T127_T63_sweeps_2_2"] = max(5, steps) / s1
+    return extra
+
+
+def legendre_extra(pk, torch, workload):
+    """Legendre GFLOP/s, T255, 15 fields (one launch per direction), per precision."""
+    extra = {}
+    spec0 = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1), device="cuda")
+    fl = legendre_flops(255, 384, 15, 255)
+    ref_grid = ref_spec = None
+    for pname, prec in PRECISIONS:
+        plan = pk.Plan(255, 384, 768, prec)
+        spec = spec0.clone()
+        grid = plan.inverse(spec)
+        spec_b = plan.forward(grid)
+        torch.cuda.synchronize()
+        if ref_grid is None:
+            ref_grid, ref_spec = grid.clone(), spec_b.clone()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        cin = torch.zeros((256 * 259 // 2) * 15, dtype=torch.complex128, device="cuda")
+        four = torch.zeros(384 * 256 * 15, dtype=torch.complex128, device="cuda")
+        pk.legendre_synthesis(plan, 15, 255, cin, four)
+        e0.record()
+        for _ in range(reps):
+            pk.legendre_synthesis(plan, 15, 255, cin, four)
+        e1.record()
+        torch.cuda.synchronize()
+        syn_us = e0.elapsed_time(e1) * 1e3 / reps
+        e0.record()
+        for _ in range(reps):
+            pk.legendre_analysis(plan, 15, 255, four, cin)
+        e1.record()
+        torch.cuda.synchronize()
+        an_us = e0.elapsed_time(e1) * 1e3 / reps
+        err_g = max((torch.linalg.vector_norm(grid[f] - ref_grid[f]) / torch.linalg.vector_norm(ref_grid[f])).item()
+                    for f in range(15))
+        err_s = max((torch.linalg.vector_norm(spec_b[f] - ref_spec[f]) / torch.linalg.vector_norm(ref_spec[f])).item()
+                    for f in range(15))
+        extra[f"legendre_T255_F15_{pname}"] = {
+            "synthesis_gflops": fl / (syn_us * 1e-6) / 1e9, "analysis_gflops": fl / (an_us * 1e-6) / 1e9,
+            "synthesis_us": syn_us, "analysis_us": an_us, "flop_per_direction": fl,
+            "max_rel_err_vs_fp64_inverse": err_g, "max_rel_err_vs_fp64_roundtrip": err_s,
+        }
+        del plan
+    return extra
+
+
+def rel_errs(torch, x, ref):
+    return [(torch.linalg.vector_norm(x[f] - ref[f]) / torch.linalg.vector_norm(ref[f])).item()
+            for f in range(x.shape[0])]
+
+
+def mixed_steps_extra(pk, torch, x0, steps, graph):
+    """The benchmark step with reduced-precision Legendre contractions."""
+    extra = {}
+    ref_state = None
+    n = max(5, steps // 2)
+    for pname, prec in PRECISIONS:
+        stp = make_stepper(pk, FINE, COARSE, NITER, NSWEEP, precision=prec)
+        one = stp.step(DT, x0.clone())
+        torch.cuda.synchronize()
+        if ref_state is None:
+            ref_state = one.clone()
+        sp, _ = run_steps(torch, stp, x0, n, 2, graph)
+        extra[f"steps_per_s_T255_T127_{pname}"] = {"value": n / sp,
+                                                   "one_step_rel_err_vs_fp64": rel_errs(torch, one, ref_state)}
+        del stp
+    return extra
+
+
+def adjoint_extra(pk, torch, workload):
+    """T127/T63 levels as in the two-level configuration, 20 steps, per-step
+    checkpoints, L = 0.5 ||Phi'(T)||^2, gradient w.r.t. Theta^0."""
+    x1 = torch.tensor(workload.state(127, 1003), device="cuda")
+    sa = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
+    nadj = 20
+    w = torch.ones(x1.shape[1], dtype=torch.float64, device="cuda")
+    w[(127 + 1):] = 2.0          # m >= 1 entries follow the (N+1) m = 0 entries
+    times = []
+    for rep in range(2):
+        x = x1.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = pk.integrate(x, sa, DT, nadj)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (0.5 * (w * (y[0].real ** 2 + y[0].imag ** 2)).sum()).backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = times[-1]
+    return {"adjoint_T127_T63_20steps": {
+        "s_per_step": bwd / nadj, "forward_s_per_step": fwd / nadj,
+        "note": "backward = per-step recompute from the checkpoint + reverse sweep, FP64",
+        "grad_finite": bool(torch.isfinite(torch.view_as_real(x.grad)).all().item()),
+    }}
+
+
+def large_extra(pk, torch, workload, graph):
+    """Fine T1023 (3072 x 1536, 5 Gauss-Radau-right collocation points) over
+    coarse T511 (1536 x 768, 3), (2,2) x 4, dt = 60 s, 5 timed steps per
+    precision; Legendre tables held in HBM."""
+    x = torch.tensor(workload.state(1023, workload.SEEDS["mlsdc_T1023"][0]), device="cuda")
+    par = pk.swe_params()
+    extra = {}
+    ref = None
+    for pname, prec in PRECISIONS:
+        lf = pk.Level(pk.Plan(1023, 1536, 3072, prec), par, pk.SDC_RADAU_RIGHT, 6)
+        lc = pk.Level(pk.Plan(511, 768, 1536, prec), par, pk.SDC_RADAU_RIGHT, 4)
+        st = pk.Stepper(lf, lc, niter=NITER, nsweep_fine=NSWEEP, nsweep_coarse=NSWEEP)
+        one = st.step(LARGE_DT, x.clone())
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = one.clone()
+        secs, _ = run_steps(torch, st, x, 5, 1, graph, dt=LARGE_DT)
+        extra[f"steps_per_s_T1023_T511_radau_{pname}"] = {"value": 5 / secs,
+                                                           "one_step_rel_err_vs_fp64": rel_errs(torch, one, ref)}
+        del st, lf, lc
+    return extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,13 +287,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--only", choices=["legendre", "mixed", "adjoint", "large"], default=None,
+                    help="run only this group of secondary measurements and print them as one JSON line "
+                         "(for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "
-              "across GPUs in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the MLSDC-SH path runs on a "
+              "single GPU and does not shard across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1805_07923_amd as pk
@@ -167,6 +308,14 @@ def main():
     torch.cuda.set_device(0)
     state_np = workload.state(FINE["N"], SEED)
     x0 = torch.tensor(state_np, device="cuda")
+    if args.only:
+        graph = not args.no_graph
+        run = {"legendre": lambda: legendre_extra(pk, torch, workload),
+               "mixed": lambda: mixed_steps_extra(pk, torch, x0, args.steps, graph),
+               "adjoint": lambda: adjoint_extra(pk, torch, workload),
+               "large": lambda: large_extra(pk, torch, workload, graph)}[args.only]
+        print(json.dumps({"only": args.only, "extra": run()}), flush=True)
+        return
 
     stepper = make_stepper(pk, FINE, COARSE, NITER, NSWEEP)
     graph = not args.no_graph
@@ -243,93 +392,11 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        # paper's variant: one fine and one coarse sweep per iteration
-        st11 = make_stepper(pk, FINE, COARSE, NITER, 1)
-        s11, _ = run_steps(torch, st11, x0, max(5, args.steps // 2), 2, graph)
-        extra["steps_per_s_T255_T127_sweeps_1_1"] = max(5, args.steps // 2) / s11
-        # T127/T63 configuration
-        x1 = torch.tensor(workload.state(127, 1001), device="cuda")
-        stc1 = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
-        s1, _ = run_steps(torch, stc1, x1, max(5, args.steps), 2, graph)
-        extra["steps_per_s_T127_T63_sweeps_2_2"] = max(5, args.steps) / s1
-        # Legendre GFLOP/s, T255, 15 fields (one launch per direction), per precision
-        spec0 = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1), device="cuda")
-        fl = legendre_flops(255, 384, 15, 255)
-        ref_grid = None
-        for pname, prec in (("fp64", 0), ("fp32", 1), ("bf16x2", 2), ("bf16x3", 3)):
-            plan = pk.Plan(255, 384, 768, prec)
-            spec = spec0.clone()
-            grid = plan.inverse(spec)
-            spec_b = plan.forward(grid)
-            torch.cuda.synchronize()
-            if ref_grid is None:
-                ref_grid, ref_spec = grid.clone(), spec_b.clone()
-            reps = 20
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            cin = torch.zeros((256 * 259 // 2) * 15, dtype=torch.complex128, device="cuda")
-            four = torch.zeros(384 * 256 * 15, dtype=torch.complex128, device="cuda")
-            pk.legendre_synthesis(plan, 15, 255, cin, four)
-            e0.record()
-            for _ in range(reps):
-                pk.legendre_synthesis(plan, 15, 255, cin, four)
-            e1.record()
-            torch.cuda.synchronize()
-            syn_us = e0.elapsed_time(e1) * 1e3 / reps
-            e0.record()
-            for _ in range(reps):
-                pk.legendre_analysis(plan, 15, 255, four, cin)
-            e1.record()
-            torch.cuda.synchronize()
-            an_us = e0.elapsed_time(e1) * 1e3 / reps
-            err_g = max((torch.linalg.vector_norm(grid[f] - ref_grid[f]) / torch.linalg.vector_norm(ref_grid[f])).item()
-                        for f in range(15))
-            err_s = max((torch.linalg.vector_norm(spec_b[f] - ref_spec[f]) / torch.linalg.vector_norm(ref_spec[f])).item()
-                        for f in range(15))
-            extra[f"legendre_T255_F15_{pname}"] = {
-                "synthesis_gflops": fl / (syn_us * 1e-6) / 1e9, "analysis_gflops": fl / (an_us * 1e-6) / 1e9,
-                "synthesis_us": syn_us, "analysis_us": an_us, "flop_per_direction": fl,
-                "max_rel_err_vs_fp64_inverse": err_g, "max_rel_err_vs_fp64_roundtrip": err_s,
-            }
-            del plan
-        # the benchmark step with reduced-precision Legendre contractions
-        ref_state = None
-        for pname, prec in (("fp64", 0), ("fp32", 1), ("bf16x2", 2), ("bf16x3", 3)):
-            stp = make_stepper(pk, FINE, COARSE, NITER, NSWEEP, precision=prec)
-            one = stp.step(DT, x0.clone())
-            torch.cuda.synchronize()
-            if ref_state is None:
-                ref_state = one.clone()
-            sp, _ = run_steps(torch, stp, x0, max(5, args.steps // 2), 2, graph)
-            errs = [(torch.linalg.vector_norm(one[f] - ref_state[f]) / torch.linalg.vector_norm(ref_state[f])).item()
-                    for f in range(3)]
-            extra[f"steps_per_s_T255_T127_{pname}"] = {"value": max(5, args.steps // 2) / sp,
-                                                       "one_step_rel_err_vs_fp64": errs}
-            del stp
-        # adjoint: T127/T63 levels as in the two-level configuration, 20 steps,
-        # per-step checkpoints, L = 0.5 ||Phi'(T)||^2, gradient w.r.t. Theta^0
-        x1 = torch.tensor(workload.state(127, 1003), device="cuda")
-        sa = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
-        nadj = 20
-        w = torch.ones(x1.shape[1], dtype=torch.float64, device="cuda")
-        w[(127 + 1):] = 2.0          # m >= 1 entries follow the (N+1) m = 0 entries
-        times = []
-        for rep in range(2):
-            x = x1.clone().requires_grad_(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            y = pk.integrate(x, sa, DT, nadj)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            (0.5 * (w * (y[0].real ** 2 + y[0].imag ** 2)).sum()).backward()
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            times.append((t1 - t0, t2 - t1))
-        fwd, bwd = times[-1]
-        extra["adjoint_T127_T63_20steps"] = {
-            "s_per_step": bwd / nadj, "forward_s_per_step": fwd / nadj,
-            "note": "backward = per-step recompute from the checkpoint + reverse sweep, FP64",
-            "grad_finite": bool(torch.isfinite(torch.view_as_real(x.grad)).all().item()),
-        }
+        extra.update(variants_extra(pk, torch, workload, x0, args.steps, graph))
+        extra.update(legendre_extra(pk, torch, workload))
+        extra.update(mixed_steps_extra(pk, torch, x0, args.steps, graph))
+        extra.update(adjoint_extra(pk, torch, workload))
+        extra.update(large_extra(pk, torch, workload, graph))
         out["extra"] = extra
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib * (1 << 20) // 8

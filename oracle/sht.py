@@ -84,21 +84,33 @@ def legendre_m(m, nmax, mu, sin_theta):
       P^m_m = sqrt((2m+1)/(2m)) sin(theta) P^{m-1}_{m-1},
       P^m_{m+1} = sqrt(2m+3) mu P^m_m,
       P^m_n = (mu P^m_{n-1} - eps^m_{n-1} P^m_{n-2}) / eps^m_n.
+    The recurrence runs in extended precision (x87 long double, 64-bit
+    significand) from the FP64 values of mu and sin(theta), and the result is
+    rounded to FP64: run in FP64 it accumulates relative errors of several
+    1e-13 by degree 1000, which the factor n(n+1) of the Laplacian turns into
+    errors near 1e-10 in the divergence tendency at T1023.
     """
-    mu = np.asarray(mu, dtype=np.float64)
-    st = np.asarray(sin_theta, dtype=np.float64)
-    pmm = np.full_like(mu, 1.0 / math.sqrt(2.0))
-    for k in range(1, m + 1):
-        pmm = pmm * (math.sqrt((2.0 * k + 1.0) / (2.0 * k)) * st)
-    out = np.zeros((nmax + 1 - m, mu.size))
+    LD = np.longdouble
+    mu = np.asarray(mu, dtype=np.float64).astype(LD)
+    st = np.asarray(sin_theta, dtype=np.float64).astype(LD)
+    out = np.zeros((max(nmax + 1 - m, 0), mu.size), dtype=LD)
     if nmax < m:
-        return out
+        return out.astype(np.float64)
+
+    def e(n):
+        if n <= m:
+            return LD(0)
+        return np.sqrt(LD(n * n - m * m) / LD(4 * n * n - 1))
+
+    pmm = np.full_like(mu, np.sqrt(LD(1) / LD(2)))
+    for k in range(1, m + 1):
+        pmm = pmm * (np.sqrt(LD(2 * k + 1) / LD(2 * k)) * st)
     out[0] = pmm
     if nmax >= m + 1:
-        out[1] = math.sqrt(2.0 * m + 3.0) * mu * pmm
+        out[1] = np.sqrt(LD(2 * m + 3)) * mu * pmm
     for n in range(m + 2, nmax + 1):
-        out[n - m] = (mu * out[n - m - 1] - eps(n - 1, m) * out[n - m - 2]) / eps(n, m)
-    return out
+        out[n - m] = (mu * out[n - m - 1] - e(n - 1) * out[n - m - 2]) / e(n)
+    return out.astype(np.float64)
 
 
 class Grid:

@@ -15,6 +15,7 @@
 // (Helmholtz) and F_I^T.  The step-level kernels transpose the linear parts of
 // the sweep node update, the FAS term and the space-time transfers.
 #include "internal.h"
+#include "row_fft.h"
 
 namespace {
 
@@ -130,120 +131,14 @@ __global__ void k_prep_adj(const int* __restrict__ ord, const int* __restrict__ 
     o[2 * nspec + i] = cadd(o[2 * nspec + i], ldelta);
 }
 
-// ------------------------------------------------------------ row FFTs (LDS)
-template <int R>
-__device__ __forceinline__ void dft(double2* v, double sg);
-template <>
-__device__ __forceinline__ void dft<2>(double2* v, double) {
-    const double2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-}
-template <>
-__device__ __forceinline__ void dft<4>(double2* v, double sg) {
-    const double2 s0 = cadd(v[0], v[2]), s1 = csub(v[0], v[2]), s2 = cadd(v[1], v[3]), s3 = csub(v[1], v[3]);
-    const double2 r3 = make_double2(-sg * s3.y, sg * s3.x);
-    v[0] = cadd(s0, s2);
-    v[2] = csub(s0, s2);
-    v[1] = cadd(s1, r3);
-    v[3] = csub(s1, r3);
-}
-template <>
-__device__ __forceinline__ void dft<3>(double2* v, double sg) {
-    const double c = 0.86602540378443864676;
-    const double2 t = cadd(v[1], v[2]), d = csub(v[1], v[2]), a = v[0];
-    const double2 mm = make_double2(a.x - 0.5 * t.x, a.y - 0.5 * t.y);
-    const double2 r = make_double2(-sg * c * d.y, sg * c * d.x);
-    v[0] = cadd(a, t);
-    v[1] = cadd(mm, r);
-    v[2] = csub(mm, r);
-}
-__device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half) {
-    const double2 w = tws[idx < half ? idx : idx - half];
-    return idx < half ? w : make_double2(-w.x, -w.y);
-}
-// In-LDS Stockham stages (same scheme as the forward transforms).
-template <int L, int T, int NR, int Ns>
-__device__ __forceinline__ void fft_stages(double2* buf, const double2* tw, double sg) {
-    constexpr int rem = L / Ns;
-    if constexpr (rem > 1) {
-        constexpr int R = (rem % 4 == 0) ? 4 : ((rem % 2 == 0) ? 2 : 3);
-        constexpr int NB = L / R, ITEMS = NR * NB, IPT = (ITEMS + T - 1) / T, TWS = L / (Ns * R) * 2;
-        double2 v[IPT][R];
-#pragma unroll
-        for (int it = 0; it < IPT; ++it) {
-            const int item = threadIdx.x + it * T;
-            if (ITEMS % T == 0 || item < ITEMS) {
-                const int row = item / NB, j = item - row * NB, k = j % Ns;
-                const double2* b = buf + row * L;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double2 x = b[j + r * NB];
-                    if (Ns > 1 && r > 0) {
-                        double2 w = tw_half(tw, r * k * TWS, L);
-                        w.y *= -sg;
-                        x = cmul(x, w);
-                    }
-                    v[it][r] = x;
-                }
-                dft<R>(v[it], sg);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < IPT; ++it) {
-            const int item = threadIdx.x + it * T;
-            if (ITEMS % T == 0 || item < ITEMS) {
-                const int row = item / NB, j = item - row * NB, k = j % Ns;
-                const int base = (j / Ns) * Ns * R + k;
-                double2* b = buf + row * L;
-#pragma unroll
-                for (int q = 0; q < R; ++q) b[base + q * Ns] = v[it][q];
-            }
-        }
-        __syncthreads();
-        fft_stages<L, T, NR, Ns * R>(buf, tw, sg);
-    }
-}
-template <int L>
-struct AdjCfg {
-    static constexpr int L2 = L / 2;
-    static constexpr int T0 = L2 / 2 < 64 ? 64 : (L2 / 2 > 1024 ? 1024 : L2 / 2);
-    static constexpr int T = (T0 + 63) / 64 * 64;
-};
-template <int L, class Coef>
-__device__ __forceinline__ void pack_synthesis(double2* row, const double2* tw, int N, Coef coef) {
-    constexpr int L2 = L / 2, T = AdjCfg<L>::T;
-    for (int m = threadIdx.x; m < L2; m += T) {
-        double2 A = make_double2(0.0, 0.0), B = A;
-        if (m <= N) A = coef(m);
-        if (m == 0) A.y = 0.0;
-        const int j = L2 - m;
-        if (m > 0 && j <= N) {
-            const double2 x = coef(j);
-            B = make_double2(x.x, -x.y);
-        }
-        const double2 s = cadd(A, B), d = csub(A, B);
-        const double2 e = make_double2(tw[m].x, -tw[m].y);
-        const double2 ed = cmul(e, d);
-        row[m] = make_double2(s.x - ed.y, s.y + ed.x);
-    }
-}
-template <int L>
-__device__ __forceinline__ double2 unpack_analysis(const double2* row, const double2* tw, int m) {
-    constexpr int L2 = L / 2;
-    const double2 z = row[m], zc = row[(L2 - m) % L2];
-    const double2 E = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-    const double2 O = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
-    return cadd(E, cmul(tw[m], O));
-}
+using rowfft::Cfg;
 
 // Tendency adjoint, grid part: one workgroup per (latitude row j, state s).
 // FIs[s]: [2][Jh][N+1][4] state (zeta, Phi', U, V); FIl[s]: [2][Jh][N+1][5]
 // cotangents of (A, B, C, D, E)^ after combine^T and halving.  Output
 // Ga[s][j][m][4] = c_m * DFT_m of the grid cotangents of (zeta, Phi', U, V).
 template <int L>
-__global__ __launch_bounds__(AdjCfg<L>::T) void k_swe_grid_adj(const double2* __restrict__ FIs,
+__global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __restrict__ FIs,
                                                                const double2* __restrict__ FIl,
                                                                const double2* __restrict__ tw,
                                                                const double* __restrict__ mu,
@@ -251,41 +146,31 @@ __global__ __launch_bounds__(AdjCfg<L>::T) void k_swe_grid_adj(const double2* __
                                                                const double* __restrict__ w,
                                                                double2* __restrict__ Ga, int N, int J,
                                                                double two_omega) {
-    constexpr int L2 = L / 2, T = AdjCfg<L>::T;
+    constexpr int L2 = L / 2, T = Cfg<L>::T;
     __shared__ double2 lds[9 * L2];
     __shared__ double2 tws[L2];
-    for (int t = threadIdx.x; t < L2; t += T) tws[t] = tw[t];
-    __syncthreads();
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
     const int jp = (j < Jh) ? j : J - 1 - j;
     const double sgn = (j < Jh) ? 1.0 : -1.0;
-    {
-        const long long ps = (long long)Jh * (N + 1) * 4;
-        const double2* e = FIs + (long long)s * J * (N + 1) * 4 + (long long)jp * (N + 1) * 4;
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            auto coef = [&](int m) {
-                const double2 a = e[(long long)m * 4 + f], b = e[(long long)m * 4 + f + ps];
-                return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
-            };
-            pack_synthesis<L>(lds + f * L2, tws, N, coef);
+    // rows 0..3: the state (zeta, Phi', U, V); rows 4..8: the cotangents
+    const long long ps4 = (long long)Jh * (N + 1) * 4, ps5 = (long long)Jh * (N + 1) * 5;
+    const double2* e4 = FIs + (long long)s * J * (N + 1) * 4 + (long long)jp * (N + 1) * 4;
+    const double2* e5 = FIl + (long long)s * J * (N + 1) * 5 + (long long)jp * (N + 1) * 5;
+    auto coef = [&](int f, int m) {
+        double2 a, b;
+        if (f < 4) {
+            a = e4[(long long)m * 4 + f];
+            b = e4[(long long)m * 4 + f + ps4];
+        } else {
+            a = e5[(long long)m * 5 + f - 4];
+            b = e5[(long long)m * 5 + f - 4 + ps5];
         }
-    }
-    {
-        const long long ps = (long long)Jh * (N + 1) * 5;
-        const double2* e = FIl + (long long)s * J * (N + 1) * 5 + (long long)jp * (N + 1) * 5;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            auto coef = [&](int m) {
-                const double2 a = e[(long long)m * 5 + f], b = e[(long long)m * 5 + f + ps];
-                return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
-            };
-            pack_synthesis<L>(lds + (4 + f) * L2, tws, N, coef);
-        }
-    }
+        return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
+    };
+    rowfft::pack_rows<L, 9>(lds, tws, tw, N, coef);
     __syncthreads();
-    fft_stages<L2, T, 9, 1>(lds, tws, 1.0);
+    rowfft::stages<L2, T, 9, 1>(lds, tws, 1.0);
     const double fc = two_omega * mu[j];
     const double ic2 = 1.0 / cos2[j];
     const double wv = w[j] / (L * cos2[j]), we = w[j] / L;
@@ -310,13 +195,13 @@ __global__ __launch_bounds__(AdjCfg<L>::T) void k_swe_grid_adj(const double2* __
         lds[3 * L2 + k] = gv;
     }
     __syncthreads();
-    fft_stages<L2, T, 4, 1>(lds, tws, -1.0);
+    rowfft::stages<L2, T, 4, 1>(lds, tws, -1.0);
     double2* out = Ga + ((long long)s * J + j) * (N + 1) * 4;
     for (int m = threadIdx.x; m <= N; m += T) {
         const double c = (m == 0) ? 1.0 : 2.0;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const double2 X = unpack_analysis<L>(lds + f * L2, tws, m);
+            const double2 X = rowfft::unpack<L>(lds + f * L2, tws, m);
             out[(long long)m * 4 + f] = cscale(c, X);
         }
     }
@@ -484,7 +369,7 @@ template <int L>
 hipError_t grid_adj_t(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S, double omega,
                       hipStream_t st) {
     dim3 g(pl->J, S);
-    k_swe_grid_adj<L><<<g, AdjCfg<L>::T, 0, st>>>(FIs, FIl, pl->tw, pl->mu, pl->cos2, pl->w, Ga, pl->N, pl->J,
+    k_swe_grid_adj<L><<<g, Cfg<L>::T, 0, st>>>(FIs, FIl, pl->tw, pl->mu, pl->cos2, pl->w, Ga, pl->N, pl->J,
                                                    2.0 * omega);
     return hipGetLastError();
 }

@@ -102,15 +102,21 @@ hipError_t timed(int kclass, hipStream_t st, F launch) {
     return e;
 }
 
+// combine = false leaves F_E, F_I unformed: the analyses stay in t.cout.
 int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double2* state, double2* fi,
-                  double2* fe, const TendWS& t, hipStream_t st) {
+                  double2* fe, const TendWS& t, hipStream_t st, bool combine = true) {
     if (fe) {
-        HIPCHK(launch_swe_prep(pl, p.a, state, t.cin, nst, st));
-        HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn(pl, t.cin, t.FI, 4, nst, pl->nmax, st); }));
+        if (pl->prec == SHX_FP64) {
+            HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn_swe(pl, p.a, state, t.FI, nst, st); }));
+        } else {
+            HIPCHK(launch_swe_prep(pl, p.a, state, t.cin, nst, st));
+            HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st,
+                         [&] { return launch_leg_syn(pl, t.cin, t.FI, 4, nst, pl->nmax, st); }));
+        }
         HIPCHK(timed(SHX_KC_GRID, st, [&] { return launch_swe_grid(pl, t.FI, t.G, nst, p.omega, st); }));
         HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] { return launch_leg_an(pl, t.G, t.cout, 5, nst, pl->nmax, st); }));
     }
-    HIPCHK(launch_swe_combine(pl, p, t.cout, state, fi, fe, nst, st));
+    if (combine) HIPCHK(launch_swe_combine(pl, p, t.cout, state, fi, fe, nst, st));
     return SHX_OK;
 }
 
@@ -133,14 +139,18 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
             wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
         }
         const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
+        // the F of node m (m >= 1) is formed inside this node update from t.cout
         HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
-            return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi_new, fe_new, fi_old, fe_old, tau, st);
+            return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi_new, fe_new, fi_old, fe_old, tau,
+                                   m > 0 ? t.cout : nullptr, st);
         }));
         const size_t o = (size_t)(m + 1) * ns3;
-        int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st);
+        int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st, false);
         if (rc) return rc;
         if (rec) HIPCHK(hipMemcpyAsync(rec + (size_t)m * ns3, th + o, ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
     }
+    const size_t oM = (size_t)M * ns3;
+    HIPCHK(launch_swe_combine(pl, lv->p, t.cout, th + oM, fi_new + oM, fe_new + oM, 1, st));
     return SHX_OK;
 }
 

@@ -32,6 +32,60 @@ __host__ __device__ inline double eps_nm(int n, int m) {
     return sqrt((nn * nn - mm * mm) / (4.0 * nn * nn - 1.0));
 }
 
+// ------------------------------------------------ tendency input rows
+// The four grid fields of the shallow-water tendency at (m, n), n <= N+1,
+// from a state (Phi', zeta, delta), each [nspec]: zeta, Phi' (zero above N)
+// and the cos-weighted wind (U, V) = (u, v) cos(phi) from the stream
+// function psi = -zeta / L_n and velocity potential chi = -delta / L_n
+// (L_n = n (n+1) / a^2, zero at n = 0):
+//   U_n = [(n-1) eps_n psi_{n-1} - (n+2) eps_{n+1} psi_{n+1} + i m chi_n] / a,
+//   V_n = [i m psi_n - (n-1) eps_n chi_{n-1} + (n+2) eps_{n+1} chi_{n+1}] / a.
+__device__ inline void swe_prep_row(const double2* __restrict__ state, long long nspec, int N, double a, int m,
+                                    int n, double2 o[4]) {
+    const double2* phi = state;
+    const double2* zeta = state + nspec;
+    const double2* delta = zeta + nspec;
+    const double a2 = a * a;
+    auto get = [&](const double2* x, int nn) -> double2 {
+        if (nn < m || nn > N || nn < 1) return make_double2(0.0, 0.0);
+        const double L = nn * (nn + 1.0) / a2;
+        const double2 v = x[spec_idx(N, m, nn)];
+        return make_double2(-v.x / L, -v.y / L);
+    };
+    const double c_dn = (n - 1.0) * eps_nm(n, m);
+    const double c_up = (n + 2.0) * eps_nm(n + 1, m);
+    const double2 psd = get(zeta, n - 1), ps0 = get(zeta, n), psu = get(zeta, n + 1);
+    const double2 chd = get(delta, n - 1), ch0 = get(delta, n), chu = get(delta, n + 1);
+    const double ia = 1.0 / a;
+    const double2 U = make_double2(c_dn * psd.x - c_up * psu.x - m * ch0.y, c_dn * psd.y - c_up * psu.y + m * ch0.x);
+    const double2 V = make_double2(-m * ps0.y - c_dn * chd.x + c_up * chu.x, m * ps0.x - c_dn * chd.y + c_up * chu.y);
+    o[0] = (n <= N) ? zeta[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+    o[1] = (n <= N) ? phi[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+    o[2] = make_double2(ia * U.x, ia * U.y);
+    o[3] = make_double2(ia * V.x, ia * V.y);
+}
+
+// ------------------------------------------------------ XCD-aware blocks
+// Workgroups go to the 8 XCDs of the chip round robin by hardware id, and
+// each XCD has its own L2.  A Legendre launch has gx blocks per (order m,
+// parity p); they all stage the same operand of order m.  With the blocks
+// numbered so that every block of an order runs on one XCD, the repeated
+// staging reads hit that XCD's L2; orders are dealt to the XCDs round robin
+// (m = xcd, xcd + 8, ...), which keeps the XCDs' shares of work even.
+struct LegTile {
+    int x, p, m;
+};
+__device__ inline LegTile leg_tile(int gx, int nm) {
+    const int hw = blockIdx.x, per_m = 2 * gx;
+    if (nm % 8 == 0) {
+        const int xcd = hw % 8, slot = hw / 8;
+        const int i = slot / per_m, r = slot - i * per_m;
+        return {r % gx, r / gx, xcd + 8 * i};
+    }
+    const int r = hw % per_m;
+    return {r % gx, r / gx, hw / per_m};
+}
+
 // -------------------------------------------------------------------- plans
 struct shx_plan {
     int N = 0, J = 0, I = 0, prec = 0, dev = 0;
@@ -84,6 +138,10 @@ struct Mat9x9 {
 hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st);
 hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, int F, int S,
                           int nmax_use, hipStream_t st);
+// Synthesis of the tendency's four grid fields straight from S states
+// [S][3][nspec] (FP64 plans): swe_prep_row feeds the staging.
+hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
+                              hipStream_t st);
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
                          int nmax_use, hipStream_t st);
 // legendre_mixed.hip (plans with a reduced working precision)
@@ -116,10 +174,12 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
                              double2* out, int S, hipStream_t st);
 hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const double2* state,
                              double2* fi, int S, hipStream_t st);
+// cout_m != nullptr (m >= 1): the new F at node m is formed from these
+// analyses of node m's tendency inside the node update (and stored).
 hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
-                           double h, const double2* theta0, double2* theta, const double2* fi,
-                           const double2* fe, const double2* fi_old, const double2* fe_old,
-                           const double2* tau, hipStream_t st);
+                           double h, const double2* theta0, double2* theta, double2* fi, double2* fe,
+                           const double2* fi_old, const double2* fe_old, const double2* tau,
+                           const double2* cout_m, hipStream_t st);
 hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc,
                            int i0, int i1, const double2* src, double2* dst, double2* dst2, hipStream_t st);
 // Copies of node 0 of up to 6 node arrays to node ranges of (other) node arrays.

@@ -9,7 +9,8 @@
 //   synthesis  E_m(mu_j) = sum_{p=0 rows} xi P,  O_m(mu_j) = sum_{p=1 rows} xi P,
 //              north = E + O, south = E - O;
 //   analysis   xi^m_n = sum_{j < J/2} P^m_n(mu_j) (g_north +/- g_south).
-// The tables are built once per plan by an FP64 recurrence on the device and
+// The tables are built once per plan by a double-double recurrence (FP64
+// operations) on the device, rounded to FP64, and
 // kept in two layouts so that both kernels read them with unit stride across
 // the 64 lanes of a wavefront: psyn[m][p][k][jp] (lanes = latitudes) and
 // pan[m][p][jp][k] (lanes = degrees).  The second operand of each
@@ -19,11 +20,70 @@
 
 namespace {
 
-constexpr int UNR = 8;
+constexpr int UNR = 8;   // table loads in flight per lane
+
+// Double-double arithmetic (an unevaluated sum hi + lo of two FP64 numbers,
+// about 106 significant bits) from FP64 operations: error-free sum (Knuth)
+// and product (FMA), division and square root by one correction step each.
+// The error-free transformations need every product and sum rounded on its
+// own, so floating-point contraction is switched off in this part of the
+// file (the backend would otherwise fuse a product into a later sum).
+#pragma clang fp contract(off)
+struct dd {
+    double h, l;
+};
+__device__ __forceinline__ dd dd_norm(double a, double b) {    // |a| >= |b|
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_sub(dd a, dd b) {
+    const double s = a.h - b.h;
+    const double bb = s - a.h;
+    const double e = (a.h - (s - bb)) + (-b.h - bb);
+    return dd_norm(s, e + (a.l - b.l));
+}
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+    const double p = a.h * b.h;
+    double e = fma(a.h, b.h, -p);
+    e = fma(a.h, b.l, e);
+    e = fma(a.l, b.h, e);
+    return dd_norm(p, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+    const double p = a.h * b;
+    double e = fma(a.h, b, -p);
+    e = fma(a.l, b, e);
+    return dd_norm(p, e);
+}
+__device__ __forceinline__ dd dd_div(dd a, dd b) {
+    const double q1 = a.h / b.h;
+    const dd r = dd_sub(a, dd_mul_d(b, q1));
+    const double q2 = r.h / b.h;
+    const dd r2 = dd_sub(r, dd_mul_d(b, q2));
+    const double q3 = r2.h / b.h;
+    const dd q = dd_norm(q1, q2);
+    return dd_norm(q.h, q.l + q3);
+}
+__device__ __forceinline__ dd dd_sqrt(dd a) {                  // a > 0
+    const double x = sqrt(a.h);
+    const double p = x * x;
+    const double e = fma(x, x, -p);
+    const dd r = dd_sub(a, dd{p, e});
+    return dd_norm(x, r.h / (2.0 * x));
+}
+// eps^m_n = sqrt((n^2 - m^2) / (4 n^2 - 1)) in double-double (n > m).
+__device__ __forceinline__ dd dd_eps(int n, int m) {
+    return dd_sqrt(dd_div(dd{(double)n * n - (double)m * m, 0.0}, dd{4.0 * n * n - 1.0, 0.0}));
+}
 
 // P^m_n(mu_j) for one (m, jp) by the standard recurrence of the orthonormal
 // functions: P^0_0 = 1/sqrt(2); P^m_m = sqrt((2m+1)/(2m)) sin(theta) P^{m-1}_{m-1};
 // P^m_{m+1} = sqrt(2m+3) mu P^m_m; eps^m_n P^m_n = mu P^m_{n-1} - eps^m_{n-1} P^m_{n-2}.
+// The recurrence runs in double-double from the FP64 mu and sin(theta) and
+// each value is rounded to FP64: in plain FP64 the forward recurrence
+// amplifies rounding errors roughly like n^2 near the poles (about 1e-12 of
+// the column maximum at degree 1000), which the Laplacian's n(n+1) turns
+// into visible errors of the divergence tendency at T1023.
 __global__ void k_plm_table(const double* __restrict__ mu, const double* __restrict__ sint,
                             const long long* __restrict__ off, double* __restrict__ psyn,
                             double* __restrict__ pan, int N, int nmax, int Jh) {
@@ -31,49 +91,62 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
     const int m = blockIdx.y;
     if (jp >= Jh) return;
     const double x = mu[jp], s = sint[jp];
-    double pmm = 0.70710678118654752440;   // 1/sqrt(2)
-    for (int k = 1; k <= m; ++k) pmm *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+    dd pmm = dd_sqrt(dd{0.5, 0.0});
+    for (int k = 1; k <= m; ++k)
+        pmm = dd_mul_d(dd_mul(pmm, dd_sqrt(dd_div(dd{2.0 * k + 1.0, 0.0}, dd{2.0 * k, 0.0}))), s);
     const int K0 = kcount(nmax, m, 0), K1 = kcount(nmax, m, 1);
     double* ps0 = psyn + off[2 * m];
     double* ps1 = psyn + off[2 * m + 1];
     double* pa0 = pan + off[2 * m];
     double* pa1 = pan + off[2 * m + 1];
-    double p2 = 0.0, p1 = pmm;   // P_{n-2}, P_{n-1}
+    dd p2{0.0, 0.0}, p1 = pmm;   // P_{n-2}, P_{n-1}
+    dd e_prev = (m + 1 <= nmax) ? dd_eps(m + 1, m) : dd{1.0, 0.0};
     for (int n = m; n <= nmax; ++n) {
-        double pn;
-        if (n == m) pn = pmm;
-        else if (n == m + 1) pn = sqrt(2.0 * m + 3.0) * x * pmm;
-        else pn = (x * p1 - eps_nm(n - 1, m) * p2) / eps_nm(n, m);
+        dd pn;
+        if (n == m) {
+            pn = pmm;
+        } else if (n == m + 1) {
+            pn = dd_mul_d(dd_mul(dd_sqrt(dd{2.0 * m + 3.0, 0.0}), pmm), x);
+        } else {
+            const dd en = dd_eps(n, m);
+            pn = dd_div(dd_sub(dd_mul_d(p1, x), dd_mul(e_prev, p2)), en);
+            e_prev = en;
+        }
         if (n > m) { p2 = p1; p1 = pn; }
+        const double v = pn.h + pn.l;
         const int p = (n - m) & 1, k = (n - m) >> 1;
         if (p == 0) {
-            ps0[(long long)k * Jh + jp] = pn;
-            pa0[(long long)jp * K0 + k] = pn;
+            ps0[(long long)k * Jh + jp] = v;
+            pa0[(long long)jp * K0 + k] = v;
         } else {
-            ps1[(long long)k * Jh + jp] = pn;
-            pa1[(long long)jp * K1 + k] = pn;
+            ps1[(long long)k * Jh + jp] = v;
+            pa1[(long long)jp * K1 + k] = v;
         }
     }
 }
+#pragma clang fp contract(fast)
 
 // Synthesis: out[s][p][jp][m][f0+f] = sum_k P[m][p][k][jp] cin[s][ext(m, m+2k+p)][f0+f].
-// grid (ceil(Jh/64), N+1, 2), 256 threads: lane = latitude jp, the four
+// gx (N+1) 2 blocks (gx = ceil(Jh/64), numbered by leg_tile), 256 threads: lane = latitude jp, the four
 // wavefronts split the degree sum into quarters.  The coefficients of this
 // (m, p) are the same for every lane: they are staged in LDS (dynamic LDS:
 // K * NF double2) and read by broadcast.  Wave 0 adds the partial sums of
-// waves 1..3 (LDS) in a fixed order.
-template <int NF>
+// waves 1..3 (LDS) in a fixed order.  With PREP, cin holds states
+// [S][3][nspec] and the staged rows are the tendency's grid fields
+// (swe_prep_row; NF = F = 4).
+template <int NF, bool PREP = false>
 __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn,
                                                  const long long* __restrict__ off,
                                                  const double2* __restrict__ cin,
                                                  double2* __restrict__ out, int N, int nmax_use,
                                                  int Jh, int F, int f0, int S, long long cin_stride,
-                                                 long long out_stride) {
+                                                 long long out_stride, int gx, long long nspec, double a) {
     extern __shared__ double2 csh[];                    // [K][NF]
     __shared__ double red[3][2 * NF][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int jp = blockIdx.x * 64 + lane;
-    const int m = blockIdx.y, p = blockIdx.z;
+    const LegTile tile = leg_tile(gx, N + 1);
+    const int jp = tile.x * 64 + lane;
+    const int m = tile.m, p = tile.p;
     const bool active = jp < Jh;
     const int K = kcount(nmax_use, m, p);
     const int kq = (K + 3) / 4;
@@ -81,11 +154,21 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
     const double* P = psyn + off[2 * m + p] + (active ? jp : 0);
     const long long e0 = ext_idx(N, m, m + p);
     for (int s = 0; s < S; ++s) {
-        const double2* cg = cin + s * cin_stride + e0 * F + f0;
         if (s > 0) __syncthreads();                     // previous state's readers are done
-        for (int i = threadIdx.x; i < K * NF; i += 256) {
-            const int kk = i / NF, f = i - kk * NF;
-            csh[i] = cg[(long long)(2 * kk) * F + f];
+        if constexpr (PREP) {
+            static_assert(NF == 4, "the tendency synthesis has four fields");
+            for (int kk = threadIdx.x; kk < K; kk += 256) {
+                double2 o[4];
+                swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * kk, o);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) csh[kk * 4 + f] = o[f];
+            }
+        } else {
+            const double2* cg = cin + s * cin_stride + e0 * F + f0;
+            for (int i = threadIdx.x; i < K * NF; i += 256) {
+                const int kk = i / NF, f = i - kk * NF;
+                csh[i] = cg[(long long)(2 * kk) * F + f];
+            }
         }
         __syncthreads();
         const double2* c = csh;
@@ -142,7 +225,7 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
 }
 
 // Analysis: cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
-// grid (ceil(K/64), N+1, 2), 256 threads: lane = degree row k, the four
+// gx (N+1) 2 blocks (gx = ceil(K/64), numbered by leg_tile), 256 threads: lane = degree row k, the four
 // wavefronts split the latitude sum into quarters.  The combined Fourier
 // data g_jp = G_north +/- G_south of this (m, p) is staged in LDS once per
 // state (dynamic LDS: Jh * NF double2) and read by broadcast; the partial
@@ -153,14 +236,15 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                                                 const double2* __restrict__ G,
                                                 double2* __restrict__ cout, int N, int nmax_tab,
                                                 int nmax_use, int J, int F, int f0, int S,
-                                                long long G_stride, long long cout_stride) {
+                                                long long G_stride, long long cout_stride, int gx) {
     extern __shared__ double2 gsh[];                    // [Jh][NF]
     __shared__ double red[3][2 * NF][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + lane;
-    const int m = blockIdx.y, p = blockIdx.z;
+    const LegTile tile = leg_tile(gx, N + 1);
+    const int k = tile.x * 64 + lane;
+    const int m = tile.m, p = tile.p;
     const int K = kcount(nmax_use, m, p);
-    if (blockIdx.x * 64 >= K) return;                   // whole block idle (uniform)
+    if (tile.x * 64 >= K) return;                       // whole block idle (uniform)
     const bool active = k < K;
     const int Ktab = kcount(nmax_tab, m, p);
     const int Jh = J / 2;
@@ -235,20 +319,21 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
 template <int NF>
 void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S,
                int nmax_use, hipStream_t st) {
-    dim3 grid((pl->Jh + 63) / 64, pl->N + 1, 2);
+    const int gx = (pl->Jh + 63) / 64;
     const size_t lds = (size_t)kcount(nmax_use, 0, 0) * NF * sizeof(double2);
-    k_leg_syn<NF><<<grid, 256, lds, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F, f0, S,
-                                       pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F);
+    k_leg_syn<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F,
+                                                       f0, S, pl->nspec_e * F,
+                                                       (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, 0.0);
 }
 
 template <int NF>
 void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
               hipStream_t st) {
-    const int kmax = kcount(nmax_use, 0, 0);
-    dim3 grid((kmax + 63) / 64, pl->N + 1, 2);
+    const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
     const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
-    k_leg_an<NF><<<grid, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use, pl->J, F,
-                                      f0, S, (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F);
+    k_leg_an<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
+                                                      pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
+                                                      pl->nspec_e * F, gx);
 }
 
 }  // namespace
@@ -276,6 +361,17 @@ hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, 
             default: syn_chunk<8>(pl, cin, out, F, f0, S, nmax_use, st); break;
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
+                              hipStream_t st) {
+    if (pl->prec != SHX_FP64) return hipErrorInvalidValue;
+    const int gx = (pl->Jh + 63) / 64;
+    const size_t lds = (size_t)kcount(pl->nmax, 0, 0) * 4 * sizeof(double2);
+    k_leg_syn<4, true><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, state, out, pl->N, pl->nmax,
+                                                            pl->Jh, 4, 0, S, 3 * pl->nspec,
+                                                            (long long)pl->J * (pl->N + 1) * 4, gx, pl->nspec, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,213 @@
+// Real latitude-row FFTs in LDS, shared by the transform, tendency and
+// adjoint kernels (the longitude sums of eq. fourier_transform and eq.
+// spectral_to_physical_space).
+//
+// A real row of length L (2^k or 3 * 2^k) goes through a complex FFT of
+// length L2 = L/2 of z_k = x_{2k} + i x_{2k+1}:
+//   synthesis:  Z_m = (X_m + conj X_{L2-m}) + i e^{2 pi i m / L} (X_m - conj X_{L2-m}),
+//               z = sum_m Z_m e^{2 pi i m k / L2}  ->  x_{2k} = Re z_k, x_{2k+1} = Im z_k;
+//   analysis:   Z = FFT_{L2}(z),  E_m = (Z_m + conj Z_{-m}) / 2,  O_m = (Z_m - conj Z_{-m}) / (2 i),
+//               X_m = E_m + e^{-2 pi i m / L} O_m.
+// The complex FFT is a Stockham transform in LDS (radix-4 stages, at most one
+// radix-2 stage, then the radix-3 stage): each stage loads its butterflies
+// into registers, meets a barrier and writes back.  Twiddles e^{-2 pi i t / L},
+// t < L2, come from a table computed on the host in quad precision and copied
+// to LDS; e^{-2 pi i t / L2} is entry 2t, and the upper half of the circle is
+// the negated lower half.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rowfft {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-register DFT of size R with exponent sign sg (-1 forward, +1 inverse).
+template <int R>
+__device__ __forceinline__ void dft(double2* v, double sg);
+
+template <>
+__device__ __forceinline__ void dft<2>(double2* v, double) {
+    const double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(double2* v, double sg) {
+    const double2 s0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+    const double2 s1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+    const double2 s2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+    const double2 s3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+    const double2 r3 = make_double2(-sg * s3.y, sg * s3.x);   // sg * i * s3
+    v[0] = make_double2(s0.x + s2.x, s0.y + s2.y);
+    v[2] = make_double2(s0.x - s2.x, s0.y - s2.y);
+    v[1] = make_double2(s1.x + r3.x, s1.y + r3.y);
+    v[3] = make_double2(s1.x - r3.x, s1.y - r3.y);
+}
+
+template <>
+__device__ __forceinline__ void dft<3>(double2* v, double sg) {
+    const double c = 0.86602540378443864676;   // sin(2 pi / 3)
+    const double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
+    const double2 d = make_double2(v[1].x - v[2].x, v[1].y - v[2].y);
+    const double2 a = v[0];
+    const double2 mm = make_double2(a.x - 0.5 * t.x, a.y - 0.5 * t.y);
+    const double2 r = make_double2(-sg * c * d.y, sg * c * d.x);   // sg * i * c * d
+    v[0] = make_double2(a.x + t.x, a.y + t.y);
+    v[1] = make_double2(mm.x + r.x, mm.y + r.y);
+    v[2] = make_double2(mm.x - r.x, mm.y - r.y);
+}
+
+// e^{-2 pi i idx / (2 half)} from the half table tws[0..half).
+__device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half) {
+    const double2 w = tws[idx < half ? idx : idx - half];
+    return idx < half ? w : make_double2(-w.x, -w.y);
+}
+
+// Launch shape for real rows of length L: T threads per workgroup, one per
+// complex point of the half-length FFT (at least 64, at most 1024).
+template <int L>
+struct Cfg {
+    static constexpr int L2 = L / 2;
+    static constexpr int T0 = L2 < 64 ? 64 : (L2 > 1024 ? 1024 : L2);
+    static constexpr int T = (T0 + 63) / 64 * 64;
+};
+
+// Stockham stages for NR complex rows of length C (row stride C) held in LDS,
+// T threads; Ns is the length of the sub-transforms already done.  tws is
+// the LDS twiddle table of the real length 2C (C entries).
+template <int C, int T, int NR, int Ns>
+__device__ __forceinline__ void stages(double2* buf, const double2* tws, double sg) {
+    constexpr int rem = C / Ns;
+    if constexpr (rem > 1) {
+        constexpr int R = (rem % 4 == 0) ? 4 : ((rem % 2 == 0) ? 2 : 3);
+        constexpr int NB = C / R;
+        constexpr int ITEMS = NR * NB;
+        constexpr int IPT = (ITEMS + T - 1) / T;
+        constexpr int TWS = C / (Ns * R) * 2;
+        double2 v[IPT][R];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = threadIdx.x + it * T;
+            if (ITEMS % T == 0 || item < ITEMS) {
+                const int row = item / NB, j = item - row * NB, k = j % Ns;
+                const double2* b = buf + row * C;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double2 x = b[j + r * NB];
+                    if (Ns > 1 && r > 0) {
+                        double2 w = tw_half(tws, r * k * TWS, C);
+                        w.y *= -sg;
+                        x = cmul(x, w);
+                    }
+                    v[it][r] = x;
+                }
+                dft<R>(v[it], sg);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = threadIdx.x + it * T;
+            if (ITEMS % T == 0 || item < ITEMS) {
+                const int row = item / NB, j = item - row * NB, k = j % Ns;
+                const int base = (j / Ns) * Ns * R + k;
+                double2* b = buf + row * C;
+#pragma unroll
+                for (int q = 0; q < R; ++q) b[base + q * Ns] = v[it][q];
+            }
+        }
+        __syncthreads();
+        stages<C, T, NR, Ns * R>(buf, tws, sg);
+    }
+}
+
+// Synthesis input of NR real rows of length L: rows[f * L2 + m] = Z_m of row
+// f, and the LDS twiddle table tws[0..L2) from the global table twg.  The
+// coefficients X_m (m <= N < L2; zero above N, Im X_0 ignored) come from
+// coef(f, m).  Thread t owns the index pairs (m, L2 - m), m = t, t + T, ...
+// < L2/2; the pair of m = 0 is the middle index L2/2 (e^{2 pi i (L2/2) / L} = i,
+// so Z_{L2/2} = 2 conj X_{L2/2}).  Every coefficient is read once, and all
+// global loads of a thread are issued before any of them is used.  Caller
+// syncs.
+template <int L, int NR, class Coef>
+__device__ __forceinline__ void pack_rows(double2* rows, double2* tws, const double2* __restrict__ twg, int N,
+                                          Coef coef) {
+    constexpr int L2 = L / 2, H = L2 / 2, T = Cfg<L>::T;
+    constexpr int IP = (H + T - 1) / T;
+    constexpr int ITW = (L2 + T - 1) / T;
+    double2 twv[ITW];
+#pragma unroll
+    for (int it = 0; it < ITW; ++it) {
+        const int t = threadIdx.x + it * T;
+        if (t < L2) twv[it] = twg[t];
+    }
+    double2 xa[IP][NR], xb[IP][NR];
+#pragma unroll
+    for (int ip = 0; ip < IP; ++ip) {
+        const int m = threadIdx.x + ip * T;
+        const int j = (m == 0) ? H : L2 - m;
+        const bool on = m < H;
+#pragma unroll
+        for (int f = 0; f < NR; ++f) {
+            xa[ip][f] = (on && m <= N) ? coef(f, m) : make_double2(0.0, 0.0);
+            xb[ip][f] = (on && j <= N) ? coef(f, j) : make_double2(0.0, 0.0);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < ITW; ++it) {
+        const int t = threadIdx.x + it * T;
+        if (t < L2) tws[t] = twv[it];
+    }
+#pragma unroll
+    for (int ip = 0; ip < IP; ++ip) {
+        const int m = threadIdx.x + ip * T, j = L2 - m;
+        if (m >= H) continue;
+        if (m == 0) {
+#pragma unroll
+            for (int f = 0; f < NR; ++f) {
+                const double a = xa[ip][f].x;                  // Z_0 = X_0 + i X_0, X_0 real
+                rows[f * L2] = make_double2(a, a);
+                rows[f * L2 + H] = make_double2(2.0 * xb[ip][f].x, -2.0 * xb[ip][f].y);
+            }
+            continue;
+        }
+        // twv[ip] = tw[m] (same index as the twiddle copy); e^{+2 pi i m / L} =
+        // conj(tw[m]), e^{+2 pi i j / L} = -tw[m]
+        const double2 tm = twv[ip];
+        const double2 em = make_double2(tm.x, -tm.y);
+        const double2 ej = make_double2(-tm.x, -tm.y);
+#pragma unroll
+        for (int f = 0; f < NR; ++f) {
+            const double2 A = xa[ip][f], B = xb[ip][f];
+            {   // Z_m, partner conj X_j
+                const double2 s = make_double2(A.x + B.x, A.y - B.y);
+                const double2 d = make_double2(A.x - B.x, A.y + B.y);
+                const double2 ed = cmul(em, d);
+                rows[f * L2 + m] = make_double2(s.x - ed.y, s.y + ed.x);
+            }
+            {   // Z_j, partner conj X_m
+                const double2 s = make_double2(B.x + A.x, B.y - A.y);
+                const double2 d = make_double2(B.x - A.x, B.y + A.y);
+                const double2 ed = cmul(ej, d);
+                rows[f * L2 + j] = make_double2(s.x - ed.y, s.y + ed.x);
+            }
+        }
+    }
+}
+
+// X_m (m <= N) of the real row whose half-length FFT is in `row`.
+template <int L>
+__device__ __forceinline__ double2 unpack(const double2* row, const double2* tws, int m) {
+    constexpr int L2 = L / 2;
+    const double2 z = row[m];
+    const double2 zc = row[(L2 - m) % L2];
+    const double2 E = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+    const double2 O = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    const double2 wo = cmul(tws[m], O);
+    return make_double2(E.x + wo.x, E.y + wo.y);
+}
+
+}  // namespace rowfft

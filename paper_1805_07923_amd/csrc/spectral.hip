@@ -59,29 +59,47 @@ __global__ void k_swe_prep(const int* __restrict__ ord_e, const int* __restrict_
     const long long e = (long long)blockIdx.x * TB + threadIdx.x;
     const int s = blockIdx.y;
     if (e >= nspec_e || s >= S) return;
-    const int m = ord_e[e], n = deg_e[e];
-    const double2* phi = state + (long long)s * 3 * nspec;
-    const double2* zeta = phi + nspec;
-    const double2* delta = zeta + nspec;
-    const double a2 = a * a;
-    auto get = [&](const double2* x, int nn) -> double2 {
-        if (nn < m || nn > N || nn < 1) return make_double2(0.0, 0.0);
-        const double L = nn * (nn + 1.0) / a2;
-        const double2 v = x[spec_idx(N, m, nn)];
-        return make_double2(-v.x / L, -v.y / L);   // -x / L_n: psi or chi
+    double2 o[4];
+    swe_prep_row(state + (long long)s * 3 * nspec, nspec, N, a, ord_e[e], deg_e[e], o);
+    double2* c = cin + ((long long)s * nspec_e + e) * 4;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) c[f] = o[f];
+}
+
+// F_E (from the weighted analyses A, B, C, D, E in the extended layout,
+// cout = [ext][5]) and F_I (from the state st = [3][nspec]) at the
+// coefficient i = (m, n).
+__device__ __forceinline__ void combine_one(const double2* __restrict__ cout, const double2* __restrict__ st,
+                                            int N, long long nspec, const swe_params& p, long long i, int m, int n,
+                                            double2 fe[3], double2 fi[3]) {
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    const double2* x0 = cout + ext_idx(N, m, n) * 5;
+    const double2* xu = cout + ext_idx(N, m, n + 1) * 5;
+    const double2 zero = make_double2(0.0, 0.0);
+    const bool has_dn = (n - 1 >= m);
+    const double2* xd = has_dn ? cout + ext_idx(N, m, n - 1) * 5 : nullptr;
+    const double cu = n * eps_nm(n + 1, m), cd = (n + 1.0) * eps_nm(n, m);
+    const double ia = 1.0 / p.a;
+    auto div = [&](int X, int Y) {
+        double2 r = cim(m, x0[X]);
+        r = caxpy(cu, xu[Y], r);
+        r = caxpy(-cd, has_dn ? xd[Y] : zero, r);
+        return cscale(ia, r);
     };
-    const double c_dn = (n - 1.0) * eps_nm(n, m);
-    const double c_up = (n + 2.0) * eps_nm(n + 1, m);
-    const double2 psd = get(zeta, n - 1), ps0 = get(zeta, n), psu = get(zeta, n + 1);
-    const double2 chd = get(delta, n - 1), ch0 = get(delta, n), chu = get(delta, n + 1);
-    const double ia = 1.0 / a;
-    double2 U = cadd(make_double2(c_dn * psd.x - c_up * psu.x, c_dn * psd.y - c_up * psu.y), cim(m, ch0));
-    double2 V = cadd(cim(m, ps0), make_double2(-c_dn * chd.x + c_up * chu.x, -c_dn * chd.y + c_up * chu.y));
-    double2* o = cin + ((long long)s * nspec_e + e) * 4;
-    o[0] = (n <= N) ? zeta[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
-    o[1] = (n <= N) ? phi[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
-    o[2] = cscale(ia, U);
-    o[3] = cscale(ia, V);
+    auto curl = [&](int X, int Y) {
+        double2 r = cim(m, x0[Y]);
+        r = caxpy(-cu, xu[X], r);
+        r = caxpy(cd, has_dn ? xd[X] : zero, r);
+        return cscale(ia, r);
+    };
+    const double2 dcd = div(2, 3), dab = div(0, 1), cab = curl(0, 1);
+    fe[0] = make_double2(-dcd.x, -dcd.y);
+    fe[1] = make_double2(-dab.x, -dab.y);
+    fe[2] = caxpy(L, x0[4], cab);
+    const double2 ph = st[i], ze = st[nspec + i], de = st[2 * nspec + i];
+    fi[0] = make_double2(-p.phibar * de.x - p.nu * L * ph.x, -p.phibar * de.y - p.nu * L * ph.y);
+    fi[1] = make_double2(-p.nu * L * ze.x, -p.nu * L * ze.y);
+    fi[2] = make_double2(L * ph.x - p.nu * L * de.x, L * ph.y - p.nu * L * de.y);
 }
 
 // F_E, F_I from the weighted analyses (A, B, C, D, E) and the state.
@@ -93,36 +111,17 @@ __global__ void k_swe_combine(const int* __restrict__ ord, const int* __restrict
     const int s = blockIdx.y;
     if (i >= nspec || s >= S) return;
     const int m = ord[i], n = deg[i];
-    const double L = n * (n + 1.0) / (p.a * p.a);
     const double2* st = state + (long long)s * 3 * nspec;
     if (fe) {
-        const double2* c = cout + (long long)s * nspec_e * 5;
-        const double2* x0 = c + ext_idx(N, m, n) * 5;
-        const double2* xu = c + ext_idx(N, m, n + 1) * 5;
-        const double2 zero = make_double2(0.0, 0.0);
-        const bool has_dn = (n - 1 >= m);
-        const double2* xd = has_dn ? c + ext_idx(N, m, n - 1) * 5 : nullptr;
-        const double cu = n * eps_nm(n + 1, m), cd = (n + 1.0) * eps_nm(n, m);
-        const double ia = 1.0 / p.a;
-        auto div = [&](int X, int Y) {
-            double2 r = cim(m, x0[X]);
-            r = caxpy(cu, xu[Y], r);
-            r = caxpy(-cd, has_dn ? xd[Y] : zero, r);
-            return cscale(ia, r);
-        };
-        auto curl = [&](int X, int Y) {
-            double2 r = cim(m, x0[Y]);
-            r = caxpy(-cu, xu[X], r);
-            r = caxpy(cd, has_dn ? xd[X] : zero, r);
-            return cscale(ia, r);
-        };
-        const double2 dcd = div(2, 3), dab = div(0, 1), cab = curl(0, 1);
+        double2 e[3], f[3];
+        combine_one(cout + (long long)s * nspec_e * 5, st, N, nspec, p, i, m, n, e, f);
         double2* o = fe + (long long)s * 3 * nspec;
-        o[i] = make_double2(-dcd.x, -dcd.y);
-        o[nspec + i] = make_double2(-dab.x, -dab.y);
-        o[2 * nspec + i] = caxpy(L, x0[4], cab);
+        o[i] = e[0];
+        o[nspec + i] = e[1];
+        o[2 * nspec + i] = e[2];
     }
     if (fi) {
+        const double L = n * (n + 1.0) / (p.a * p.a);
         const double2 ph = st[i], ze = st[nspec + i], de = st[2 * nspec + i];
         double2* o = fi + (long long)s * 3 * nspec;
         o[i] = make_double2(-p.phibar * de.x - p.nu * L * ph.x, -p.phibar * de.y - p.nu * L * ph.y);
@@ -176,14 +175,26 @@ __global__ void k_f_implicit(const int* __restrict__ deg, const double2* __restr
 //   b = Theta^0 + sum_j dtQ[m+1][j] (F_I + F_E)^{j,old}
 //       + sum_{j=1}^{m} [dtQE[m+1][j] dF_E^j + dtQD[m+1][j] dF_I^j]
 //       - h F_I^{m+1,old} + tau^{m+1},   Theta^{m+1} = solve(b, h).
-__global__ void k_sdc_node(const int* __restrict__ deg, long long nspec, swe_params p, int m, int M,
-                           NodeWeights wt, double h, const double2* __restrict__ th0,
-                           double2* __restrict__ theta, const double2* __restrict__ fi,
-                           const double2* __restrict__ fe, const double2* __restrict__ fi_old,
-                           const double2* __restrict__ fe_old, const double2* __restrict__ tau) {
+// With cout != nullptr (m >= 1) the new F at node m is not yet formed: it is
+// combined here from the analyses of node m's tendency (cout) and Theta^m,
+// stored to (fi, fe) node m and used directly.
+__global__ void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ deg, int N, long long nspec,
+                           swe_params p, int m, int M, NodeWeights wt, double h, const double2* __restrict__ th0,
+                           double2* __restrict__ theta, double2* __restrict__ fi, double2* __restrict__ fe,
+                           const double2* __restrict__ fi_old, const double2* __restrict__ fe_old,
+                           const double2* __restrict__ tau, const double2* __restrict__ cout) {
     const long long i = (long long)blockIdx.x * TB + threadIdx.x;
     if (i >= nspec) return;
     const long long ns3 = 3 * nspec;
+    double2 fem[3], fim[3];
+    if (cout) {
+        combine_one(cout, theta + m * ns3, N, nspec, p, i, ord[i], deg[i], fem, fim);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            fe[m * ns3 + c * nspec + i] = fem[c];
+            fi[m * ns3 + c * nspec + i] = fim[c];
+        }
+    }
     double2 b[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -193,9 +204,14 @@ __global__ void k_sdc_node(const int* __restrict__ deg, long long nspec, swe_par
             const double2 f = cadd(fi_old[j * ns3 + o], fe_old[j * ns3 + o]);
             acc = caxpy(wt.q[j], f, acc);
         }
-        for (int j = 1; j <= m; ++j) {
+        const int jm = cout ? m - 1 : m;               // nodes read back from memory
+        for (int j = 1; j <= jm; ++j) {
             acc = caxpy(wt.qe[j], csub(fe[j * ns3 + o], fe_old[j * ns3 + o]), acc);
             acc = caxpy(wt.qd[j], csub(fi[j * ns3 + o], fi_old[j * ns3 + o]), acc);
+        }
+        if (cout) {
+            acc = caxpy(wt.qe[m], csub(fem[c], fe_old[m * ns3 + o]), acc);
+            acc = caxpy(wt.qd[m], csub(fim[c], fi_old[m * ns3 + o]), acc);
         }
         acc = caxpy(-h, fi_old[(m + 1) * ns3 + o], acc);
         if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + o]);
@@ -212,25 +228,23 @@ __global__ void k_sdc_node(const int* __restrict__ deg, long long nspec, swe_par
 }
 
 // dst[i][c] = sum_j Pi[i][j] src[j][map(c)], i in [i0, i1); c runs over the
-// coarse coefficients, map(c) is the fine index of the same (m, n).
+// coarse coefficients, map(c) is the fine index of the same (m, n).  One
+// thread per (coefficient, field = blockIdx.y, node i0 + blockIdx.z).
 __global__ void k_restrict(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
-                           long long nsf, long long nsc, Mat9x9 Pi, int nsrc, int i0, int i1,
+                           long long nsf, long long nsc, Mat9x9 Pi, int nsrc, int i0,
                            const double2* __restrict__ src, double2* __restrict__ dst,
                            double2* __restrict__ dst2) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
     if (c >= nsc) return;
+    const int f = blockIdx.y, i = i0 + blockIdx.z;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    for (int i = i0; i < i1; ++i) {
-        for (int f = 0; f < 3; ++f) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int j = 0; j < nsrc; ++j) {
-                const double w = Pi.a[i * nsrc + j];
-                if (w != 0.0) acc = caxpy(w, src[(j * 3 + f) * nsf + fidx], acc);
-            }
-            dst[(i * 3 + f) * nsc + c] = acc;
-            if (dst2) dst2[(i * 3 + f) * nsc + c] = acc;
-        }
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < nsrc; ++j) {
+        const double w = Pi.a[i * nsrc + j];
+        if (w != 0.0) acc = caxpy(w, src[(j * 3 + f) * nsf + fidx], acc);
     }
+    dst[(i * 3 + f) * nsc + c] = acc;
+    if (dst2) dst2[(i * 3 + f) * nsc + c] = acc;
 }
 
 // dst_p[m] = src_p[0] for nodes m = first_p..last_p (element-wise over n3).
@@ -244,6 +258,7 @@ __global__ void k_node_copies(NodeCopies nc, long long n3) {
 }
 
 // tau_c^i = dt [sum_j (Pi Q_f)_{ij} D(F_f^j) - sum_j (Q_c)_{ij} F_c^j], i = 0..nc-1.
+// One thread per (coefficient, field = blockIdx.y, node i = blockIdx.z).
 __global__ void k_fas_tau(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
                           long long nsf, long long nsc, Mat9x9 PQ, Mat9x9 Qc, int nf, int nc, double dt,
                           const double2* __restrict__ fi_f, const double2* __restrict__ fe_f,
@@ -251,25 +266,23 @@ __global__ void k_fas_tau(const int* __restrict__ ordc, const int* __restrict__ 
                           double2* __restrict__ tau) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
     if (c >= nsc) return;
+    const int f = blockIdx.y, i = blockIdx.z;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    for (int i = 0; i < nc; ++i) {
-        for (int f = 0; f < 3; ++f) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int j = 0; j < nf; ++j) {
-                const long long o = (j * 3 + f) * nsf + fidx;
-                acc = caxpy(PQ.a[i * nf + j], cadd(fi_f[o], fe_f[o]), acc);
-            }
-            for (int j = 0; j < nc; ++j) {
-                const long long o = (j * 3 + f) * nsc + c;
-                acc = caxpy(-Qc.a[i * nc + j], cadd(fi_c[o], fe_c[o]), acc);
-            }
-            tau[(i * 3 + f) * nsc + c] = cscale(dt, acc);
-        }
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < nf; ++j) {
+        const long long o = (j * 3 + f) * nsf + fidx;
+        acc = caxpy(PQ.a[i * nf + j], cadd(fi_f[o], fe_f[o]), acc);
     }
+    for (int j = 0; j < nc; ++j) {
+        const long long o = (j * 3 + f) * nsc + c;
+        acc = caxpy(-Qc.a[i * nc + j], cadd(fi_c[o], fe_c[o]), acc);
+    }
+    tau[(i * 3 + f) * nsc + c] = cscale(dt, acc);
 }
 
 // For fine nodes m = 1..nf-1: X_f^m += Pad(sum_i Pfc[m][i] (X_c^i - X~_c^i)) for
-// X in {Theta, F_I, F_E}; only the coefficients with n <= N_c change.
+// X in {Theta, F_I, F_E}; only the coefficients with n <= N_c change.  One
+// thread per (coarse coefficient, field = blockIdx.y, fine node m = 1 + blockIdx.z).
 __global__ void k_interp(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
                          long long nsf, long long nsc, Mat9x9 P, int nf, int nc,
                          const double2* __restrict__ thc, const double2* __restrict__ thct,
@@ -278,29 +291,20 @@ __global__ void k_interp(const int* __restrict__ ordc, const int* __restrict__ d
                          double2* __restrict__ thf, double2* __restrict__ fif, double2* __restrict__ fef) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
     if (c >= nsc) return;
+    const int f = blockIdx.y, m = 1 + blockIdx.z;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    for (int f = 0; f < 3; ++f) {
-        double2 dth[9], dfi[9], dfe[9];
-        for (int i = 0; i < nc; ++i) {
-            const long long o = (i * 3 + f) * nsc + c;
-            dth[i] = csub(thc[o], thct[o]);
-            dfi[i] = csub(fic[o], fict[o]);
-            dfe[i] = csub(fec[o], fect[o]);
-        }
-        for (int m = 1; m < nf; ++m) {
-            double2 a = make_double2(0.0, 0.0), b = a, d = a;
-            for (int i = 0; i < nc; ++i) {
-                const double w = P.a[m * nc + i];
-                a = caxpy(w, dth[i], a);
-                b = caxpy(w, dfi[i], b);
-                d = caxpy(w, dfe[i], d);
-            }
-            const long long o = (m * 3 + f) * nsf + fidx;
-            thf[o] = cadd(thf[o], a);
-            fif[o] = cadd(fif[o], b);
-            fef[o] = cadd(fef[o], d);
-        }
+    double2 a = make_double2(0.0, 0.0), b = a, d = a;
+    for (int i = 0; i < nc; ++i) {
+        const long long o = (i * 3 + f) * nsc + c;
+        const double w = P.a[m * nc + i];
+        a = caxpy(w, csub(thc[o], thct[o]), a);
+        b = caxpy(w, csub(fic[o], fict[o]), b);
+        d = caxpy(w, csub(fec[o], fect[o]), d);
     }
+    const long long o = (m * 3 + f) * nsf + fidx;
+    thf[o] = cadd(thf[o], a);
+    fif[o] = cadd(fif[o], b);
+    fef[o] = cadd(fef[o], d);
 }
 
 // Per-block partial sums for the residual: [blk][M+1] of ||r^m||^2 (m >= 1)
@@ -418,18 +422,21 @@ hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const doub
 }
 
 hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
-                           double h, const double2* theta0, double2* theta, const double2* fi,
-                           const double2* fe, const double2* fi_old, const double2* fe_old,
-                           const double2* tau, hipStream_t st) {
-    k_sdc_node<<<nblocks(pl->nspec), TB, 0, st>>>(pl->deg, pl->nspec, p, m, M, wts, h, theta0, theta, fi, fe,
-                                                   fi_old, fe_old, tau);
+                           double h, const double2* theta0, double2* theta, double2* fi, double2* fe,
+                           const double2* fi_old, const double2* fe_old, const double2* tau,
+                           const double2* cout_m, hipStream_t st) {
+    if (cout_m && m < 1) return hipErrorInvalidValue;
+    k_sdc_node<<<nblocks(pl->nspec), TB, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, m, M, wts, h, theta0,
+                                                   theta, fi, fe, fi_old, fe_old, tau, cout_m);
     return hipGetLastError();
 }
 
 hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc, int i0,
                            int i1, const double2* src, double2* dst, double2* dst2, hipStream_t st) {
-    k_restrict<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
-                                                       coarse->nspec, Pi, nsrc, i0, i1, src, dst, dst2);
+    if (i1 <= i0) return hipSuccess;
+    dim3 g(nblocks(coarse->nspec), 3, i1 - i0);
+    k_restrict<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec, coarse->nspec, Pi,
+                                 nsrc, i0, src, dst, dst2);
     return hipGetLastError();
 }
 
@@ -441,9 +448,9 @@ hipError_t launch_node_copies(const NodeCopies& nc, long long n3, hipStream_t st
 hipError_t launch_fas_tau(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ, const Mat9x9& Qc,
                           int nf, int nc, double dt, const double2* fi_f, const double2* fe_f,
                           const double2* fi_c, const double2* fe_c, double2* tau, hipStream_t st) {
-    k_fas_tau<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
-                                                      coarse->nspec, PQ, Qc, nf, nc, dt, fi_f, fe_f, fi_c, fe_c,
-                                                      tau);
+    dim3 g(nblocks(coarse->nspec), 3, nc);
+    k_fas_tau<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec, coarse->nspec, PQ, Qc,
+                                nf, nc, dt, fi_f, fe_f, fi_c, fe_c, tau);
     return hipGetLastError();
 }
 
@@ -451,9 +458,10 @@ hipError_t launch_interp(const shx_plan* fine, const shx_plan* coarse, const Mat
                          const double2* th_c, const double2* th_ct, const double2* fi_c, const double2* fi_ct,
                          const double2* fe_c, const double2* fe_ct, double2* th_f, double2* fi_f,
                          double2* fe_f, hipStream_t st) {
-    k_interp<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec,
-                                                     coarse->nspec, Pfc, nf, nc, th_c, th_ct, fi_c, fi_ct, fe_c,
-                                                     fe_ct, th_f, fi_f, fe_f);
+    if (nf < 2) return hipSuccess;
+    dim3 g(nblocks(coarse->nspec), 3, nf - 1);
+    k_interp<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec, coarse->nspec, Pfc, nf,
+                               nc, th_c, th_ct, fi_c, fi_ct, fe_c, fe_ct, th_f, fi_f, fe_f);
     return hipGetLastError();
 }
 

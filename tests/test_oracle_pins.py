@@ -80,6 +80,36 @@ def test_plm_vs_scipy():
             assert np.abs(P[n - m] - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
 
 
+def test_plm_high_degree_accuracy():
+    """At the degrees of T1023 the tabulated values match the same recurrence
+    run in 50-digit arithmetic (mpmath) on the same FP64 inputs mu and
+    sin(theta) to 3e-15 of the column's largest value (the recurrence itself
+    is pinned by the closed forms and scipy above).  The forward recurrence
+    amplifies rounding errors roughly like n^2 near the poles: run in FP64 it
+    is off by about 1e-12 of the column maximum at degree 1023 next to the
+    pole, in long double by about 1e-15."""
+    from mpmath import mp
+    mu = np.array([0.9999987751809604, 0.7071067811865476, 0.31415926535897931, 0.001])
+    with mp.workdps(50):
+        st = np.array([float(mp.sqrt(1 - mp.mpf(float(x)) ** 2)) for x in mu])
+        for m in (0, 1, 300, 900):
+            P = sht.legendre_m(m, 1024, mu, st)
+            for j in range(mu.size):
+                scale = np.abs(P[:, j]).max()
+                x, s = mp.mpf(float(mu[j])), mp.mpf(float(st[j]))
+                pmm = 1 / mp.sqrt(2)
+                for k in range(1, m + 1):
+                    pmm *= mp.sqrt(mp.mpf(2 * k + 1) / (2 * k)) * s
+                ref = [pmm, mp.sqrt(2 * m + 3) * x * pmm]
+                e = [mp.mpf(0)] * 1025
+                for n in range(m + 1, 1025):
+                    e[n] = mp.sqrt(mp.mpf(n * n - m * m) / (4 * n * n - 1))
+                for n in range(m + 2, 1025):
+                    ref.append((x * ref[-1] - e[n - 1] * ref[-2]) / e[n])
+                err = max(abs(P[k, j] - float(ref[k])) for k in range(len(ref)))
+                assert err <= 3e-15 * scale, (m, j, err, scale)
+
+
 def test_plm_discrete_orthonormality():
     N, J = 63, 96
     mu, st, _, w = Qd.gauss_legendre(J)
