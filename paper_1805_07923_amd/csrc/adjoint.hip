@@ -147,7 +147,9 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
                                                                double2* __restrict__ Ga, int N, int J,
                                                                double two_omega) {
     constexpr int L2 = L / 2, T = Cfg<L>::T;
-    __shared__ double2 lds[9 * L2];
+    // two 9-row buffers where LDS has room (L <= 1024), else in place
+    constexpr bool PP = 19 * L2 * (int)sizeof(double2) <= 160 * 1024;
+    __shared__ double2 lds[(PP ? 18 : 9) * L2];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
@@ -168,16 +170,18 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
         }
         return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
     };
+    double2* other = lds + (PP ? 9 * L2 : 0);
     rowfft::pack_rows<L, 9>(lds, tws, tw, N, coef);
     __syncthreads();
-    rowfft::stages<L2, T, 9, 1>(lds, tws, 1.0);
+    double2* x = rowfft::fft<L2, T, 9, PP>(lds, other, tws, 1.0);
+    double2* y = (x == lds) ? other : lds;
     const double fc = two_omega * mu[j];
     const double ic2 = 1.0 / cos2[j];
     const double wv = w[j] / (L * cos2[j]), we = w[j] / L;
     for (int k = threadIdx.x; k < L2; k += T) {
-        const double2 z = lds[k], ph = lds[L2 + k], U = lds[2 * L2 + k], V = lds[3 * L2 + k];
-        const double2 lA = lds[4 * L2 + k], lB = lds[5 * L2 + k], lC = lds[6 * L2 + k], lD = lds[7 * L2 + k],
-                      lE = lds[8 * L2 + k];
+        const double2 z = x[k], ph = x[L2 + k], U = x[2 * L2 + k], V = x[3 * L2 + k];
+        const double2 lA = x[4 * L2 + k], lB = x[5 * L2 + k], lC = x[6 * L2 + k], lD = x[7 * L2 + k],
+                      lE = x[8 * L2 + k];
         const double2 eta = make_double2(z.x + fc, z.y + fc);
         // A = eta U, B = eta V, C = Phi' U, D = Phi' V, E = (U^2 + V^2) / (2 cos^2 phi)
         double2 gz, gp, gu, gv;
@@ -189,19 +193,19 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
         gu.y = wv * (lA.y * eta.y + lC.y * ph.y) + we * lE.y * U.y * ic2;
         gv.x = wv * (lB.x * eta.x + lD.x * ph.x) + we * lE.x * V.x * ic2;
         gv.y = wv * (lB.y * eta.y + lD.y * ph.y) + we * lE.y * V.y * ic2;
-        lds[k] = gz;
-        lds[L2 + k] = gp;
-        lds[2 * L2 + k] = gu;
-        lds[3 * L2 + k] = gv;
+        x[k] = gz;
+        x[L2 + k] = gp;
+        x[2 * L2 + k] = gu;
+        x[3 * L2 + k] = gv;
     }
     __syncthreads();
-    rowfft::stages<L2, T, 4, 1>(lds, tws, -1.0);
+    const double2* r = rowfft::fft<L2, T, 4, PP>(x, y, tws, -1.0);
     double2* out = Ga + ((long long)s * J + j) * (N + 1) * 4;
     for (int m = threadIdx.x; m <= N; m += T) {
         const double c = (m == 0) ? 1.0 : 2.0;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const double2 X = rowfft::unpack<L>(lds + f * L2, tws, m);
+            const double2 X = rowfft::unpack<L>(r + f * L2, tws, m);
             out[(long long)m * 4 + f] = cscale(c, X);
         }
     }

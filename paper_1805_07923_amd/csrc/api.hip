@@ -60,14 +60,13 @@ struct Carve {
     }
 };
 
-// Tendency workspace for S states: cin [S][ext][4], FI [S][J][N+1][4],
-// G [S][J][N+1][5], cout [S][ext][5] (double2).
+// Tendency workspace for S states: FI [S][J][N+1][4], G [S][J][N+1][5],
+// cout [S][ext][5] (double2).
 struct TendWS {
-    double2 *cin, *FI, *G, *cout;
+    double2 *FI, *G, *cout;
 };
 TendWS carve_tend(Carve& c, const shx_plan* pl, int S) {
     TendWS t;
-    t.cin = c.take<double2>((size_t)S * pl->nspec_e * 4);
     t.FI = c.take<double2>((size_t)S * pl->J * (pl->N + 1) * 4);
     t.G = c.take<double2>((size_t)S * pl->J * (pl->N + 1) * 5);
     t.cout = c.take<double2>((size_t)S * pl->nspec_e * 5);
@@ -106,13 +105,7 @@ hipError_t timed(int kclass, hipStream_t st, F launch) {
 int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double2* state, double2* fi,
                   double2* fe, const TendWS& t, hipStream_t st, bool combine = true) {
     if (fe) {
-        if (pl->prec == SHX_FP64) {
-            HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn_swe(pl, p.a, state, t.FI, nst, st); }));
-        } else {
-            HIPCHK(launch_swe_prep(pl, p.a, state, t.cin, nst, st));
-            HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st,
-                         [&] { return launch_leg_syn(pl, t.cin, t.FI, 4, nst, pl->nmax, st); }));
-        }
+        HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn_swe(pl, p.a, state, t.FI, nst, st); }));
         HIPCHK(timed(SHX_KC_GRID, st, [&] { return launch_swe_grid(pl, t.FI, t.G, nst, p.omega, st); }));
         HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] { return launch_leg_an(pl, t.G, t.cout, 5, nst, pl->nmax, st); }));
     }

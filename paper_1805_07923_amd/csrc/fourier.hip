@@ -24,7 +24,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_inv(const double2* __restrict
                                                        double* __restrict__ grid, int N, int J, int F,
                                                        int mode) {
     constexpr int L2 = L / 2, T = Cfg<L>::T;
-    __shared__ double2 row[L2];
+    __shared__ double2 row[2 * L2];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, f = blockIdx.y;
     const int Jh = J / 2;
@@ -38,10 +38,10 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_inv(const double2* __restrict
     };
     rowfft::pack_rows<L, 1>(row, tws, tw, N, coef);
     __syncthreads();
-    rowfft::stages<L2, T, 1, 1>(row, tws, 1.0);
+    const double2* z = rowfft::fft<L2, T, 1, true>(row, row + L2, tws, 1.0);
     double2* g = reinterpret_cast<double2*>(grid + ((long long)f * J + j) * L);
     const double gs = mode ? w[j] / L : 1.0;
-    for (int k = threadIdx.x; k < L2; k += T) g[k] = make_double2(gs * row[k].x, gs * row[k].y);
+    for (int k = threadIdx.x; k < L2; k += T) g[k] = make_double2(gs * z[k].x, gs * z[k].y);
 }
 
 // Forward: one workgroup per (latitude row j, field f); G[j][m][f] = w_j X_m / L.
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_fwd(const double* __restrict_
                                                        double2* __restrict__ G, int N, int J, int F,
                                                        int mode) {
     constexpr int L2 = L / 2, T = Cfg<L>::T, IT = (L2 + T - 1) / T;
-    __shared__ double2 row[L2];
+    __shared__ double2 row[2 * L2];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, f = blockIdx.y;
     const double2* g = reinterpret_cast<const double2*>(grid + ((long long)f * J + j) * L);
@@ -74,11 +74,11 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_fwd(const double* __restrict_
         }
     }
     __syncthreads();
-    rowfft::stages<L2, T, 1, 1>(row, tws, -1.0);
+    const double2* z = rowfft::fft<L2, T, 1, true>(row, row + L2, tws, -1.0);
     double2* out = G + (long long)j * (N + 1) * F + f;
     for (int m = threadIdx.x; m <= N; m += T) {
         const double sc = mode ? (m == 0 ? 1.0 : 2.0) : w[j] / L;
-        const double2 X = rowfft::unpack<L>(row, tws, m);
+        const double2 X = rowfft::unpack<L>(z, tws, m);
         out[(long long)m * F] = make_double2(sc * X.x, sc * X.y);
     }
 }
@@ -95,7 +95,9 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
                                                         double2* __restrict__ G, int N, int J,
                                                         double two_omega) {
     constexpr int L2 = L / 2, T = Cfg<L>::T;
-    __shared__ double2 lds[5 * L2];
+    // two 5-row buffers where LDS has room (L <= 1536), else in place
+    constexpr bool PP = 11 * L2 * (int)sizeof(double2) <= 160 * 1024;
+    __shared__ double2 lds[(PP ? 10 : 5) * L2];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
@@ -107,23 +109,25 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
         const double2 a = e[(long long)m * 4 + f], b = e[(long long)m * 4 + f + pstride];
         return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
     };
+    double2* other = lds + (PP ? 5 * L2 : 0);
     rowfft::pack_rows<L, 4>(lds, tws, tw, N, coef);
     __syncthreads();
-    rowfft::stages<L2, T, 4, 1>(lds, tws, 1.0);
+    double2* x = rowfft::fft<L2, T, 4, PP>(lds, other, tws, 1.0);
+    double2* y = (x == lds) ? other : lds;
     const double fc = two_omega * mu[j];
     const double hk = 0.5 / cos2[j];
     for (int k = threadIdx.x; k < L2; k += T) {
-        // (x_{2k}, x_{2k+1}) of zeta, Phi', U, V
-        const double2 z = lds[k], ph = lds[L2 + k], U = lds[2 * L2 + k], V = lds[3 * L2 + k];
+        // (x_{2k}, x_{2k+1}) of zeta, Phi', U, V; the five products in place
+        const double2 z = x[k], ph = x[L2 + k], U = x[2 * L2 + k], V = x[3 * L2 + k];
         const double2 eta = make_double2(z.x + fc, z.y + fc);
-        lds[k] = make_double2(eta.x * U.x, eta.y * U.y);
-        lds[L2 + k] = make_double2(eta.x * V.x, eta.y * V.y);
-        lds[2 * L2 + k] = make_double2(ph.x * U.x, ph.y * U.y);
-        lds[3 * L2 + k] = make_double2(ph.x * V.x, ph.y * V.y);
-        lds[4 * L2 + k] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
+        x[k] = make_double2(eta.x * U.x, eta.y * U.y);
+        x[L2 + k] = make_double2(eta.x * V.x, eta.y * V.y);
+        x[2 * L2 + k] = make_double2(ph.x * U.x, ph.y * U.y);
+        x[3 * L2 + k] = make_double2(ph.x * V.x, ph.y * V.y);
+        x[4 * L2 + k] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
     }
     __syncthreads();
-    rowfft::stages<L2, T, 5, 1>(lds, tws, -1.0);
+    const double2* r = rowfft::fft<L2, T, 5, PP>(x, y, tws, -1.0);
     const double sv = w[j] / (L * cos2[j]);
     const double se = w[j] / L;
     double2* out = G + ((long long)s * J + j) * (N + 1) * 5;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
         double2* o = out + (long long)m * 5;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            const double2 X = rowfft::unpack<L>(lds + f * L2, tws, m);
+            const double2 X = rowfft::unpack<L>(r + f * L2, tws, m);
             const double sc = (f < 4) ? sv : se;
             o[f] = make_double2(sc * X.x, sc * X.y);
         }

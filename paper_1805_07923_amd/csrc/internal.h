@@ -139,7 +139,7 @@ hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st);
 hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, int F, int S,
                           int nmax_use, hipStream_t st);
 // Synthesis of the tendency's four grid fields straight from S states
-// [S][3][nspec] (FP64 plans): swe_prep_row feeds the staging.
+// [S][3][nspec]: swe_prep_row feeds the staging (any working precision).
 hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
                               hipStream_t st);
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
@@ -149,6 +149,8 @@ hipError_t launch_leg_an_mixed(const shx_plan* pl, const double2* G, double2* co
                                hipStream_t st);
 hipError_t launch_leg_syn_mixed(const shx_plan* pl, const double2* cin, double2* out, int F, int S, int nmax_use,
                                 hipStream_t st);
+hipError_t launch_leg_syn_mixed_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
+                                    hipStream_t st);
 hipError_t launch_tables_to_f32(const shx_plan* pl, hipStream_t st);
 hipError_t launch_tables_to_bf16(const shx_plan* pl, const int* d_rows_an, const int* d_cols_an,
                                  const int* d_colsp_an, const int* d_rows_syn, const int* d_cols_syn,

@@ -366,7 +366,7 @@ hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, 
 
 hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
                               hipStream_t st) {
-    if (pl->prec != SHX_FP64) return hipErrorInvalidValue;
+    if (pl->prec != SHX_FP64) return launch_leg_syn_mixed_swe(pl, a, state, out, S, st);
     const int gx = (pl->Jh + 63) / 64;
     const size_t lds = (size_t)kcount(pl->nmax, 0, 0) * 4 * sizeof(double2);
     k_leg_syn<4, true><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, state, out, pl->N, pl->nmax,

@@ -103,14 +103,15 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
                                                    const long long* __restrict__ off,
                                                    const double2* __restrict__ G, double2* __restrict__ cout,
                                                    int N, int nmax_tab, int nmax_use, int J, int F, int f0, int NF,
-                                                   int S, long long G_stride, long long cout_stride) {
+                                                   int S, long long G_stride, long long cout_stride, int gx) {
     constexpr int NP = (MODE == 1) ? 1 : MODE;
     constexpr int CW = 16 * NCT;                        // columns
     extern __shared__ unsigned char smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m = blockIdx.y, p = blockIdx.z;
+    const LegTile tile = leg_tile(gx, N + 1);
+    const int m = tile.m, p = tile.p;
     const int K = kcount(nmax_use, m, p);
-    const int kb = blockIdx.x * 64;
+    const int kb = tile.x * 64;
     if (kb >= K) return;
     const int Ktab = kcount(nmax_tab, m, p);
     const int Jh = J / 2;
@@ -224,21 +225,23 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
 // ----------------------------------------------------------------- synthesis
 // D[jp][c] = sum_k P[k][jp] C[k][c], C = coefficients of order m, parity p.
 // grid (ceil(Jh/64), N+1, 2), 4 waves: wave w owns latitudes jb + 16 w .. + 15.
-template <int MODE, int NCT>
+template <int MODE, int NCT, bool PREP = false>
 __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab, long long plane,
                                                     const long long* __restrict__ off,
                                                     const double2* __restrict__ cin, double2* __restrict__ out,
                                                     int N, int nmax_tab, int nmax_use, int Jh, int F, int f0,
-                                                    int NF, int S, long long cin_stride, long long out_stride) {
+                                                    int NF, int S, long long cin_stride, long long out_stride,
+                                                    int gx, long long nspec, double a) {
     constexpr int NP = (MODE == 1) ? 1 : MODE;
     constexpr int CW = 16 * NCT;
     extern __shared__ unsigned char smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m = blockIdx.y, p = blockIdx.z;
+    const LegTile tile = leg_tile(gx, N + 1);
+    const int m = tile.m, p = tile.p;
     const int K = kcount(nmax_use, m, p);
     const int Ktab = kcount(nmax_tab, m, p);
     const int Kp = (Ktab + 15) / 16 * 16;
-    const int j0 = blockIdx.x * 64 + 16 * wv;           // this wave's latitude tile
+    const int j0 = tile.x * 64 + 16 * wv;               // this wave's latitude tile
     const bool wave_on = j0 < Jh;
     const long long e0 = ext_idx(N, m, m + p);
     const int KL = (MODE == 1) ? K : Kp;                // staged rows
@@ -246,22 +249,39 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
         const double2* c = cin + s * cin_stride + e0 * F + f0;
         __syncthreads();
         // stage C: FP32 as [k][CW]; bf16 planes as [q][c][Kp]
-        for (int i = threadIdx.x; i < KL * CW; i += 256) {
-            // columns fastest: consecutive threads read consecutive fields
-            const int k = i / CW, cc = i - k * CW;
-            double v = 0.0;
-            if (k < K && cc < 2 * NF) {
-                const double2 x = c[(long long)(2 * k) * F + cc / 2];
-                v = (cc & 1) ? x.y : x.x;
-            }
+        auto put = [&](int k, int cc, double v) {
             if constexpr (MODE == 1) {
-                reinterpret_cast<float*>(smem)[i] = (float)v;
+                reinterpret_cast<float*>(smem)[k * CW + cc] = (float)v;
             } else {
                 unsigned short h[NP];
                 split_bf16<NP>(v, h);
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
                     reinterpret_cast<unsigned short*>(smem)[q * Kp * CW + cc * Kp + k] = h[q];
+            }
+        };
+        if constexpr (PREP) {
+            // one thread per row: the tendency's four fields from the state
+            for (int k = threadIdx.x; k < KL; k += 256) {
+                double2 o[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                                make_double2(0.0, 0.0)};
+                if (k < K) swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * k, o);
+#pragma unroll
+                for (int cc = 0; cc < CW; ++cc) {
+                    const double2 x = o[(cc / 2) & 3];
+                    put(k, cc, (cc < 8) ? ((cc & 1) ? x.y : x.x) : 0.0);
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < KL * CW; i += 256) {
+                // columns fastest: consecutive threads read consecutive fields
+                const int k = i / CW, cc = i - k * CW;
+                double v = 0.0;
+                if (k < K && cc < 2 * NF) {
+                    const double2 x = c[(long long)(2 * k) * F + cc / 2];
+                    v = (cc & 1) ? x.y : x.x;
+                }
+                put(k, cc, v);
             }
         }
         __syncthreads();
@@ -345,28 +365,31 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
 template <int MODE, int NCT>
 void an_mx(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int NF, int S, int nmax_use,
            hipStream_t st) {
-    const int kmax = kcount(nmax_use, 0, 0);
-    dim3 grid((kmax + 63) / 64, pl->N + 1, 2);
+    const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
+    const unsigned grid = gx * (pl->N + 1) * 2;
     const int Jhp = (pl->Jh + 15) / 16 * 16;
     const int NP = MODE == 1 ? 1 : MODE;
     const size_t lds = (MODE == 1) ? (size_t)Jhp * 16 * NCT * 4 : (size_t)NP * Jhp * 16 * NCT * 2;
     const void* tab = (MODE == 1) ? (const void*)pl->pan32 : (const void*)pl->an16;
     k_leg_an_mx<MODE, NCT><<<grid, 256, lds, st>>>(tab, pl->an16_plane, MODE == 1 ? pl->off : pl->off_an16, G, cout,
                                                     pl->N, pl->nmax, nmax_use, pl->J, F, f0, NF, S,
-                                                    (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F);
+                                                    (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F, gx);
 }
 
-template <int MODE, int NCT>
+// PREP: cin holds states [S][3][nspec] and the staged rows are the
+// tendency's four grid fields (F = NF = 4, NCT = 1).
+template <int MODE, int NCT, bool PREP = false>
 void syn_mx(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int NF, int S, int nmax_use,
-            hipStream_t st) {
-    dim3 grid((pl->Jh + 63) / 64, pl->N + 1, 2);
+            hipStream_t st, double a = 0.0) {
+    const int gx = (pl->Jh + 63) / 64;
+    const unsigned grid = gx * (pl->N + 1) * 2;
     const int Kp = (kcount(pl->nmax, 0, 0) + 15) / 16 * 16;
     const int NP = MODE == 1 ? 1 : MODE;
     const size_t lds = (MODE == 1) ? (size_t)Kp * 16 * NCT * 4 : (size_t)NP * Kp * 16 * NCT * 2;
     const void* tab = (MODE == 1) ? (const void*)pl->psyn32 : (const void*)pl->syn16;
-    k_leg_syn_mx<MODE, NCT><<<grid, 256, lds, st>>>(tab, pl->syn16_plane, MODE == 1 ? pl->off : pl->off_syn16, cin,
-                                                     out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, NF, S,
-                                                     pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F);
+    k_leg_syn_mx<MODE, NCT, PREP><<<grid, 256, lds, st>>>(
+        tab, pl->syn16_plane, MODE == 1 ? pl->off : pl->off_syn16, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F,
+        f0, NF, S, PREP ? 3 * pl->nspec : pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a);
 }
 
 template <int MODE>
@@ -395,6 +418,17 @@ hipError_t launch_leg_an_mixed(const shx_plan* pl, const double2* G, double2* co
         case SHX_FP32: an_mode<1>(pl, G, cout, F, S, nmax_use, st); break;
         case SHX_SPLIT_BF16_2: an_mode<2>(pl, G, cout, F, S, nmax_use, st); break;
         case SHX_SPLIT_BF16_3: an_mode<3>(pl, G, cout, F, S, nmax_use, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_syn_mixed_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
+                                    hipStream_t st) {
+    switch (pl->prec) {
+        case SHX_FP32: syn_mx<1, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
+        case SHX_SPLIT_BF16_2: syn_mx<2, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
+        case SHX_SPLIT_BF16_3: syn_mx<3, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

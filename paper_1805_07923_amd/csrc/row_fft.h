@@ -8,9 +8,12 @@
 //               z = sum_m Z_m e^{2 pi i m k / L2}  ->  x_{2k} = Re z_k, x_{2k+1} = Im z_k;
 //   analysis:   Z = FFT_{L2}(z),  E_m = (Z_m + conj Z_{-m}) / 2,  O_m = (Z_m - conj Z_{-m}) / (2 i),
 //               X_m = E_m + e^{-2 pi i m / L} O_m.
-// The complex FFT is a Stockham transform in LDS (radix-4 stages, at most one
-// radix-2 stage, then the radix-3 stage): each stage loads its butterflies
-// into registers, meets a barrier and writes back.  Twiddles e^{-2 pi i t / L},
+// The complex FFT is a Stockham transform in LDS with radix-8 stages first,
+// then one stage of radix 6, 4, 3 or 2 as the remaining length requires (384 =
+// 8 8 6, 1536 = 8 8 8 3).  Each stage loads its butterflies into registers
+// and writes them to a second LDS buffer (one barrier per stage), or, where
+// LDS has no room for two buffers, back in place after a barrier.
+// Twiddles e^{-2 pi i t / L},
 // t < L2, come from a table computed on the host in quad precision and copied
 // to LDS; e^{-2 pi i t / L2} is entry 2t, and the upper half of the circle is
 // the negated lower half.
@@ -60,6 +63,61 @@ __device__ __forceinline__ void dft<3>(double2* v, double sg) {
     v[2] = make_double2(mm.x - r.x, mm.y - r.y);
 }
 
+// Radix 6 and 8 by one radix-2 split (decimation in frequency) into two
+// DFTs of size 3 or 4: X_{2k} = DFT(x_j + x_{j+R/2}), X_{2k+1} =
+// DFT((x_j - x_{j+R/2}) w_R^j), w_R = e^{sg 2 pi i / R}.
+template <>
+__device__ __forceinline__ void dft<6>(double2* v, double sg) {
+    const double c = 0.86602540378443864676;   // sin(2 pi / 3)
+    double2 a[3], b[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        a[j] = make_double2(v[j].x + v[j + 3].x, v[j].y + v[j + 3].y);
+        b[j] = make_double2(v[j].x - v[j + 3].x, v[j].y - v[j + 3].y);
+    }
+    b[1] = cmul(b[1], make_double2(0.5, sg * c));
+    b[2] = cmul(b[2], make_double2(-0.5, sg * c));
+    dft<3>(a, sg);
+    dft<3>(b, sg);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[2 * k] = a[k];
+        v[2 * k + 1] = b[k];
+    }
+}
+
+template <>
+__device__ __forceinline__ void dft<8>(double2* v, double sg) {
+    const double h = 0.70710678118654752440;   // sqrt(1/2)
+    double2 a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j] = make_double2(v[j].x + v[j + 4].x, v[j].y + v[j + 4].y);
+        b[j] = make_double2(v[j].x - v[j + 4].x, v[j].y - v[j + 4].y);
+    }
+    b[1] = make_double2(h * (b[1].x - sg * b[1].y), h * (b[1].y + sg * b[1].x));
+    b[2] = make_double2(-sg * b[2].y, sg * b[2].x);
+    b[3] = make_double2(h * (-b[3].x - sg * b[3].y), h * (-b[3].y + sg * b[3].x));
+    dft<4>(a, sg);
+    dft<4>(b, sg);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = a[k];
+        v[2 * k + 1] = b[k];
+    }
+}
+
+// Radix of the next stage for a remaining length rem.
+__host__ __device__ constexpr int next_radix(int rem) {
+    return rem % 8 == 0 ? 8 : (rem == 6 ? 6 : (rem % 4 == 0 ? 4 : (rem % 2 == 0 ? 2 : 3)));
+}
+// Number of stages of a length-C transform.
+__host__ __device__ constexpr int stage_count(int C) {
+    int n = 0;
+    for (int rem = C; rem > 1; rem /= next_radix(rem)) ++n;
+    return n;
+}
+
 // e^{-2 pi i idx / (2 half)} from the half table tws[0..half).
 __device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half) {
     const double2 w = tws[idx < half ? idx : idx - half];
@@ -75,52 +133,81 @@ struct Cfg {
     static constexpr int T = (T0 + 63) / 64 * 64;
 };
 
-// Stockham stages for NR complex rows of length C (row stride C) held in LDS,
-// T threads; Ns is the length of the sub-transforms already done.  tws is
-// the LDS twiddle table of the real length 2C (C entries).
+// One Stockham stage for NR complex rows of length C (row stride C), T
+// threads; Ns is the length of the sub-transforms already done.  tws is the
+// LDS twiddle table of the real length 2C (C entries).  Reads src; writes dst
+// (dst == src: in place, with a barrier between the reads and the writes).
+template <int C, int T, int NR, int Ns>
+__device__ __forceinline__ void stage(const double2* src, double2* dst, const double2* tws, double sg) {
+    constexpr int R = next_radix(C / Ns);
+    constexpr int NB = C / R;
+    constexpr int ITEMS = NR * NB;
+    constexpr int IPT = (ITEMS + T - 1) / T;
+    constexpr int TWS = C / (Ns * R) * 2;
+    double2 v[IPT][R];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int item = threadIdx.x + it * T;
+        if (ITEMS % T == 0 || item < ITEMS) {
+            const int row = item / NB, j = item - row * NB, k = j % Ns;
+            const double2* b = src + row * C;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = b[j + r * NB];
+                if (Ns > 1 && r > 0) {
+                    double2 w = tw_half(tws, r * k * TWS, C);
+                    w.y *= -sg;
+                    x = cmul(x, w);
+                }
+                v[it][r] = x;
+            }
+            dft<R>(v[it], sg);
+        }
+    }
+    if (src == dst) __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int item = threadIdx.x + it * T;
+        if (ITEMS % T == 0 || item < ITEMS) {
+            const int row = item / NB, j = item - row * NB, k = j % Ns;
+            const int base = (j / Ns) * Ns * R + k;
+            double2* b = dst + row * C;
+#pragma unroll
+            for (int q = 0; q < R; ++q) b[base + q * Ns] = v[it][q];
+        }
+    }
+    __syncthreads();
+}
+
+// All stages in place in buf.
 template <int C, int T, int NR, int Ns>
 __device__ __forceinline__ void stages(double2* buf, const double2* tws, double sg) {
-    constexpr int rem = C / Ns;
-    if constexpr (rem > 1) {
-        constexpr int R = (rem % 4 == 0) ? 4 : ((rem % 2 == 0) ? 2 : 3);
-        constexpr int NB = C / R;
-        constexpr int ITEMS = NR * NB;
-        constexpr int IPT = (ITEMS + T - 1) / T;
-        constexpr int TWS = C / (Ns * R) * 2;
-        double2 v[IPT][R];
-#pragma unroll
-        for (int it = 0; it < IPT; ++it) {
-            const int item = threadIdx.x + it * T;
-            if (ITEMS % T == 0 || item < ITEMS) {
-                const int row = item / NB, j = item - row * NB, k = j % Ns;
-                const double2* b = buf + row * C;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double2 x = b[j + r * NB];
-                    if (Ns > 1 && r > 0) {
-                        double2 w = tw_half(tws, r * k * TWS, C);
-                        w.y *= -sg;
-                        x = cmul(x, w);
-                    }
-                    v[it][r] = x;
-                }
-                dft<R>(v[it], sg);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < IPT; ++it) {
-            const int item = threadIdx.x + it * T;
-            if (ITEMS % T == 0 || item < ITEMS) {
-                const int row = item / NB, j = item - row * NB, k = j % Ns;
-                const int base = (j / Ns) * Ns * R + k;
-                double2* b = buf + row * C;
-#pragma unroll
-                for (int q = 0; q < R; ++q) b[base + q * Ns] = v[it][q];
-            }
-        }
-        __syncthreads();
-        stages<C, T, NR, Ns * R>(buf, tws, sg);
+    if constexpr (C / Ns > 1) {
+        stage<C, T, NR, Ns>(buf, buf, tws, sg);
+        stages<C, T, NR, Ns * next_radix(C / Ns)>(buf, tws, sg);
+    }
+}
+
+// All stages between two buffers (a holds the input); the result ends in a
+// when the stage count is even, else in b.
+template <int C, int T, int NR, int Ns>
+__device__ __forceinline__ void stages_pp(double2* a, double2* b, const double2* tws, double sg) {
+    if constexpr (C / Ns > 1) {
+        stage<C, T, NR, Ns>(a, b, tws, sg);
+        stages_pp<C, T, NR, Ns * next_radix(C / Ns)>(b, a, tws, sg);
+    }
+}
+
+// FFT of NR rows held in a; with PP the second buffer b is used and the
+// returned pointer says where the result is.
+template <int C, int T, int NR, bool PP>
+__device__ __forceinline__ double2* fft(double2* a, double2* b, const double2* tws, double sg) {
+    if constexpr (PP) {
+        stages_pp<C, T, NR, 1>(a, b, tws, sg);
+        return (stage_count(C) % 2 == 0) ? a : b;
+    } else {
+        stages<C, T, NR, 1>(a, tws, sg);
+        return a;
     }
 }
 
