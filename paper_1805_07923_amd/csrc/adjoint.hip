@@ -132,6 +132,8 @@ __global__ void k_prep_adj(const int* __restrict__ ord, const int* __restrict__ 
 }
 
 using rowfft::Cfg;
+using rowfft::padded;
+using rowfft::pidx;
 
 // Tendency adjoint, grid part: one workgroup per (latitude row j, state s).
 // FIs[s]: [2][Jh][N+1][4] state (zeta, Phi', U, V); FIl[s]: [2][Jh][N+1][5]
@@ -146,10 +148,10 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
                                                                const double* __restrict__ w,
                                                                double2* __restrict__ Ga, int N, int J,
                                                                double two_omega) {
-    constexpr int L2 = L / 2, T = Cfg<L>::T;
+    constexpr int L2 = L / 2, T = Cfg<L>::T, P = padded(L2);
     // two 9-row buffers where LDS has room (L <= 1024), else in place
-    constexpr bool PP = 19 * L2 * (int)sizeof(double2) <= 160 * 1024;
-    __shared__ double2 lds[(PP ? 18 : 9) * L2];
+    constexpr bool PP = (18 * P + L2) * (int)sizeof(double2) <= 160 * 1024;
+    __shared__ double2 lds[(PP ? 18 : 9) * P];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
         }
         return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
     };
-    double2* other = lds + (PP ? 9 * L2 : 0);
+    double2* other = lds + (PP ? 9 * P : 0);
     rowfft::pack_rows<L, 9>(lds, tws, tw, N, coef);
     __syncthreads();
     double2* x = rowfft::fft<L2, T, 9, PP>(lds, other, tws, 1.0);
@@ -179,9 +181,10 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
     const double ic2 = 1.0 / cos2[j];
     const double wv = w[j] / (L * cos2[j]), we = w[j] / L;
     for (int k = threadIdx.x; k < L2; k += T) {
-        const double2 z = x[k], ph = x[L2 + k], U = x[2 * L2 + k], V = x[3 * L2 + k];
-        const double2 lA = x[4 * L2 + k], lB = x[5 * L2 + k], lC = x[6 * L2 + k], lD = x[7 * L2 + k],
-                      lE = x[8 * L2 + k];
+        const int q = pidx(k);
+        const double2 z = x[q], ph = x[P + q], U = x[2 * P + q], V = x[3 * P + q];
+        const double2 lA = x[4 * P + q], lB = x[5 * P + q], lC = x[6 * P + q], lD = x[7 * P + q],
+                      lE = x[8 * P + q];
         const double2 eta = make_double2(z.x + fc, z.y + fc);
         // A = eta U, B = eta V, C = Phi' U, D = Phi' V, E = (U^2 + V^2) / (2 cos^2 phi)
         double2 gz, gp, gu, gv;
@@ -193,10 +196,10 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
         gu.y = wv * (lA.y * eta.y + lC.y * ph.y) + we * lE.y * U.y * ic2;
         gv.x = wv * (lB.x * eta.x + lD.x * ph.x) + we * lE.x * V.x * ic2;
         gv.y = wv * (lB.y * eta.y + lD.y * ph.y) + we * lE.y * V.y * ic2;
-        x[k] = gz;
-        x[L2 + k] = gp;
-        x[2 * L2 + k] = gu;
-        x[3 * L2 + k] = gv;
+        x[q] = gz;
+        x[P + q] = gp;
+        x[2 * P + q] = gu;
+        x[3 * P + q] = gv;
     }
     __syncthreads();
     const double2* r = rowfft::fft<L2, T, 4, PP>(x, y, tws, -1.0);
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
         const double c = (m == 0) ? 1.0 : 2.0;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const double2 X = rowfft::unpack<L>(r + f * L2, tws, m);
+            const double2 X = rowfft::unpack<L>(r + f * P, tws, m);
             out[(long long)m * 4 + f] = cscale(c, X);
         }
     }

@@ -14,6 +14,8 @@
 namespace {
 
 using rowfft::Cfg;
+using rowfft::padded;
+using rowfft::pidx;
 
 // Inverse: one workgroup per (latitude row j, field f).  FI: [2][Jh][N+1][F]
 // (even / odd Legendre sums); X = E + sgn O with sgn = +1 north, -1 south.
@@ -23,8 +25,8 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_inv(const double2* __restrict
                                                        const double* __restrict__ w,
                                                        double* __restrict__ grid, int N, int J, int F,
                                                        int mode) {
-    constexpr int L2 = L / 2, T = Cfg<L>::T;
-    __shared__ double2 row[2 * L2];
+    constexpr int L2 = L / 2, T = Cfg<L>::T, P = padded(L2);
+    __shared__ double2 row[2 * P];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, f = blockIdx.y;
     const int Jh = J / 2;
@@ -38,10 +40,13 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_inv(const double2* __restrict
     };
     rowfft::pack_rows<L, 1>(row, tws, tw, N, coef);
     __syncthreads();
-    const double2* z = rowfft::fft<L2, T, 1, true>(row, row + L2, tws, 1.0);
+    const double2* z = rowfft::fft<L2, T, 1, true>(row, row + P, tws, 1.0);
     double2* g = reinterpret_cast<double2*>(grid + ((long long)f * J + j) * L);
     const double gs = mode ? w[j] / L : 1.0;
-    for (int k = threadIdx.x; k < L2; k += T) g[k] = make_double2(gs * z[k].x, gs * z[k].y);
+    for (int k = threadIdx.x; k < L2; k += T) {
+        const double2 v = z[pidx(k)];
+        g[k] = make_double2(gs * v.x, gs * v.y);
+    }
 }
 
 // Forward: one workgroup per (latitude row j, field f); G[j][m][f] = w_j X_m / L.
@@ -51,8 +56,8 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_fwd(const double* __restrict_
                                                        const double* __restrict__ w,
                                                        double2* __restrict__ G, int N, int J, int F,
                                                        int mode) {
-    constexpr int L2 = L / 2, T = Cfg<L>::T, IT = (L2 + T - 1) / T;
-    __shared__ double2 row[2 * L2];
+    constexpr int L2 = L / 2, T = Cfg<L>::T, IT = (L2 + T - 1) / T, P = padded(L2);
+    __shared__ double2 row[2 * P];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, f = blockIdx.y;
     const double2* g = reinterpret_cast<const double2*>(grid + ((long long)f * J + j) * L);
@@ -70,11 +75,11 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_fwd(const double* __restrict_
         const int k = threadIdx.x + it * T;
         if (k < L2) {
             tws[k] = tv[it];
-            row[k] = rv[it];
+            row[pidx(k)] = rv[it];
         }
     }
     __syncthreads();
-    const double2* z = rowfft::fft<L2, T, 1, true>(row, row + L2, tws, -1.0);
+    const double2* z = rowfft::fft<L2, T, 1, true>(row, row + P, tws, -1.0);
     double2* out = G + (long long)j * (N + 1) * F + f;
     for (int m = threadIdx.x; m <= N; m += T) {
         const double sc = mode ? (m == 0 ? 1.0 : 2.0) : w[j] / L;
@@ -94,10 +99,10 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
                                                         const double* __restrict__ w,
                                                         double2* __restrict__ G, int N, int J,
                                                         double two_omega) {
-    constexpr int L2 = L / 2, T = Cfg<L>::T;
+    constexpr int L2 = L / 2, T = Cfg<L>::T, P = padded(L2);
     // two 5-row buffers where LDS has room (L <= 1536), else in place
-    constexpr bool PP = 11 * L2 * (int)sizeof(double2) <= 160 * 1024;
-    __shared__ double2 lds[(PP ? 10 : 5) * L2];
+    constexpr bool PP = (10 * P + L2) * (int)sizeof(double2) <= 160 * 1024;
+    __shared__ double2 lds[(PP ? 10 : 5) * P];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
         const double2 a = e[(long long)m * 4 + f], b = e[(long long)m * 4 + f + pstride];
         return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
     };
-    double2* other = lds + (PP ? 5 * L2 : 0);
+    double2* other = lds + (PP ? 5 * P : 0);
     rowfft::pack_rows<L, 4>(lds, tws, tw, N, coef);
     __syncthreads();
     double2* x = rowfft::fft<L2, T, 4, PP>(lds, other, tws, 1.0);
@@ -118,13 +123,14 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
     const double hk = 0.5 / cos2[j];
     for (int k = threadIdx.x; k < L2; k += T) {
         // (x_{2k}, x_{2k+1}) of zeta, Phi', U, V; the five products in place
-        const double2 z = x[k], ph = x[L2 + k], U = x[2 * L2 + k], V = x[3 * L2 + k];
+        const int q = pidx(k);
+        const double2 z = x[q], ph = x[P + q], U = x[2 * P + q], V = x[3 * P + q];
         const double2 eta = make_double2(z.x + fc, z.y + fc);
-        x[k] = make_double2(eta.x * U.x, eta.y * U.y);
-        x[L2 + k] = make_double2(eta.x * V.x, eta.y * V.y);
-        x[2 * L2 + k] = make_double2(ph.x * U.x, ph.y * U.y);
-        x[3 * L2 + k] = make_double2(ph.x * V.x, ph.y * V.y);
-        x[4 * L2 + k] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
+        x[q] = make_double2(eta.x * U.x, eta.y * U.y);
+        x[P + q] = make_double2(eta.x * V.x, eta.y * V.y);
+        x[2 * P + q] = make_double2(ph.x * U.x, ph.y * U.y);
+        x[3 * P + q] = make_double2(ph.x * V.x, ph.y * V.y);
+        x[4 * P + q] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
     }
     __syncthreads();
     const double2* r = rowfft::fft<L2, T, 5, PP>(x, y, tws, -1.0);
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
         double2* o = out + (long long)m * 5;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            const double2 X = rowfft::unpack<L>(r + f * L2, tws, m);
+            const double2 X = rowfft::unpack<L>(r + f * P, tws, m);
             const double sc = (f < 4) ? sv : se;
             o[f] = make_double2(sc * X.x, sc * X.y);
         }

@@ -124,6 +124,13 @@ __device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half
     return idx < half ? w : make_double2(-w.x, -w.y);
 }
 
+// Padded LDS row layout: one spare element after every 16, so that the
+// strided butterfly writes of a stage (stride R elements for the first
+// stage) spread over the LDS banks instead of piling onto a few of them.
+// A row of C complex values takes padded(C) slots; element i sits at pidx(i).
+__host__ __device__ constexpr int padded(int C) { return C + C / 16; }
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+
 // Launch shape for real rows of length L: T threads per workgroup, one per
 // complex point of the half-length FFT (at least 64, at most 1024).
 template <int L>
@@ -133,7 +140,7 @@ struct Cfg {
     static constexpr int T = (T0 + 63) / 64 * 64;
 };
 
-// One Stockham stage for NR complex rows of length C (row stride C), T
+// One Stockham stage for NR complex rows of length C (padded rows), T
 // threads; Ns is the length of the sub-transforms already done.  tws is the
 // LDS twiddle table of the real length 2C (C entries).  Reads src; writes dst
 // (dst == src: in place, with a barrier between the reads and the writes).
@@ -150,10 +157,10 @@ __device__ __forceinline__ void stage(const double2* src, double2* dst, const do
         const int item = threadIdx.x + it * T;
         if (ITEMS % T == 0 || item < ITEMS) {
             const int row = item / NB, j = item - row * NB, k = j % Ns;
-            const double2* b = src + row * C;
+            const double2* b = src + row * padded(C);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                double2 x = b[j + r * NB];
+                double2 x = b[pidx(j + r * NB)];
                 if (Ns > 1 && r > 0) {
                     double2 w = tw_half(tws, r * k * TWS, C);
                     w.y *= -sg;
@@ -171,9 +178,9 @@ __device__ __forceinline__ void stage(const double2* src, double2* dst, const do
         if (ITEMS % T == 0 || item < ITEMS) {
             const int row = item / NB, j = item - row * NB, k = j % Ns;
             const int base = (j / Ns) * Ns * R + k;
-            double2* b = dst + row * C;
+            double2* b = dst + row * padded(C);
 #pragma unroll
-            for (int q = 0; q < R; ++q) b[base + q * Ns] = v[it][q];
+            for (int q = 0; q < R; ++q) b[pidx(base + q * Ns)] = v[it][q];
         }
     }
     __syncthreads();
@@ -211,8 +218,8 @@ __device__ __forceinline__ double2* fft(double2* a, double2* b, const double2* t
     }
 }
 
-// Synthesis input of NR real rows of length L: rows[f * L2 + m] = Z_m of row
-// f, and the LDS twiddle table tws[0..L2) from the global table twg.  The
+// Synthesis input of NR real rows of length L: Z_m of row f at
+// rows[f * padded(L2) + pidx(m)], and the LDS twiddle table tws[0..L2) from the global table twg.  The
 // coefficients X_m (m <= N < L2; zero above N, Im X_0 ignored) come from
 // coef(f, m).  Thread t owns the index pairs (m, L2 - m), m = t, t + T, ...
 // < L2/2; the pair of m = 0 is the middle index L2/2 (e^{2 pi i (L2/2) / L} = i,
@@ -222,7 +229,7 @@ __device__ __forceinline__ double2* fft(double2* a, double2* b, const double2* t
 template <int L, int NR, class Coef>
 __device__ __forceinline__ void pack_rows(double2* rows, double2* tws, const double2* __restrict__ twg, int N,
                                           Coef coef) {
-    constexpr int L2 = L / 2, H = L2 / 2, T = Cfg<L>::T;
+    constexpr int L2 = L / 2, H = L2 / 2, T = Cfg<L>::T, P = padded(L2);
     constexpr int IP = (H + T - 1) / T;
     constexpr int ITW = (L2 + T - 1) / T;
     double2 twv[ITW];
@@ -256,8 +263,8 @@ __device__ __forceinline__ void pack_rows(double2* rows, double2* tws, const dou
 #pragma unroll
             for (int f = 0; f < NR; ++f) {
                 const double a = xa[ip][f].x;                  // Z_0 = X_0 + i X_0, X_0 real
-                rows[f * L2] = make_double2(a, a);
-                rows[f * L2 + H] = make_double2(2.0 * xb[ip][f].x, -2.0 * xb[ip][f].y);
+                rows[f * P] = make_double2(a, a);
+                rows[f * P + pidx(H)] = make_double2(2.0 * xb[ip][f].x, -2.0 * xb[ip][f].y);
             }
             continue;
         }
@@ -273,24 +280,24 @@ __device__ __forceinline__ void pack_rows(double2* rows, double2* tws, const dou
                 const double2 s = make_double2(A.x + B.x, A.y - B.y);
                 const double2 d = make_double2(A.x - B.x, A.y + B.y);
                 const double2 ed = cmul(em, d);
-                rows[f * L2 + m] = make_double2(s.x - ed.y, s.y + ed.x);
+                rows[f * P + pidx(m)] = make_double2(s.x - ed.y, s.y + ed.x);
             }
             {   // Z_j, partner conj X_m
                 const double2 s = make_double2(B.x + A.x, B.y - A.y);
                 const double2 d = make_double2(B.x - A.x, B.y + A.y);
                 const double2 ed = cmul(ej, d);
-                rows[f * L2 + j] = make_double2(s.x - ed.y, s.y + ed.x);
+                rows[f * P + pidx(j)] = make_double2(s.x - ed.y, s.y + ed.x);
             }
         }
     }
 }
 
-// X_m (m <= N) of the real row whose half-length FFT is in `row`.
+// X_m (m <= N) of the real row whose half-length FFT is in `row` (padded).
 template <int L>
 __device__ __forceinline__ double2 unpack(const double2* row, const double2* tws, int m) {
     constexpr int L2 = L / 2;
-    const double2 z = row[m];
-    const double2 zc = row[(L2 - m) % L2];
+    const double2 z = row[pidx(m)];
+    const double2 zc = row[pidx((L2 - m) % L2)];
     const double2 E = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
     const double2 O = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     const double2 wo = cmul(tws[m], O);
