@@ -46,16 +46,18 @@ __device__ inline void swe_prep_row(const double2* __restrict__ state, long long
     const double2* zeta = state + nspec;
     const double2* delta = zeta + nspec;
     const double a2 = a * a;
-    auto get = [&](const double2* x, int nn) -> double2 {
-        if (nn < m || nn > N || nn < 1) return make_double2(0.0, 0.0);
-        const double L = nn * (nn + 1.0) / a2;
+    // -1/L_nn (zero outside the stored degrees and at nn = 0), one division per degree
+    auto neg_inv_l = [&](int nn) { return (nn < m || nn > N || nn < 1) ? 0.0 : -a2 / (nn * (nn + 1.0)); };
+    auto get = [&](const double2* x, int nn, double r) -> double2 {
+        if (r == 0.0) return make_double2(0.0, 0.0);
         const double2 v = x[spec_idx(N, m, nn)];
-        return make_double2(-v.x / L, -v.y / L);
+        return make_double2(r * v.x, r * v.y);
     };
+    const double rd = neg_inv_l(n - 1), r0 = neg_inv_l(n), ru = neg_inv_l(n + 1);
     const double c_dn = (n - 1.0) * eps_nm(n, m);
     const double c_up = (n + 2.0) * eps_nm(n + 1, m);
-    const double2 psd = get(zeta, n - 1), ps0 = get(zeta, n), psu = get(zeta, n + 1);
-    const double2 chd = get(delta, n - 1), ch0 = get(delta, n), chu = get(delta, n + 1);
+    const double2 psd = get(zeta, n - 1, rd), ps0 = get(zeta, n, r0), psu = get(zeta, n + 1, ru);
+    const double2 chd = get(delta, n - 1, rd), ch0 = get(delta, n, r0), chu = get(delta, n + 1, ru);
     const double ia = 1.0 / a;
     const double2 U = make_double2(c_dn * psd.x - c_up * psu.x - m * ch0.y, c_dn * psd.y - c_up * psu.y + m * ch0.x);
     const double2 V = make_double2(-m * ps0.y - c_dn * chd.x + c_up * chu.x, m * ps0.x - c_dn * chd.y + c_up * chu.y);

@@ -102,6 +102,41 @@ __device__ __forceinline__ void combine_one(const double2* __restrict__ cout, co
     fi[2] = make_double2(L * ph.x - p.nu * L * de.x, L * ph.y - p.nu * L * de.y);
 }
 
+// Field c of combine_one (F_E, F_I of Phi', zeta or delta).
+__device__ __forceinline__ void combine_field(const double2* __restrict__ cout, const double2* __restrict__ st,
+                                              int N, long long nspec, const swe_params& p, long long i, int m, int n,
+                                              int c, double2& fe, double2& fi) {
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    const double2* x0 = cout + ext_idx(N, m, n) * 5;
+    const double2* xu = cout + ext_idx(N, m, n + 1) * 5;
+    const bool has_dn = (n - 1 >= m);
+    const double2* xd = has_dn ? cout + ext_idx(N, m, n - 1) * 5 : nullptr;
+    const double cu = n * eps_nm(n + 1, m), cd = (n + 1.0) * eps_nm(n, m);
+    const double ia = 1.0 / p.a;
+    const double2 zero = make_double2(0.0, 0.0);
+    // c = 0: -div(C, D); c = 1: -div(A, B); c = 2: curl(A, B) + L E
+    const int X = (c == 0) ? 2 : 0, Y = X + 1;
+    if (c < 2) {
+        double2 r = cim(m, x0[X]);
+        r = caxpy(cu, xu[Y], r);
+        r = caxpy(-cd, has_dn ? xd[Y] : zero, r);
+        fe = cscale(-ia, r);
+    } else {
+        double2 r = cim(m, x0[Y]);
+        r = caxpy(-cu, xu[X], r);
+        r = caxpy(cd, has_dn ? xd[X] : zero, r);
+        fe = caxpy(L, x0[4], cscale(ia, r));
+    }
+    if (c == 1) {
+        const double2 ze = st[nspec + i];
+        fi = make_double2(-p.nu * L * ze.x, -p.nu * L * ze.y);
+    } else {
+        const double2 ph = st[i], de = st[2 * nspec + i];
+        fi = (c == 0) ? make_double2(-p.phibar * de.x - p.nu * L * ph.x, -p.phibar * de.y - p.nu * L * ph.y)
+                      : make_double2(L * ph.x - p.nu * L * de.x, L * ph.y - p.nu * L * de.y);
+    }
+}
+
 // F_E, F_I from the weighted analyses (A, B, C, D, E) and the state.
 __global__ void k_swe_combine(const int* __restrict__ ord, const int* __restrict__ deg,
                               const double2* __restrict__ cout, const double2* __restrict__ state,
@@ -177,29 +212,33 @@ __global__ void k_f_implicit(const int* __restrict__ deg, const double2* __restr
 //       - h F_I^{m+1,old} + tau^{m+1},   Theta^{m+1} = solve(b, h).
 // With cout != nullptr (m >= 1) the new F at node m is not yet formed: it is
 // combined here from the analyses of node m's tendency (cout) and Theta^m,
-// stored to (fi, fe) node m and used directly.
-__global__ void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ deg, int N, long long nspec,
-                           swe_params p, int m, int M, NodeWeights wt, double h, const double2* __restrict__ th0,
-                           double2* __restrict__ theta, double2* __restrict__ fi, double2* __restrict__ fe,
-                           const double2* __restrict__ fi_old, const double2* __restrict__ fe_old,
-                           const double2* __restrict__ tau, const double2* __restrict__ cout) {
-    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
-    if (i >= nspec) return;
-    const long long ns3 = 3 * nspec;
-    double2 fem[3], fim[3];
-    if (cout) {
-        combine_one(cout, theta + m * ns3, N, nspec, p, i, ord[i], deg[i], fem, fim);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            fe[m * ns3 + c * nspec + i] = fem[c];
-            fi[m * ns3 + c * nspec + i] = fim[c];
+// stored to (fi, fe) node m and used directly.  Blocks of NODE_CO
+// coefficients x 3 fields: wave c accumulates field c; the 2 x 2 solve of
+// (Phi', delta) meets the three right-hand sides in LDS.
+constexpr int NODE_CO = 64;
+__global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ deg,
+                                                        int N, long long nspec, swe_params p, int m, int M,
+                                                        NodeWeights wt, double h, const double2* __restrict__ th0,
+                                                        double2* __restrict__ theta, double2* __restrict__ fi,
+                                                        double2* __restrict__ fe,
+                                                        const double2* __restrict__ fi_old,
+                                                        const double2* __restrict__ fe_old,
+                                                        const double2* __restrict__ tau,
+                                                        const double2* __restrict__ cout) {
+    __shared__ double2 bsh[3][NODE_CO];
+    const int c = threadIdx.x / NODE_CO, loc = threadIdx.x - c * NODE_CO;
+    const long long i = (long long)blockIdx.x * NODE_CO + loc;
+    const bool on = i < nspec;
+    const long long ns3 = 3 * nspec, o = c * nspec + i;
+    double2 acc = make_double2(0.0, 0.0);
+    if (on) {
+        double2 fem = acc, fim = acc;
+        if (cout) {
+            combine_field(cout, theta + m * ns3, N, nspec, p, i, ord[i], deg[i], c, fem, fim);
+            fe[m * ns3 + o] = fem;
+            fi[m * ns3 + o] = fim;
         }
-    }
-    double2 b[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const long long o = c * nspec + i;
-        double2 acc = th0[o];
+        acc = th0[o];
         for (int j = 0; j <= M; ++j) {
             const double2 f = cadd(fi_old[j * ns3 + o], fe_old[j * ns3 + o]);
             acc = caxpy(wt.q[j], f, acc);
@@ -210,21 +249,20 @@ __global__ void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ 
             acc = caxpy(wt.qd[j], csub(fi[j * ns3 + o], fi_old[j * ns3 + o]), acc);
         }
         if (cout) {
-            acc = caxpy(wt.qe[m], csub(fem[c], fe_old[m * ns3 + o]), acc);
-            acc = caxpy(wt.qd[m], csub(fim[c], fi_old[m * ns3 + o]), acc);
+            acc = caxpy(wt.qe[m], csub(fem, fe_old[m * ns3 + o]), acc);
+            acc = caxpy(wt.qd[m], csub(fim, fi_old[m * ns3 + o]), acc);
         }
         acc = caxpy(-h, fi_old[(m + 1) * ns3 + o], acc);
         if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + o]);
-        b[c] = acc;
     }
+    bsh[c][loc] = acc;
+    __syncthreads();
+    if (!on) return;
     const int n = deg[i];
     const double L = n * (n + 1.0) / (p.a * p.a);
     double2 xp, xz, xd;
-    solve_one(L, h, p, b[0], b[1], b[2], xp, xz, xd);
-    double2* out = theta + (m + 1) * ns3;
-    out[i] = xp;
-    out[nspec + i] = xz;
-    out[2 * nspec + i] = xd;
+    solve_one(L, h, p, bsh[0][loc], bsh[1][loc], bsh[2][loc], xp, xz, xd);
+    theta[(m + 1) * ns3 + o] = (c == 0) ? xp : ((c == 1) ? xz : xd);
 }
 
 // dst[i][c] = sum_j Pi[i][j] src[j][map(c)], i in [i0, i1); c runs over the
@@ -426,8 +464,9 @@ hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M
                            const double2* fi_old, const double2* fe_old, const double2* tau,
                            const double2* cout_m, hipStream_t st) {
     if (cout_m && m < 1) return hipErrorInvalidValue;
-    k_sdc_node<<<nblocks(pl->nspec), TB, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, m, M, wts, h, theta0,
-                                                   theta, fi, fe, fi_old, fe_old, tau, cout_m);
+    const unsigned nb = (unsigned)((pl->nspec + NODE_CO - 1) / NODE_CO);
+    k_sdc_node<<<nb, 3 * NODE_CO, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, m, M, wts, h, theta0, theta, fi,
+                                          fe, fi_old, fe_old, tau, cout_m);
     return hipGetLastError();
 }
 
