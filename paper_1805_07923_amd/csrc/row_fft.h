@@ -244,10 +244,15 @@ __device__ __forceinline__ void pack_rows(double2* rows, double2* tws, const dou
         const int m = threadIdx.x + ip * T;
         const int j = (m == 0) ? H : L2 - m;
         const bool on = m < H;
+        const bool ina = on && m <= N, inb = on && j <= N;
+        // unconditional loads from a valid index, then select: every load of
+        // the thread is issued before the first one is waited for
+        const int ma = ina ? m : 0, jb = inb ? j : 0;
 #pragma unroll
         for (int f = 0; f < NR; ++f) {
-            xa[ip][f] = (on && m <= N) ? coef(f, m) : make_double2(0.0, 0.0);
-            xb[ip][f] = (on && j <= N) ? coef(f, j) : make_double2(0.0, 0.0);
+            const double2 va = coef(f, ma), vb = coef(f, jb);
+            xa[ip][f] = ina ? va : make_double2(0.0, 0.0);
+            xb[ip][f] = inb ? vb : make_double2(0.0, 0.0);
         }
     }
 #pragma unroll
