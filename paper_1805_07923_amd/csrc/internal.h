@@ -74,11 +74,12 @@ __device__ inline void swe_prep_row(const double2* __restrict__ state, long long
 // numbered so that every block of an order runs on one XCD, the repeated
 // staging reads hit that XCD's L2; orders are dealt to the XCDs round robin
 // (m = xcd, xcd + 8, ...), which keeps the XCDs' shares of work even.
+// np = 1 for launches that take both parities of an order in one block.
 struct LegTile {
     int x, p, m;
 };
-__device__ inline LegTile leg_tile(int gx, int nm) {
-    const int hw = blockIdx.x, per_m = 2 * gx;
+__device__ inline LegTile leg_tile(int gx, int nm, int np = 2) {
+    const int hw = blockIdx.x, per_m = np * gx;
     if (nm % 8 == 0) {
         const int xcd = hw % 8, slot = hw / 8;
         const int i = slot / per_m, r = slot - i * per_m;
