@@ -376,6 +376,19 @@ class Stepper:
                "mlsdc_step_adj")
         return lam_n
 
+    def graphs(self, dt, like):
+        """HIP graphs of one step and of one adjoint step at time step dt
+        (captured on first use, replayed from fixed buffers): the launch
+        sequence of a step is recorded once instead of being issued kernel by
+        kernel from the host for every step of an integration."""
+        key = float(dt)
+        g = getattr(self, "_graphs", {}).get(key)
+        if g is None:
+            g = _StepGraphs(self, key, like)
+            self._graphs = getattr(self, "_graphs", {})
+            self._graphs[key] = g
+        return g
+
     def step(self, dt, theta_n, theta_np1=None, status=None):
         import torch
         n = 3 * self.fine.plan.nspec
@@ -392,6 +405,43 @@ class Stepper:
         return theta_np1
 
 
+class _StepGraphs:
+    """Captured forward and adjoint step of a Stepper (see Stepper.graphs)."""
+
+    def __init__(self, stepper, dt, like):
+        import torch
+        self.x_in = like.detach().clone().contiguous()
+        self.x_out = torch.empty_like(self.x_in)
+        self.lam_in = torch.zeros_like(self.x_in)
+        self.lam_out = torch.empty_like(self.x_in)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            # workspaces are allocated by these eager calls, before capture
+            stepper.step(dt, self.x_in, self.x_out)
+            stepper.step_adj(dt, self.x_in, self.lam_in, self.lam_out)
+            s.synchronize()
+            self.fwd = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.fwd, stream=s):
+                stepper.step(dt, self.x_in, self.x_out)
+            self.adj = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.adj, stream=s):
+                stepper.step_adj(dt, self.x_in, self.lam_in, self.lam_out)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+
+    def step(self, x):
+        self.x_in.copy_(x)
+        self.fwd.replay()
+        return self.x_out.clone()
+
+    def step_adj(self, x, lam):
+        self.x_in.copy_(x)
+        self.lam_in.copy_(lam)
+        self.adj.replay()
+        return self.lam_out.clone()
+
+
 def _autograd():
     import torch
 
@@ -400,13 +450,14 @@ def _autograd():
         runs the hand-written adjoint step by step from per-step checkpoints."""
 
         @staticmethod
-        def forward(ctx, theta0, stepper, dt, nsteps):
+        def forward(ctx, theta0, stepper, dt, nsteps, graph):
             ckpt = [theta0.detach().contiguous()]
             x = ckpt[0]
+            g = stepper.graphs(dt, x) if graph else None
             for _ in range(nsteps):
-                x = stepper.step(dt, x)
+                x = g.step(x) if g else stepper.step(dt, x)
                 ckpt.append(x)
-            ctx.stepper, ctx.dt = stepper, dt
+            ctx.stepper, ctx.dt, ctx.g = stepper, dt, g
             ctx.ckpt = ckpt[:-1]
             return x.clone()
 
@@ -414,8 +465,8 @@ def _autograd():
         def backward(ctx, grad_out):
             lam = grad_out.contiguous()
             for x in reversed(ctx.ckpt):
-                lam = ctx.stepper.step_adj(ctx.dt, x, lam)
-            return lam, None, None, None
+                lam = ctx.g.step_adj(x, lam) if ctx.g else ctx.stepper.step_adj(ctx.dt, x, lam)
+            return lam, None, None, None, None
 
     class SHInverse(torch.autograd.Function):
         """sh_inverse with its transpose as the backward pass."""
@@ -444,9 +495,10 @@ def _autograd():
     return MLSDCIntegrate, SHInverse, SHForward
 
 
-def integrate(theta0, stepper, dt, nsteps):
-    """Differentiable MLSDC integration (torch.autograd)."""
-    return _autograd()[0].apply(theta0, stepper, dt, nsteps)
+def integrate(theta0, stepper, dt, nsteps, graph=True):
+    """Differentiable MLSDC integration (torch.autograd); with graph=True the
+    forward and adjoint steps replay HIP graphs captured once per (stepper, dt)."""
+    return _autograd()[0].apply(theta0, stepper, dt, nsteps, bool(graph))
 
 
 def sh_inverse_fn(spec, plan):

@@ -236,3 +236,25 @@ def test_integrate_gradient_vs_cpu_reference(pk):
         e = relerr(x.grad[1], xo.grad[1])
         print("gradient vs CPU reference", fine, nsteps, e, flush=True)
         assert e < 1e-10
+
+
+def test_integrate_graph_replays_match_eager(pk):
+    """The captured forward and adjoint steps give the eager results, replay
+    after replay, with eager work in between."""
+    print("CASE integrate graph vs eager", flush=True)
+    par = pk.swe_params()
+    lf = pk.Level(pk.Plan(31, 48, 96), par, pk.SDC_GAUSS_LOBATTO, 5)
+    lc = pk.Level(pk.Plan(15, 24, 48), par, pk.SDC_GAUSS_LOBATTO, 3)
+    stepper = pk.Stepper(lf, lc, niter=4, nsweep_fine=2, nsweep_coarse=2)
+    th0 = torch.tensor(workload.state(31, 1000)).cuda()
+    results = []
+    for graph in (False, True, True):
+        x = th0.clone().requires_grad_(True)
+        y = pk.integrate(x, stepper, 600.0, 3, graph=graph)
+        _loss(y).backward()
+        torch.cuda.synchronize()
+        results.append((y.detach().clone(), x.grad.clone()))
+        stepper.step(600.0, th0)                      # eager work between the replays
+    for y, gr in results[1:]:
+        assert torch.equal(y, results[0][0])
+        assert torch.equal(gr, results[0][1])
