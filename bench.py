@@ -158,7 +158,35 @@ def variants_extra(pk, torch, workload, x0, steps, graph):
     stc1 = make_stepper(pk, C1_FINE, C1_COARSE, NITER, NSWEEP)
     s1, _ = run_steps(torch, stc1, x1, max(5, steps), 2, graph)
     extra["steps_per_s_T127_T63_sweeps_2_2"] = max(5, steps) / s1
+    # the paper's comparison (Sec. 6): MLSDC(5,3,4,1/2) above vs single-level
+    # SDC(5,8) on the fine level alone, same nodes, 8 sweeps
+    par = pk.swe_params()
+    sdc = pk.Stepper(pk.Level(pk.Plan(FINE["N"], FINE["J"], FINE["I"]), par, pk.SDC_GAUSS_LOBATTO, FINE["nodes"]),
+                     None, niter=8, nsweep_fine=1)
+    ssdc, _ = run_steps(torch, sdc, x0, max(5, steps // 2), 2, graph)
+    sdc_rate = max(5, steps // 2) / ssdc
+    extra["steps_per_s_T255_SDC_5_8"] = sdc_rate
+    extra["speedup_MLSDC_5_3_4_vs_SDC_5_8"] = extra["steps_per_s_T255_T127_sweeps_1_1"] / sdc_rate
     return extra
+
+
+def copy_bandwidth(torch, mib=2048):
+    """Achievable HBM bandwidth of a plain device copy (read + write bytes / time)."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) * 1e-3 / 10
+    del src, dst
+    return 2.0 * n * 8 / secs / 1e9
 
 
 def legendre_extra(pk, torch, workload):
@@ -385,6 +413,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "avg_launch_us": an_us, "algorithmic_bytes_per_launch": abytes,
+            "measured_copy_gbs": copy_bandwidth(torch),
             "table_bytes": table_bytes, "timed_launches": reps,
         },
         "kernel_ms_per_step": kinds,
