@@ -243,40 +243,47 @@ __global__ void k_imex_solve_adj(const int* __restrict__ deg, const double2* lx,
 // Transpose of one sweep node update (node m+1) given lth[m+1] (already
 // including the tendency adjoint at that node): lam_b = solve^T(lth[m+1]),
 // lth[m+1] = 0, and lam_b is spread over the inputs of the quadrature.
-__global__ void k_sdc_node_adj(const int* __restrict__ deg, long long nspec, swe_params p, int m, int M,
-                               NodeWeights wt, double h, double2* __restrict__ lth, double2* __restrict__ lfi_new,
-                               double2* __restrict__ lfe_new, double2* __restrict__ lfi_in,
-                               double2* __restrict__ lfe_in, double2* __restrict__ ltau) {
-    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
-    if (i >= nspec) return;
+// Blocks of NODE_ADJ_CO coefficients x 3 fields: every thread solves the
+// transposed 2 x 2 system of its coefficient (the three cotangents of node
+// m+1 are read before any is cleared) and applies field c of the result.
+constexpr int NODE_ADJ_CO = 64;
+__global__ __launch_bounds__(3 * NODE_ADJ_CO) void k_sdc_node_adj(const int* __restrict__ deg, long long nspec,
+                                                                swe_params p, int m, int M, NodeWeights wt,
+                                                                double h, double2* __restrict__ lth,
+                                                                double2* __restrict__ lfi_new,
+                                                                double2* __restrict__ lfe_new,
+                                                                double2* __restrict__ lfi_in,
+                                                                double2* __restrict__ lfe_in,
+                                                                double2* __restrict__ ltau) {
+    const int c = threadIdx.x / NODE_ADJ_CO, loc = threadIdx.x - c * NODE_ADJ_CO;
+    const long long i = (long long)blockIdx.x * NODE_ADJ_CO + loc;
+    const bool on = i < nspec;
     const long long ns3 = 3 * nspec;
-    const int n = deg[i];
-    const double L = n * (n + 1.0) / (p.a * p.a);
     double2* t = lth + (m + 1) * ns3;
-    double2 lb[3];
-    solve_adj_one(L, h, p, t[i], t[nspec + i], t[2 * nspec + i], lb[0], lb[1], lb[2]);
-    const double2 z = make_double2(0.0, 0.0);
-    t[i] = z;
-    t[nspec + i] = z;
-    t[2 * nspec + i] = z;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const long long o = c * nspec + i;
-        const double2 b = lb[c];
-        lth[o] = cadd(lth[o], b);
-        for (int j = 0; j <= M; ++j) {
-            lfi_in[j * ns3 + o] = caxpy(wt.q[j], b, lfi_in[j * ns3 + o]);
-            lfe_in[j * ns3 + o] = caxpy(wt.q[j], b, lfe_in[j * ns3 + o]);
-        }
-        for (int j = 1; j <= m; ++j) {
-            lfe_new[j * ns3 + o] = caxpy(wt.qe[j], b, lfe_new[j * ns3 + o]);
-            lfe_in[j * ns3 + o] = caxpy(-wt.qe[j], b, lfe_in[j * ns3 + o]);
-            lfi_new[j * ns3 + o] = caxpy(wt.qd[j], b, lfi_new[j * ns3 + o]);
-            lfi_in[j * ns3 + o] = caxpy(-wt.qd[j], b, lfi_in[j * ns3 + o]);
-        }
-        lfi_in[(m + 1) * ns3 + o] = caxpy(-h, b, lfi_in[(m + 1) * ns3 + o]);
-        if (ltau) ltau[(m + 1) * ns3 + o] = cadd(ltau[(m + 1) * ns3 + o], b);
+    double2 lb[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    if (on) {
+        const int n = deg[i];
+        const double L = n * (n + 1.0) / (p.a * p.a);
+        solve_adj_one(L, h, p, t[i], t[nspec + i], t[2 * nspec + i], lb[0], lb[1], lb[2]);
     }
+    __syncthreads();                                    // all three reads of node m+1 done
+    if (!on) return;
+    const long long o = c * nspec + i;
+    const double2 b = (c == 0) ? lb[0] : ((c == 1) ? lb[1] : lb[2]);
+    t[o] = make_double2(0.0, 0.0);
+    lth[o] = cadd(lth[o], b);
+    for (int j = 0; j <= M; ++j) {
+        lfi_in[j * ns3 + o] = caxpy(wt.q[j], b, lfi_in[j * ns3 + o]);
+        lfe_in[j * ns3 + o] = caxpy(wt.q[j], b, lfe_in[j * ns3 + o]);
+    }
+    for (int j = 1; j <= m; ++j) {
+        lfe_new[j * ns3 + o] = caxpy(wt.qe[j], b, lfe_new[j * ns3 + o]);
+        lfe_in[j * ns3 + o] = caxpy(-wt.qe[j], b, lfe_in[j * ns3 + o]);
+        lfi_new[j * ns3 + o] = caxpy(wt.qd[j], b, lfi_new[j * ns3 + o]);
+        lfi_in[j * ns3 + o] = caxpy(-wt.qd[j], b, lfi_in[j * ns3 + o]);
+    }
+    lfi_in[(m + 1) * ns3 + o] = caxpy(-h, b, lfi_in[(m + 1) * ns3 + o]);
+    if (ltau) ltau[(m + 1) * ns3 + o] = cadd(ltau[(m + 1) * ns3 + o], b);
 }
 
 // lf[j][map(c)] += sum_{i0 <= i < i1} Pi[i][j] lc[i][c]   (restriction^T = zero padding)
@@ -284,14 +291,12 @@ __global__ void k_restrict_adj(const int* __restrict__ ordc, const int* __restri
                                long long nsc, Mat9x9 Pi, int nsrc, int i0, int i1, const double2* __restrict__ lc,
                                double2* __restrict__ lf) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    const int f = blockIdx.y, j = blockIdx.z;           // field, target node
     if (c >= nsc) return;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    for (int f = 0; f < 3; ++f)
-        for (int j = 0; j < nsrc; ++j) {
-            double2 acc = lf[(j * 3 + f) * nsf + fidx];
-            for (int i = i0; i < i1; ++i) acc = caxpy(Pi.a[i * nsrc + j], lc[(i * 3 + f) * nsc + c], acc);
-            lf[(j * 3 + f) * nsf + fidx] = acc;
-        }
+    double2 acc = lf[(j * 3 + f) * nsf + fidx];
+    for (int i = i0; i < i1; ++i) acc = caxpy(Pi.a[i * nsrc + j], lc[(i * 3 + f) * nsc + c], acc);
+    lf[(j * 3 + f) * nsf + fidx] = acc;
 }
 
 // Transpose of step D for Theta, F_I, F_E: for coarse node i,
@@ -302,26 +307,24 @@ __global__ void k_interp_adj(const int* __restrict__ ordc, const int* __restrict
                              double2* __restrict__ lthc, double2* __restrict__ lthct, double2* __restrict__ lfic,
                              double2* __restrict__ lfict, double2* __restrict__ lfec, double2* __restrict__ lfect) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    const int f = blockIdx.y, i = blockIdx.z;           // field, coarse node
     if (c >= nsc) return;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    for (int f = 0; f < 3; ++f)
-        for (int i = 0; i < nc; ++i) {
-            double2 a = make_double2(0.0, 0.0), b = a, d = a;
-            for (int m = 1; m < nf; ++m) {
-                const double wgt = P.a[m * nc + i];
-                const long long o = (m * 3 + f) * nsf + fidx;
-                a = caxpy(wgt, lthf[o], a);
-                b = caxpy(wgt, lfif[o], b);
-                d = caxpy(wgt, lfef[o], d);
-            }
-            const long long o = (i * 3 + f) * nsc + c;
-            lthc[o] = cadd(lthc[o], a);
-            lthct[o] = csub(lthct[o], a);
-            lfic[o] = cadd(lfic[o], b);
-            lfict[o] = csub(lfict[o], b);
-            lfec[o] = cadd(lfec[o], d);
-            lfect[o] = csub(lfect[o], d);
-        }
+    double2 a = make_double2(0.0, 0.0), b = a, d = a;
+    for (int m = 1; m < nf; ++m) {
+        const double wgt = P.a[m * nc + i];
+        const long long o = (m * 3 + f) * nsf + fidx;
+        a = caxpy(wgt, lthf[o], a);
+        b = caxpy(wgt, lfif[o], b);
+        d = caxpy(wgt, lfef[o], d);
+    }
+    const long long o = (i * 3 + f) * nsc + c;
+    lthc[o] = cadd(lthc[o], a);
+    lthct[o] = csub(lthct[o], a);
+    lfic[o] = cadd(lfic[o], b);
+    lfict[o] = csub(lfict[o], b);
+    lfec[o] = cadd(lfec[o], d);
+    lfect[o] = csub(lfect[o], d);
 }
 
 // Transpose of the FAS term: lfi_f[j], lfe_f[j] += dt Pad(sum_i PQ[i][j] ltau[i]);
@@ -331,23 +334,22 @@ __global__ void k_fas_tau_adj(const int* __restrict__ ordc, const int* __restric
                               const double2* __restrict__ ltau, double2* __restrict__ lfif,
                               double2* __restrict__ lfef, double2* __restrict__ lfic, double2* __restrict__ lfec) {
     const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+    const int f = blockIdx.y, z = blockIdx.z;           // field; fine node z < nf, else coarse node z - nf
     if (c >= nsc) return;
-    const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    for (int f = 0; f < 3; ++f) {
-        for (int j = 0; j < nf; ++j) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int i = 0; i < nc; ++i) acc = caxpy(PQ.a[i * nf + j], ltau[(i * 3 + f) * nsc + c], acc);
-            const long long o = (j * 3 + f) * nsf + fidx;
-            lfif[o] = caxpy(dt, acc, lfif[o]);
-            lfef[o] = caxpy(dt, acc, lfef[o]);
-        }
-        for (int j = 0; j < nc; ++j) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int i = 0; i < nc; ++i) acc = caxpy(Qc.a[i * nc + j], ltau[(i * 3 + f) * nsc + c], acc);
-            const long long o = (j * 3 + f) * nsc + c;
-            lfic[o] = caxpy(-dt, acc, lfic[o]);
-            lfec[o] = caxpy(-dt, acc, lfec[o]);
-        }
+    if (z < nf) {
+        const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < nc; ++i) acc = caxpy(PQ.a[i * nf + z], ltau[(i * 3 + f) * nsc + c], acc);
+        const long long o = (z * 3 + f) * nsf + fidx;
+        lfif[o] = caxpy(dt, acc, lfif[o]);
+        lfef[o] = caxpy(dt, acc, lfef[o]);
+    } else {
+        const int j = z - nf;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < nc; ++i) acc = caxpy(Qc.a[i * nc + j], ltau[(i * 3 + f) * nsc + c], acc);
+        const long long o = (j * 3 + f) * nsc + c;
+        lfic[o] = caxpy(-dt, acc, lfic[o]);
+        lfec[o] = caxpy(-dt, acc, lfec[o]);
     }
 }
 
@@ -429,14 +431,17 @@ hipError_t launch_imex_solve_adj(const shx_plan* pl, const swe_params& p, double
 hipError_t launch_sdc_node_adj(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wt,
                                double h, double2* lth, double2* lfi_new, double2* lfe_new, double2* lfi_in,
                                double2* lfe_in, double2* ltau, hipStream_t st) {
-    k_sdc_node_adj<<<nblocks(pl->nspec), TB, 0, st>>>(pl->deg, pl->nspec, p, m, M, wt, h, lth, lfi_new, lfe_new,
-                                                       lfi_in, lfe_in, ltau);
+    const unsigned nb = (unsigned)((pl->nspec + NODE_ADJ_CO - 1) / NODE_ADJ_CO);
+    k_sdc_node_adj<<<nb, 3 * NODE_ADJ_CO, 0, st>>>(pl->deg, pl->nspec, p, m, M, wt, h, lth, lfi_new, lfe_new,
+                                                  lfi_in, lfe_in, ltau);
     return hipGetLastError();
 }
 
 hipError_t launch_restrict_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc, int i0,
                                int i1, const double2* lc, double2* lf, hipStream_t st) {
-    k_restrict_adj<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
+    if (nsrc <= 0) return hipSuccess;
+    const dim3 g((unsigned)nblocks(coarse->nspec), 3, (unsigned)nsrc);
+    k_restrict_adj<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
                                                            coarse->nspec, Pi, nsrc, i0, i1, lc, lf);
     return hipGetLastError();
 }
@@ -445,7 +450,9 @@ hipError_t launch_interp_adj(const shx_plan* fine, const shx_plan* coarse, const
                              const double2* lthf, const double2* lfif, const double2* lfef, double2* lthc,
                              double2* lthct, double2* lfic, double2* lfict, double2* lfec, double2* lfect,
                              hipStream_t st) {
-    k_interp_adj<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
+    if (nc <= 0) return hipSuccess;
+    const dim3 g((unsigned)nblocks(coarse->nspec), 3, (unsigned)nc);
+    k_interp_adj<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
                                                          coarse->nspec, Pfc, nf, nc, lthf, lfif, lfef, lthc, lthct,
                                                          lfic, lfict, lfec, lfect);
     return hipGetLastError();
@@ -454,7 +461,8 @@ hipError_t launch_interp_adj(const shx_plan* fine, const shx_plan* coarse, const
 hipError_t launch_fas_tau_adj(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& PQ, const Mat9x9& Qc,
                               int nf, int nc, double dt, const double2* ltau, double2* lfif, double2* lfef,
                               double2* lfic, double2* lfec, hipStream_t st) {
-    k_fas_tau_adj<<<nblocks(coarse->nspec), TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
+    const dim3 g((unsigned)nblocks(coarse->nspec), 3, (unsigned)(nf + nc));
+    k_fas_tau_adj<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, fine->nspec,
                                                           coarse->nspec, PQ, Qc, nf, nc, dt, ltau, lfif, lfef, lfic,
                                                           lfec);
     return hipGetLastError();

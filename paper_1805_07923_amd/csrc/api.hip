@@ -382,12 +382,11 @@ namespace {
 // ------------------------------------------------------------------ adjoint
 // Workspace of the tendency adjoint for S states.
 struct TendAdjWS {
-    double2 *cin4, *FIs, *lam5, *FIl, *Ga, *lam4;
+    double2 *FIs, *lam5, *FIl, *Ga, *lam4;
 };
 TendAdjWS carve_tadj(Carve& c, const shx_plan* pl, int S) {
     TendAdjWS t;
     const size_t fj = (size_t)S * pl->J * (pl->N + 1);
-    t.cin4 = c.take<double2>((size_t)S * pl->nspec_e * 4);
     t.FIs = c.take<double2>(fj * 4);
     t.lam5 = c.take<double2>((size_t)S * pl->nspec_e * 5);
     t.FIl = c.take<double2>(fj * 5);
@@ -400,8 +399,7 @@ TendAdjWS carve_tadj(Carve& c, const shx_plan* pl, int S) {
 int tendency_adj_impl(const shx_plan* pl, const swe_params& p, int S, const double2* state, const double2* lfi,
                       const double2* lfe, double2* lstate, const TendAdjWS& t, hipStream_t st) {
     if (lfe) {
-        HIPCHK(launch_swe_prep(pl, p.a, state, t.cin4, S, st));
-        HIPCHK(launch_leg_syn(pl, t.cin4, t.FIs, 4, S, pl->nmax, st));
+        HIPCHK(launch_leg_syn_swe(pl, p.a, state, t.FIs, S, st));
         HIPCHK(launch_combine_adj(pl, p.a, lfe, t.lam5, S, st));
         HIPCHK(launch_leg_syn(pl, t.lam5, t.FIl, 5, S, pl->nmax, st));
         HIPCHK(launch_swe_grid_adj(pl, t.FIs, t.FIl, t.Ga, S, p.omega, st));
