@@ -149,8 +149,8 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid_adj(const double2* __res
                                                                double2* __restrict__ Ga, int N, int J,
                                                                double two_omega) {
     constexpr int L2 = L / 2, T = Cfg<L>::T, P = padded(L2);
-    // two 9-row buffers where LDS has room (L <= 1024), else in place
-    constexpr bool PP = (18 * P + L2) * (int)sizeof(double2) <= 160 * 1024;
+    // two 9-row buffers while the footprint stays small (L <= 192), else in place
+    constexpr bool PP = (18 * P + L2) * (int)sizeof(double2) <= rowfft::PP_LDS_MAX;
     __shared__ double2 lds[(PP ? 18 : 9) * P];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, s = blockIdx.y;

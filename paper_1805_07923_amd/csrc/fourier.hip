@@ -100,8 +100,8 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restric
                                                         double2* __restrict__ G, int N, int J,
                                                         double two_omega) {
     constexpr int L2 = L / 2, T = Cfg<L>::T, P = padded(L2);
-    // two 5-row buffers where LDS has room (L <= 1536), else in place
-    constexpr bool PP = (10 * P + L2) * (int)sizeof(double2) <= 160 * 1024;
+    // two 5-row buffers while the footprint stays small (L <= 384), else in place
+    constexpr bool PP = (10 * P + L2) * (int)sizeof(double2) <= rowfft::PP_LDS_MAX;
     __shared__ double2 lds[(PP ? 10 : 5) * P];
     __shared__ double2 tws[L2];
     const int j = blockIdx.x, s = blockIdx.y;

@@ -131,6 +131,14 @@ __device__ __forceinline__ double2 tw_half(const double2* tws, int idx, int half
 __host__ __device__ constexpr int padded(int C) { return C + C / 16; }
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
+// Largest LDS footprint (bytes per workgroup) for which a row kernel keeps a
+// second set of row buffers for ping-pong stages.  Measured on the 768-point
+// tendency rows (384 workgroups): 71 KB with ping-pong ran 18.1 us, the same
+// kernel in place with 38.8 KB 14.0 us, and the in-place kernel padded with
+// unused LDS to 57 KB or 71 KB again 18.8 us: fewer resident workgroups per
+// CU cost more than the barriers that the second buffer saves.
+constexpr int PP_LDS_MAX = 40 * 1024;
+
 // Launch shape for real rows of length L: T threads per workgroup, one per
 // complex point of the half-length FFT (at least 64, at most 1024).
 template <int L>
