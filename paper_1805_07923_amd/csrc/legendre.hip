@@ -153,6 +153,13 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
     const int k0 = min(K, wv * kq), k1 = min(K, k0 + kq);
     const double* P = psyn + off[2 * m + p] + (active ? jp : 0);
     const long long e0 = ext_idx(N, m, m + p);
+    // The lane's first UNR table values do not depend on the staged rows:
+    // they are requested before the staging so that the table stream is
+    // under way while the coefficients are fetched (rows clamped to the
+    // table, which holds at least one row for every (m, p)).
+    double pf[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) pf[u] = P[(long long)min(k0 + u, max(K - 1, 0)) * Jh];
     for (int s = 0; s < S; ++s) {
         if (s > 0) __syncthreads();                     // previous state's readers are done
         if constexpr (PREP) {
@@ -175,12 +182,7 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
         double ar[NF], ai[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        int k = k0;
-        // UNR table loads in flight per lane before the FMAs consume them
-        for (; k + UNR <= k1; k += UNR) {
-            double pv[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(k + u) * Jh];
+        auto batch = [&](const double* pv, int k) {
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const double2* ck = c + (k + u) * NF;
@@ -190,6 +192,18 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
                     ai[f] = fma(pv[u], ck[f].y, ai[f]);
                 }
             }
+        };
+        int k = k0;
+        if (s == 0 && k + UNR <= k1) {
+            batch(pf, k);
+            k += UNR;
+        }
+        // UNR table loads in flight per lane before the FMAs consume them
+        for (; k + UNR <= k1; k += UNR) {
+            double pv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(k + u) * Jh];
+            batch(pv, k);
         }
         for (; k < k1; ++k) {
             const double pv = P[(long long)k * Jh];
