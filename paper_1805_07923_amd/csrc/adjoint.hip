@@ -246,7 +246,7 @@ __global__ void k_imex_solve_adj(const int* __restrict__ deg, const double2* lx,
 // Blocks of NODE_ADJ_CO coefficients x 3 fields: every thread solves the
 // transposed 2 x 2 system of its coefficient (the three cotangents of node
 // m+1 are read before any is cleared) and applies field c of the result.
-constexpr int NODE_ADJ_CO = 64;
+constexpr int NODE_ADJ_CO = 32;
 __global__ __launch_bounds__(3 * NODE_ADJ_CO) void k_sdc_node_adj(const int* __restrict__ deg, long long nspec,
                                                                 swe_params p, int m, int M, NodeWeights wt,
                                                                 double h, double2* __restrict__ lth,

@@ -213,9 +213,12 @@ __global__ void k_f_implicit(const int* __restrict__ deg, const double2* __restr
 // With cout != nullptr (m >= 1) the new F at node m is not yet formed: it is
 // combined here from the analyses of node m's tendency (cout) and Theta^m,
 // stored to (fi, fe) node m and used directly.  Blocks of NODE_CO
-// coefficients x 3 fields: wave c accumulates field c; the 2 x 2 solve of
-// (Phi', delta) meets the three right-hand sides in LDS.
-constexpr int NODE_CO = 64;
+// coefficients x 3 fields: thread group c accumulates field c; the 2 x 2
+// solve of (Phi', delta) meets the three right-hand sides in LDS.  32
+// coefficients per block (96 threads, a quarter of the second wave idle)
+// measured faster than 64 (8.8 vs 10.1 us at T255): twice the blocks spread
+// the memory-bound loop over more CUs.
+constexpr int NODE_CO = 32;
 __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ deg,
                                                         int N, long long nspec, swe_params p, int m, int M,
                                                         NodeWeights wt, double h, const double2* __restrict__ th0,
