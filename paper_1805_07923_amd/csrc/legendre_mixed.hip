@@ -123,23 +123,43 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();
-        // stage g: FP32 as [jp][CW]; bf16 planes as [q][c][Jhp]
-        for (int i = threadIdx.x; i < Jhp * CW; i += 256) {
-            // columns fastest: consecutive threads read consecutive fields
-            const int jp = i / CW, c = i - jp * CW;
-            double v = 0.0;
-            if (jp < Jh && c < 2 * NF) {
-                const double2 a = g[jp * rowstride + c / 2], b = g[(J - 1 - jp) * rowstride + c / 2];
-                v = (c & 1) ? a.y + sg * b.y : a.x + sg * b.x;
-            }
-            if constexpr (MODE == 1) {
-                reinterpret_cast<float*>(smem)[i] = (float)v;
-            } else {
-                unsigned short h[NP];
-                split_bf16<NP>(v, h);
+        // stage g: FP32 as [jp][CW]; bf16 planes as [q][c][Jhp].  One thread
+        // per complex value (both columns of a field), in rounds of 4 per
+        // thread whose loads (indices clamped to the range) are all issued
+        // before any is used.
+        constexpr int CH = CW / 2;
+        const int tot = Jhp * CH;
+        for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * 256) {
+            double2 v[4];
 #pragma unroll
-                for (int q = 0; q < NP; ++q)
-                    reinterpret_cast<unsigned short*>(smem)[q * Jhp * CW + c * Jhp + jp] = h[q];
+            for (int u = 0; u < 4; ++u) {
+                const int i = min(i0 + u * 256, tot - 1);
+                const int jp = i / CH, f = i - jp * CH;
+                const bool in = jp < Jh && f < NF;
+                const int jc = in ? jp : 0, fc = in ? f : 0;
+                const double2 a = g[jc * rowstride + fc], b = g[(J - 1 - jc) * rowstride + fc];
+                v[u] = in ? make_double2(a.x + sg * b.x, a.y + sg * b.y) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * 256;
+                if (i >= tot) break;
+                const int jp = i / CH, f = i - jp * CH;
+                if constexpr (MODE == 1) {
+                    float* d = reinterpret_cast<float*>(smem) + jp * CW + 2 * f;
+                    d[0] = (float)v[u].x;
+                    d[1] = (float)v[u].y;
+                } else {
+                    unsigned short hr[NP], hi[NP];
+                    split_bf16<NP>(v[u].x, hr);
+                    split_bf16<NP>(v[u].y, hi);
+                    unsigned short* d = reinterpret_cast<unsigned short*>(smem);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        d[q * Jhp * CW + (2 * f) * Jhp + jp] = hr[q];
+                        d[q * Jhp * CW + (2 * f + 1) * Jhp + jp] = hi[q];
+                    }
+                }
             }
         }
         __syncthreads();
@@ -273,15 +293,29 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
                 }
             }
         } else {
-            for (int i = threadIdx.x; i < KL * CW; i += 256) {
-                // columns fastest: consecutive threads read consecutive fields
-                const int k = i / CW, cc = i - k * CW;
-                double v = 0.0;
-                if (k < K && cc < 2 * NF) {
-                    const double2 x = c[(long long)(2 * k) * F + cc / 2];
-                    v = (cc & 1) ? x.y : x.x;
+            // one thread per complex value (both columns of a field), in
+            // rounds of 4 per thread whose loads (indices clamped to the
+            // range) are all issued before any is used
+            constexpr int CH = CW / 2;
+            const int tot = KL * CH;
+            for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * 256) {
+                double2 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = min(i0 + u * 256, tot - 1);
+                    const int k = i / CH, f = i - k * CH;
+                    const bool in = k < K && f < NF;
+                    const double2 x = c[(long long)(2 * (in ? k : 0)) * F + (in ? f : 0)];
+                    v[u] = in ? x : make_double2(0.0, 0.0);
                 }
-                put(k, cc, v);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * 256;
+                    if (i >= tot) break;
+                    const int k = i / CH, f = i - k * CH;
+                    put(k, 2 * f, v[u].x);
+                    put(k, 2 * f + 1, v[u].y);
+                }
             }
         }
         __syncthreads();
