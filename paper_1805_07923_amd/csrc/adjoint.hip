@@ -374,6 +374,17 @@ __global__ void k_zero(double2* __restrict__ x, long long n) {
     if (e < n) x[e] = make_double2(0.0, 0.0);
 }
 
+// The same over the arrays of a list (blockIdx.y picks the array).
+__global__ void k_zero_n(ArrayList a, long long n) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e < n) a.y[blockIdx.y][e] = make_double2(0.0, 0.0);
+}
+__global__ void k_add_n(ArrayList a, long long n) {
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    double2* y = a.y[blockIdx.y];
+    if (e < n) y[e] = cadd(y[e], a.x[blockIdx.y][e]);
+}
+
 template <int L>
 hipError_t grid_adj_t(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S, double omega,
                       hipStream_t st) {
@@ -475,6 +486,20 @@ hipError_t launch_node_sum(const double2* x, double2* y, long long n3, int nn, i
 
 hipError_t launch_add(const double2* x, double2* y, long long n, hipStream_t st) {
     k_add<<<nblocks(n), TB, 0, st>>>(x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_n(const ArrayList& a, long long n, hipStream_t st) {
+    if (n <= 0 || a.k < 1) return hipSuccess;
+    if (a.k > 8) return hipErrorInvalidValue;
+    k_zero_n<<<dim3(nblocks(n), a.k), TB, 0, st>>>(a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_n(const ArrayList& a, long long n, hipStream_t st) {
+    if (n <= 0 || a.k < 1) return hipSuccess;
+    if (a.k > 8) return hipErrorInvalidValue;
+    k_add_n<<<dim3(nblocks(n), a.k), TB, 0, st>>>(a, n);
     return hipGetLastError();
 }
 

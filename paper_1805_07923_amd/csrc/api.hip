@@ -135,12 +135,11 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
         // the F of node m (m >= 1) is formed inside this node update from t.cout
         HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
             return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi_new, fe_new, fi_old, fe_old, tau,
-                                   m > 0 ? t.cout : nullptr, st);
+                                   m > 0 ? t.cout : nullptr, rec ? rec + (size_t)m * ns3 : nullptr, st);
         }));
         const size_t o = (size_t)(m + 1) * ns3;
         int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st, false);
         if (rc) return rc;
-        if (rec) HIPCHK(hipMemcpyAsync(rec + (size_t)m * ns3, th + o, ns3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
     }
     const size_t oM = (size_t)M * ns3;
     HIPCHK(launch_swe_combine(pl, lv->p, t.cout, th + oM, fi_new + oM, fe_new + oM, 1, st));
@@ -419,8 +418,12 @@ int sweep_adj_impl(const sdc_level* lv, double dt, const double2* states, double
     const shx_plan* pl = lv->plan;
     const int M = lv->nnodes - 1, n1 = lv->nnodes;
     const size_t ns3 = 3 * (size_t)pl->nspec;
-    HIPCHK(launch_add(lfi_out, lfi_in, (long long)ns3, st));      // node 0 passes through
-    HIPCHK(launch_add(lfe_out, lfe_in, (long long)ns3, st));
+    {   // node 0 passes through
+        ArrayList a{};
+        a.add(lfi_in, lfi_out);
+        a.add(lfe_in, lfe_out);
+        HIPCHK(launch_add_n(a, (long long)ns3, st));
+    }
     for (int m = M - 1; m >= 0; --m) {
         const size_t o = (size_t)(m + 1) * ns3;
         int rc = tendency_adj_impl(pl, lv->p, 1, states + (size_t)m * ns3, lfi_out + o, lfe_out + o, lth + o, t, st);
@@ -803,9 +806,13 @@ int mlsdc_step_adj(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o
     int rc = step_body(fl, cl, &fo, dt, th_n, lout, nullptr, w.fw, &w.tape, st);
     if (rc) return rc;
     // 2. reverse pass
-    HIPCHK(launch_zero(w.lthf, (long long)nfa, st));
-    for (int b = 0; b < 2; ++b)
-        for (int q = 0; q < 2; ++q) HIPCHK(launch_zero(w.lff[b][q], (long long)nfa, st));
+    {
+        ArrayList z{};
+        z.add(w.lthf);
+        for (int b = 0; b < 2; ++b)
+            for (int q = 0; q < 2; ++q) z.add(w.lff[b][q]);
+        HIPCHK(launch_zero_n(z, (long long)nfa, st));
+    }
     HIPCHK(hipMemcpyAsync(w.lthf + Mf * nf3, lam_np1, nf3 * sizeof(double2), hipMemcpyDeviceToDevice, st));
     const shx_plan* pc = cl ? cl->plan : nullptr;
     int Mc = 0, nsc = 0;
@@ -817,37 +824,49 @@ int mlsdc_step_adj(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o
         nc3 = 3 * (size_t)pc->nspec;
         nca = (size_t)cl->nnodes * nc3;
         if (level_pair_matrices(fl, cl, Pcf, Pfc, PQ, Qc)) return SHX_EINVAL;
-        HIPCHK(launch_zero(w.lthc0, (long long)nc3, st));
-        HIPCHK(launch_zero(w.lfic0, (long long)nc3, st));
-        HIPCHK(launch_zero(w.lfec0, (long long)nc3, st));
+        ArrayList z{};
+        z.add(w.lthc0);
+        z.add(w.lfic0);
+        z.add(w.lfec0);
+        HIPCHK(launch_zero_n(z, (long long)nc3, st));
     }
     int fc = 0;
     for (int k = o->niter - 1; k >= 0; --k) {
         if (cl) {
             int cc = 0;
-            HIPCHK(launch_zero(w.lthc, (long long)nca, st));
-            HIPCHK(launch_zero(w.lthct, (long long)nca, st));
-            HIPCHK(launch_zero(w.lfict, (long long)nca, st));
-            HIPCHK(launch_zero(w.lfect, (long long)nca, st));
-            HIPCHK(launch_zero(w.lfc[cc][0], (long long)nca, st));
-            HIPCHK(launch_zero(w.lfc[cc][1], (long long)nca, st));
-            HIPCHK(launch_zero(w.ltau, (long long)nca, st));
+            {
+                ArrayList z{};
+                z.add(w.lthc);
+                z.add(w.lthct);
+                z.add(w.lfict);
+                z.add(w.lfect);
+                z.add(w.lfc[cc][0]);
+                z.add(w.lfc[cc][1]);
+                z.add(w.ltau);
+                HIPCHK(launch_zero_n(z, (long long)nca, st));
+            }
             // D^T
             HIPCHK(launch_interp_adj(pf, pc, Pfc, fl->nnodes, cl->nnodes, w.lthf, w.lff[fc][0], w.lff[fc][1], w.lthc,
                                      w.lthct, w.lfc[cc][0], w.lfict, w.lfc[cc][1], w.lfect, st));
             // C^T: coarse sweeps in reverse
             const size_t cbase = 1 + (size_t)k * (Mc + nsc * Mc);
             for (int s2 = nsc - 1; s2 >= 0; --s2) {
-                HIPCHK(launch_zero(w.lfc[1 - cc][0], (long long)nca, st));
-                HIPCHK(launch_zero(w.lfc[1 - cc][1], (long long)nca, st));
+                ArrayList z{};
+                z.add(w.lfc[1 - cc][0]);
+                z.add(w.lfc[1 - cc][1]);
+                HIPCHK(launch_zero_n(z, (long long)nca, st));
                 rc = sweep_adj_impl(cl, dt, w.tape.c + (cbase + Mc + (size_t)s2 * Mc) * nc3, w.lthc, w.lfc[cc][0],
                                     w.lfc[cc][1], w.lfc[1 - cc][0], w.lfc[1 - cc][1], w.ltau, w.tc, st);
                 if (rc) return rc;
                 cc = 1 - cc;
             }
             // adjoint of F at the restricted states: sweep input + saved copy
-            HIPCHK(launch_add(w.lfict, w.lfc[cc][0], (long long)nca, st));
-            HIPCHK(launch_add(w.lfect, w.lfc[cc][1], (long long)nca, st));
+            {
+                ArrayList a{};
+                a.add(w.lfc[cc][0], w.lfict);
+                a.add(w.lfc[cc][1], w.lfect);
+                HIPCHK(launch_add_n(a, (long long)nca, st));
+            }
             HIPCHK(launch_fas_tau_adj(pf, pc, PQ, Qc, fl->nnodes, cl->nnodes, dt, w.ltau, w.lff[fc][0], w.lff[fc][1],
                                       w.lfc[cc][0], w.lfc[cc][1], st));
             // B^T: restricted Theta adjoint = lthc + lthct + F^T at the restricted states
@@ -857,14 +876,20 @@ int mlsdc_step_adj(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o
             if (rc) return rc;
             HIPCHK(launch_restrict_adj(pf, pc, Pcf, fl->nnodes, 1, cl->nnodes, w.lthct, w.lthf, st));
             // coarse node 0 belongs to the whole step
-            HIPCHK(launch_add(w.lthct, w.lthc0, (long long)nc3, st));
-            HIPCHK(launch_add(w.lfc[cc][0], w.lfic0, (long long)nc3, st));
-            HIPCHK(launch_add(w.lfc[cc][1], w.lfec0, (long long)nc3, st));
+            {
+                ArrayList a{};
+                a.add(w.lthc0, w.lthct);
+                a.add(w.lfic0, w.lfc[cc][0]);
+                a.add(w.lfec0, w.lfc[cc][1]);
+                HIPCHK(launch_add_n(a, (long long)nc3, st));
+            }
         }
         // A^T: fine sweeps in reverse
         for (int s2 = nsf - 1; s2 >= 0; --s2) {
-            HIPCHK(launch_zero(w.lff[1 - fc][0], (long long)nfa, st));
-            HIPCHK(launch_zero(w.lff[1 - fc][1], (long long)nfa, st));
+            ArrayList z{};
+            z.add(w.lff[1 - fc][0]);
+            z.add(w.lff[1 - fc][1]);
+            HIPCHK(launch_zero_n(z, (long long)nfa, st));
             rc = sweep_adj_impl(fl, dt, w.tape.f + (1 + (size_t)(k * nsf + s2) * Mf) * nf3, w.lthf, w.lff[fc][0],
                                 w.lff[fc][1], w.lff[1 - fc][0], w.lff[1 - fc][1], nullptr, w.tf, st);
             if (rc) return rc;

@@ -181,10 +181,11 @@ hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const doub
                              double2* fi, int S, hipStream_t st);
 // cout_m != nullptr (m >= 1): the new F at node m is formed from these
 // analyses of node m's tendency inside the node update (and stored).
+// rec != nullptr: Theta^{m+1} is also stored there (the adjoint's tape).
 hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
                            double h, const double2* theta0, double2* theta, double2* fi, double2* fe,
                            const double2* fi_old, const double2* fe_old, const double2* tau,
-                           const double2* cout_m, hipStream_t st);
+                           const double2* cout_m, double2* rec, hipStream_t st);
 hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc,
                            int i0, int i1, const double2* src, double2* dst, double2* dst2, hipStream_t st);
 // Copies of node 0 of up to 6 node arrays to node ranges of (other) node arrays.
@@ -240,3 +241,12 @@ hipError_t launch_fas_tau_adj(const shx_plan* fine, const shx_plan* coarse, cons
 hipError_t launch_node_sum(const double2* x, double2* y, long long n3, int nn, int acc, hipStream_t st);
 hipError_t launch_add(const double2* x, double2* y, long long n, hipStream_t st);
 hipError_t launch_zero(double2* x, long long n, hipStream_t st);
+// Up to 8 arrays of the same length in one launch: y[i] = 0, or y[i] += x[i].
+struct ArrayList {
+    double2* y[8];
+    const double2* x[8];
+    int k;
+    void add(double2* yi, const double2* xi = nullptr) { y[k] = yi; x[k] = xi; ++k; }
+};
+hipError_t launch_zero_n(const ArrayList& a, long long n, hipStream_t st);
+hipError_t launch_add_n(const ArrayList& a, long long n, hipStream_t st);

@@ -227,7 +227,8 @@ __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict_
                                                         const double2* __restrict__ fi_old,
                                                         const double2* __restrict__ fe_old,
                                                         const double2* __restrict__ tau,
-                                                        const double2* __restrict__ cout) {
+                                                        const double2* __restrict__ cout,
+                                                        double2* __restrict__ rec) {
     __shared__ double2 bsh[3][NODE_CO];
     const int c = threadIdx.x / NODE_CO, loc = threadIdx.x - c * NODE_CO;
     const long long i = (long long)blockIdx.x * NODE_CO + loc;
@@ -265,7 +266,9 @@ __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict_
     const double L = n * (n + 1.0) / (p.a * p.a);
     double2 xp, xz, xd;
     solve_one(L, h, p, bsh[0][loc], bsh[1][loc], bsh[2][loc], xp, xz, xd);
-    theta[(m + 1) * ns3 + o] = (c == 0) ? xp : ((c == 1) ? xz : xd);
+    const double2 v = (c == 0) ? xp : ((c == 1) ? xz : xd);
+    theta[(m + 1) * ns3 + o] = v;
+    if (rec) rec[o] = v;
 }
 
 // dst[i][c] = sum_j Pi[i][j] src[j][map(c)], i in [i0, i1); c runs over the
@@ -465,11 +468,11 @@ hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const doub
 hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
                            double h, const double2* theta0, double2* theta, double2* fi, double2* fe,
                            const double2* fi_old, const double2* fe_old, const double2* tau,
-                           const double2* cout_m, hipStream_t st) {
+                           const double2* cout_m, double2* rec, hipStream_t st) {
     if (cout_m && m < 1) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((pl->nspec + NODE_CO - 1) / NODE_CO);
     k_sdc_node<<<nb, 3 * NODE_CO, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, m, M, wts, h, theta0, theta, fi,
-                                          fe, fi_old, fe_old, tau, cout_m);
+                                          fe, fi_old, fe_old, tau, cout_m, rec);
     return hipGetLastError();
 }
 
