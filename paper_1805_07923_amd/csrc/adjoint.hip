@@ -43,41 +43,11 @@ __global__ void k_combine_adj(const int* __restrict__ ord_e, const int* __restri
     const long long e = (long long)blockIdx.x * TB + threadIdx.x;
     const int s = blockIdx.y;
     if (e >= nspec_e || s >= S) return;
-    const int m = ord_e[e], n = deg_e[e];
-    const double2* lp = lfe + (long long)s * 3 * nspec;   // cotangent of F_E,Phi
-    const double2* lz = lp + nspec;                        // F_E,zeta
-    const double2* ld = lz + nspec;                        // F_E,delta
-    const double2 z = make_double2(0.0, 0.0);
-    auto get = [&](const double2* x, int k) { return (k >= m && k <= N) ? x[spec_idx(N, m, k)] : z; };
-    const double ia = 1.0 / a;
-    const double cdn = (n - 1.0) * eps_nm(n, m), cup = (n + 2.0) * eps_nm(n + 1, m);
-    // div(X, Y) with cotangent q: X_n += -i m q_n / a; Y_n += [(n-1) eps_n q_{n-1} - (n+2) eps_{n+1} q_{n+1}] / a
-    // curl(X, Y) with cotangent r: Y_n += -i m r_n / a; X_n += [-(n-1) eps_n r_{n-1} + (n+2) eps_{n+1} r_{n+1}] / a
-    // F_E = [-div(C, D), -div(A, B), curl(A, B) + L E^]: q_AB = -lz, q_CD = -lp, r_AB = ld
-    const double2 qab0 = cscale(-1.0, get(lz, n)), qabd = cscale(-1.0, get(lz, n - 1)),
-                  qabu = cscale(-1.0, get(lz, n + 1));
-    const double2 qcd0 = cscale(-1.0, get(lp, n)), qcdd = cscale(-1.0, get(lp, n - 1)),
-                  qcdu = cscale(-1.0, get(lp, n + 1));
-    const double2 r0 = get(ld, n), rd = get(ld, n - 1), ru = get(ld, n + 1);
-    double2 A = cim(-m, qab0);
-    A = caxpy(-cdn, rd, A);
-    A = caxpy(cup, ru, A);
-    double2 B = cim(-m, r0);
-    B = caxpy(cdn, qabd, B);
-    B = caxpy(-cup, qabu, B);
-    double2 C = cim(-m, qcd0);
-    double2 D = make_double2(0.0, 0.0);
-    D = caxpy(cdn, qcdd, D);
-    D = caxpy(-cup, qcdu, D);
-    const double L = n * (n + 1.0) / (a * a);
-    double2 E = (n <= N) ? cscale(L, r0) : z;
-    const double hm = (m == 0) ? ia : 0.5 * ia;             // 1/a and the halving for m >= 1
-    double2* o = lam5 + ((long long)s * nspec_e + e) * 5;
-    o[0] = cscale(hm, A);
-    o[1] = cscale(hm, B);
-    o[2] = cscale(hm, C);
-    o[3] = cscale(hm, D);
-    o[4] = cscale(m == 0 ? 1.0 : 0.5, E);
+    double2 o[5];
+    swe_combine_adj_row(lfe + (long long)s * 3 * nspec, nspec, N, a, ord_e[e], deg_e[e], o);
+    double2* out = lam5 + ((long long)s * nspec_e + e) * 5;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) out[f] = o[f];
 }
 
 // Transpose of the wind coefficients and of F_I, accumulated into lam_state:

@@ -399,8 +399,12 @@ int tendency_adj_impl(const shx_plan* pl, const swe_params& p, int S, const doub
                       const double2* lfe, double2* lstate, const TendAdjWS& t, hipStream_t st) {
     if (lfe) {
         HIPCHK(launch_leg_syn_swe(pl, p.a, state, t.FIs, S, st));
-        HIPCHK(launch_combine_adj(pl, p.a, lfe, t.lam5, S, st));
-        HIPCHK(launch_leg_syn(pl, t.lam5, t.FIl, 5, S, pl->nmax, st));
+        if (pl->prec == SHX_FP64) {
+            HIPCHK(launch_leg_syn_swe_adj(pl, p.a, lfe, t.FIl, S, st));
+        } else {
+            HIPCHK(launch_combine_adj(pl, p.a, lfe, t.lam5, S, st));
+            HIPCHK(launch_leg_syn(pl, t.lam5, t.FIl, 5, S, pl->nmax, st));
+        }
         HIPCHK(launch_swe_grid_adj(pl, t.FIs, t.FIl, t.Ga, S, p.omega, st));
         HIPCHK(launch_leg_an(pl, t.Ga, t.lam4, 4, S, pl->nmax, st));
     }

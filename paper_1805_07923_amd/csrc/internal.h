@@ -67,6 +67,52 @@ __device__ inline void swe_prep_row(const double2* __restrict__ state, long long
     o[3] = make_double2(ia * V.x, ia * V.y);
 }
 
+// Transpose of the F_E combine (F_E = [-div(C, D), -div(A, B), curl(A, B)
+// + L E^] of the weighted analyses A..E) at ext entry (m, n), followed by
+// the halving of m >= 1 that turns the analysis adjoint into a synthesis.
+// lfe: cotangents of F_E [3][nspec] (Phi', zeta, delta); o: cotangents of
+// (A, B, C, D, E)^ at (m, n).  With the cotangent q of div(X, Y):
+// X_n += -i m q_n / a, Y_n += [(n-1) eps_n q_{n-1} - (n+2) eps_{n+1} q_{n+1}] / a;
+// with the cotangent r of curl(X, Y): Y_n += -i m r_n / a,
+// X_n += [-(n-1) eps_n r_{n-1} + (n+2) eps_{n+1} r_{n+1}] / a.
+__device__ inline void swe_combine_adj_row(const double2* __restrict__ lfe, long long nspec, int N, double a, int m,
+                                           int n, double2 o[5]) {
+    const double2* lp = lfe;
+    const double2* lz = lp + nspec;
+    const double2* ld = lz + nspec;
+    auto get = [&](const double2* x, int k) {
+        return (k >= m && k <= N) ? x[spec_idx(N, m, k)] : make_double2(0.0, 0.0);
+    };
+    auto neg = [](double2 v) { return make_double2(-v.x, -v.y); };
+    auto cim = [](double mu, double2 v) { return make_double2(-mu * v.y, mu * v.x); };   // i mu v
+    auto axpy = [](double s, double2 x, double2 y) { return make_double2(fma(s, x.x, y.x), fma(s, x.y, y.y)); };
+    const double cdn = (n - 1.0) * eps_nm(n, m), cup = (n + 2.0) * eps_nm(n + 1, m);
+    // q_AB = -lz, q_CD = -lp, r_AB = ld
+    const double2 qab0 = neg(get(lz, n)), qabd = neg(get(lz, n - 1)), qabu = neg(get(lz, n + 1));
+    const double2 qcd0 = neg(get(lp, n)), qcdd = neg(get(lp, n - 1)), qcdu = neg(get(lp, n + 1));
+    const double2 r0 = get(ld, n), rd = get(ld, n - 1), ru = get(ld, n + 1);
+    double2 A = cim(-m, qab0);
+    A = axpy(-cdn, rd, A);
+    A = axpy(cup, ru, A);
+    double2 B = cim(-m, r0);
+    B = axpy(cdn, qabd, B);
+    B = axpy(-cup, qabu, B);
+    const double2 C = cim(-m, qcd0);
+    double2 D = make_double2(0.0, 0.0);
+    D = axpy(cdn, qcdd, D);
+    D = axpy(-cup, qcdu, D);
+    const double L = n * (n + 1.0) / (a * a);
+    const double2 E = (n <= N) ? make_double2(L * r0.x, L * r0.y) : make_double2(0.0, 0.0);
+    const double ia = 1.0 / a;
+    const double hm = (m == 0) ? ia : 0.5 * ia;          // 1/a and the halving for m >= 1
+    const double he = (m == 0) ? 1.0 : 0.5;
+    o[0] = make_double2(hm * A.x, hm * A.y);
+    o[1] = make_double2(hm * B.x, hm * B.y);
+    o[2] = make_double2(hm * C.x, hm * C.y);
+    o[3] = make_double2(hm * D.x, hm * D.y);
+    o[4] = make_double2(he * E.x, he * E.y);
+}
+
 // ------------------------------------------------------ XCD-aware blocks
 // Workgroups go to the 8 XCDs of the chip round robin by hardware id, and
 // each XCD has its own L2.  A Legendre launch has gx blocks per (order m,
@@ -145,6 +191,12 @@ hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, 
 // [S][3][nspec]: swe_prep_row feeds the staging (any working precision).
 hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
                               hipStream_t st);
+// Synthesis of the five cotangent fields of the tendency adjoint straight
+// from the F_E cotangents [S][3][nspec]: swe_combine_adj_row feeds the
+// staging (FP64 plans; other working precisions run the combine transpose
+// and the synthesis as two launches).
+hipError_t launch_leg_syn_swe_adj(const shx_plan* pl, double a, const double2* lfe, double2* out, int S,
+                                  hipStream_t st);
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
                          int nmax_use, hipStream_t st);
 // legendre_mixed.hip (plans with a reduced working precision)

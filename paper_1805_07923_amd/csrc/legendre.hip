@@ -131,10 +131,12 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
 // wavefronts split the degree sum into quarters.  The coefficients of this
 // (m, p) are the same for every lane: they are staged in LDS (dynamic LDS:
 // K * NF double2) and read by broadcast.  Wave 0 adds the partial sums of
-// waves 1..3 (LDS) in a fixed order.  With PREP, cin holds states
+// waves 1..3 (LDS) in a fixed order.  STAGE = 1: cin holds states
 // [S][3][nspec] and the staged rows are the tendency's grid fields
-// (swe_prep_row; NF = F = 4).
-template <int NF, bool PREP = false>
+// (swe_prep_row; NF = F = 4).  STAGE = 2: cin holds F_E cotangents
+// [S][3][nspec] and the staged rows are the cotangents of the five weighted
+// analyses (swe_combine_adj_row; NF = F = 5).
+template <int NF, int STAGE = 0>
 __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn,
                                                  const long long* __restrict__ off,
                                                  const double2* __restrict__ cin,
@@ -162,13 +164,21 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
     for (int u = 0; u < UNR; ++u) pf[u] = P[(long long)min(k0 + u, max(K - 1, 0)) * Jh];
     for (int s = 0; s < S; ++s) {
         if (s > 0) __syncthreads();                     // previous state's readers are done
-        if constexpr (PREP) {
+        if constexpr (STAGE == 1) {
             static_assert(NF == 4, "the tendency synthesis has four fields");
             for (int kk = threadIdx.x; kk < K; kk += 256) {
                 double2 o[4];
                 swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * kk, o);
 #pragma unroll
                 for (int f = 0; f < 4; ++f) csh[kk * 4 + f] = o[f];
+            }
+        } else if constexpr (STAGE == 2) {
+            static_assert(NF == 5, "the tendency adjoint synthesises five fields");
+            for (int kk = threadIdx.x; kk < K; kk += 256) {
+                double2 o[5];
+                swe_combine_adj_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * kk, o);
+#pragma unroll
+                for (int f = 0; f < 5; ++f) csh[kk * 5 + f] = o[f];
             }
         } else {
             const double2* cg = cin + s * cin_stride + e0 * F + f0;
@@ -383,9 +393,20 @@ hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state
     if (pl->prec != SHX_FP64) return launch_leg_syn_mixed_swe(pl, a, state, out, S, st);
     const int gx = (pl->Jh + 63) / 64;
     const size_t lds = (size_t)kcount(pl->nmax, 0, 0) * 4 * sizeof(double2);
-    k_leg_syn<4, true><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, state, out, pl->N, pl->nmax,
-                                                            pl->Jh, 4, 0, S, 3 * pl->nspec,
-                                                            (long long)pl->J * (pl->N + 1) * 4, gx, pl->nspec, a);
+    k_leg_syn<4, 1><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, state, out, pl->N, pl->nmax,
+                                                         pl->Jh, 4, 0, S, 3 * pl->nspec,
+                                                         (long long)pl->J * (pl->N + 1) * 4, gx, pl->nspec, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_syn_swe_adj(const shx_plan* pl, double a, const double2* lfe, double2* out, int S,
+                                  hipStream_t st) {
+    if (pl->prec != SHX_FP64) return hipErrorInvalidValue;
+    const int gx = (pl->Jh + 63) / 64;
+    const size_t lds = (size_t)kcount(pl->nmax, 0, 0) * 5 * sizeof(double2);
+    k_leg_syn<5, 2><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, lfe, out, pl->N, pl->nmax,
+                                                         pl->Jh, 5, 0, S, 3 * pl->nspec,
+                                                         (long long)pl->J * (pl->N + 1) * 5, gx, pl->nspec, a);
     return hipGetLastError();
 }
 
