@@ -64,8 +64,11 @@ __global__ void k_prep_adj(const int* __restrict__ ord, const int* __restrict__ 
     double2 lphi = make_double2(0.0, 0.0), lzeta = lphi, ldelta = lphi;
     if (has_fe) {
         const double2* l4 = lam4 + (long long)s * nspec_e * 4;
-        const double2 z = make_double2(0.0, 0.0);
-        auto g4 = [&](int k, int f) { return (k >= m && k <= N + 1) ? l4[ext_idx(N, m, k) * 4 + f] : z; };
+        // a value, not a reference, on both branches (no address select with a local)
+        auto g4 = [&](int k, int f) -> double2 {
+            if (k < m || k > N + 1) return make_double2(0.0, 0.0);
+            return l4[ext_idx(N, m, k) * 4 + f];
+        };
         const double ia = 1.0 / p.a;
         const double cu = n * eps_nm(n + 1, m), cd = (n + 1.0) * eps_nm(n, m);
         // psi_n appears in U_{n+1} (n eps_{n+1}), U_{n-1} (-(n+1) eps_n), V_n (i m)
