@@ -341,12 +341,6 @@ __global__ void k_add(const double2* __restrict__ x, double2* __restrict__ y, lo
     if (e < n) y[e] = cadd(y[e], x[e]);
 }
 
-// x = 0 over n complex values (a kernel, usable under graph capture).
-__global__ void k_zero(double2* __restrict__ x, long long n) {
-    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
-    if (e < n) x[e] = make_double2(0.0, 0.0);
-}
-
 // The same over the arrays of a list (blockIdx.y picks the array).
 __global__ void k_zero_n(ArrayList a, long long n) {
     const long long e = (long long)blockIdx.x * TB + threadIdx.x;
@@ -476,8 +470,3 @@ hipError_t launch_add_n(const ArrayList& a, long long n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_zero(double2* x, long long n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    k_zero<<<nblocks(n), TB, 0, st>>>(x, n);
-    return hipGetLastError();
-}

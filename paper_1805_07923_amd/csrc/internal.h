@@ -223,14 +223,10 @@ bool fft_length_supported(int L);
 hipError_t launch_spec_to_ext(const shx_plan* pl, const double2* spec, double2* cin, int F, int halve,
                               hipStream_t st);
 hipError_t launch_ext_to_spec(const shx_plan* pl, const double2* cout, double2* spec, int F, hipStream_t st);
-hipError_t launch_swe_prep(const shx_plan* pl, double a, const double2* state, double2* cin, int S,
-                           hipStream_t st);
 hipError_t launch_swe_combine(const shx_plan* pl, const swe_params& p, const double2* cout,
                               const double2* state, double2* fi, double2* fe, int S, hipStream_t st);
 hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, const double2* rhs,
                              double2* out, int S, hipStream_t st);
-hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const double2* state,
-                             double2* fi, int S, hipStream_t st);
 // cout_m != nullptr (m >= 1): the new F at node m is formed from these
 // analyses of node m's tendency inside the node update (and stored).
 // rec != nullptr: Theta^{m+1} is also stored there (the adjoint's tape).
@@ -292,7 +288,6 @@ hipError_t launch_fas_tau_adj(const shx_plan* fine, const shx_plan* coarse, cons
                               double2* lfic, double2* lfec, hipStream_t st);
 hipError_t launch_node_sum(const double2* x, double2* y, long long n3, int nn, int acc, hipStream_t st);
 hipError_t launch_add(const double2* x, double2* y, long long n, hipStream_t st);
-hipError_t launch_zero(double2* x, long long n, hipStream_t st);
 // Up to 8 arrays of the same length in one launch: y[i] = 0, or y[i] += x[i].
 struct ArrayList {
     double2* y[8];

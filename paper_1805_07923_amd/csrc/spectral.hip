@@ -52,20 +52,6 @@ __global__ void k_ext_to_spec(const int* __restrict__ ord, const int* __restrict
     for (int f = 0; f < F; ++f) spec[f * nspec + i] = cout[e * F + f];
 }
 
-// cin[s][e][0..3] = (zeta, Phi', U, V) at (m, n = deg_e[e]), n <= N+1.
-__global__ void k_swe_prep(const int* __restrict__ ord_e, const int* __restrict__ deg_e,
-                           const double2* __restrict__ state, double2* __restrict__ cin, int N,
-                           long long nspec, long long nspec_e, double a, int S) {
-    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
-    const int s = blockIdx.y;
-    if (e >= nspec_e || s >= S) return;
-    double2 o[4];
-    swe_prep_row(state + (long long)s * 3 * nspec, nspec, N, a, ord_e[e], deg_e[e], o);
-    double2* c = cin + ((long long)s * nspec_e + e) * 4;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) c[f] = o[f];
-}
-
 // F_E (from the weighted analyses A, B, C, D, E in the extended layout,
 // cout = [ext][5]) and F_I (from the state st = [3][nspec]) at the
 // coefficient i = (m, n).
@@ -189,21 +175,6 @@ __global__ void k_imex_solve(const int* __restrict__ deg, const double2* rhs, do
     x[i] = xp;
     x[nspec + i] = xz;
     x[2 * nspec + i] = xd;
-}
-
-__global__ void k_f_implicit(const int* __restrict__ deg, const double2* __restrict__ st,
-                             double2* __restrict__ fi, long long nspec, swe_params p, int S) {
-    const long long i = (long long)blockIdx.x * TB + threadIdx.x;
-    const int s = blockIdx.y;
-    if (i >= nspec || s >= S) return;
-    const int n = deg[i];
-    const double L = n * (n + 1.0) / (p.a * p.a);
-    const double2* x = st + (long long)s * 3 * nspec;
-    double2* o = fi + (long long)s * 3 * nspec;
-    const double2 ph = x[i], ze = x[nspec + i], de = x[2 * nspec + i];
-    o[i] = make_double2(-p.phibar * de.x - p.nu * L * ph.x, -p.phibar * de.y - p.nu * L * ph.y);
-    o[nspec + i] = make_double2(-p.nu * L * ze.x, -p.nu * L * ze.y);
-    o[2 * nspec + i] = make_double2(L * ph.x - p.nu * L * de.x, L * ph.y - p.nu * L * de.y);
 }
 
 // Node update of the sweep for node m+1 (m = 0..M-1):
@@ -437,13 +408,6 @@ hipError_t launch_ext_to_spec(const shx_plan* pl, const double2* cout, double2* 
     return hipGetLastError();
 }
 
-hipError_t launch_swe_prep(const shx_plan* pl, double a, const double2* state, double2* cin, int S,
-                           hipStream_t st) {
-    dim3 g(nblocks(pl->nspec_e), S);
-    k_swe_prep<<<g, TB, 0, st>>>(pl->ord_e, pl->deg_e, state, cin, pl->N, pl->nspec, pl->nspec_e, a, S);
-    return hipGetLastError();
-}
-
 hipError_t launch_swe_combine(const shx_plan* pl, const swe_params& p, const double2* cout,
                               const double2* state, double2* fi, double2* fe, int S, hipStream_t st) {
     dim3 g(nblocks(pl->nspec), S);
@@ -455,13 +419,6 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
                              double2* out, int S, hipStream_t st) {
     dim3 g(nblocks(pl->nspec), S);
     k_imex_solve<<<g, TB, 0, st>>>(pl->deg, rhs, out, pl->nspec, p, h, S);
-    return hipGetLastError();
-}
-
-hipError_t launch_f_implicit(const shx_plan* pl, const swe_params& p, const double2* state, double2* fi,
-                             int S, hipStream_t st) {
-    dim3 g(nblocks(pl->nspec), S);
-    k_f_implicit<<<g, TB, 0, st>>>(pl->deg, state, fi, pl->nspec, p, S);
     return hipGetLastError();
 }
 
