@@ -11,8 +11,8 @@
 // The complex FFT is a Stockham transform in LDS with radix-8 stages first,
 // then one stage of radix 6, 4, 3 or 2 as the remaining length requires (384 =
 // 8 8 6, 1536 = 8 8 8 3).  Each stage loads its butterflies into registers
-// and writes them to a second LDS buffer (one barrier per stage), or, where
-// LDS has no room for two buffers, back in place after a barrier.
+// and writes them to a second LDS buffer (one barrier per stage) while the
+// workgroup's LDS stays under PP_LDS_MAX, or back in place after a barrier.
 // Twiddles e^{-2 pi i t / L},
 // t < L2, come from a table computed on the host in quad precision and copied
 // to LDS; e^{-2 pi i t / L2} is entry 2t, and the upper half of the circle is
