@@ -216,8 +216,8 @@ int mlsdc_step(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts*
  * spectral arrays <x, y> = sum over the stored coefficients of
  * Re x Re y + Im x Im y; grids sum_ij x_ij y_ij.  So a cotangent returned for
  * a spectral input is the gradient with respect to its real and imaginary
- * parts.  Transforms with nlon = 2048 or 3072 are not supported here
- * (SHX_EUNSUPPORTED). */
+ * parts.  Transforms with nlon = 2048 or 3072 and plans of a reduced
+ * working precision are not supported here (SHX_EUNSUPPORTED). */
 
 /* spec_cot = S^T grid_cot for the synthesis S of sh_inverse:
  *   spec_cot^m_n = c_m sum_j P^m_n(mu_j) sum_i grid_cot_ij e^{-i m lambda_i}, c_0 = 1, c_m = 2.

@@ -34,22 +34,6 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 inline unsigned nblocks(long long n) { return (unsigned)((n + TB - 1) / TB); }
 
-// Transpose of the combine step (F_E from the weighted analyses), then the
-// halving of m >= 1 that turns the analysis adjoint into a synthesis:
-// lam5[s][e][0..4] = adjoints of (A, B, C, D, E)^ at ext entry e.
-__global__ void k_combine_adj(const int* __restrict__ ord_e, const int* __restrict__ deg_e,
-                              const double2* __restrict__ lfe, double2* __restrict__ lam5, int N,
-                              long long nspec, long long nspec_e, double a, int S) {
-    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
-    const int s = blockIdx.y;
-    if (e >= nspec_e || s >= S) return;
-    double2 o[5];
-    swe_combine_adj_row(lfe + (long long)s * 3 * nspec, nspec, N, a, ord_e[e], deg_e[e], o);
-    double2* out = lam5 + ((long long)s * nspec_e + e) * 5;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) out[f] = o[f];
-}
-
 // Transpose of the wind coefficients and of F_I, accumulated into lam_state:
 // lam4[s][e] holds the adjoints of the synthesised (zeta, Phi', U, V) coefficients.
 __global__ void k_prep_adj(const int* __restrict__ ord, const int* __restrict__ deg,
@@ -373,13 +357,6 @@ bool adjoint_length_supported(int L) {
         return true;
         default: return false;
     }
-}
-
-hipError_t launch_combine_adj(const shx_plan* pl, double a, const double2* lfe, double2* lam5, int S,
-                              hipStream_t st) {
-    dim3 g(nblocks(pl->nspec_e), S);
-    k_combine_adj<<<g, TB, 0, st>>>(pl->ord_e, pl->deg_e, lfe, lam5, pl->N, pl->nspec, pl->nspec_e, a, S);
-    return hipGetLastError();
 }
 
 hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double2* lam4, const double2* lfi,

@@ -381,13 +381,12 @@ namespace {
 // ------------------------------------------------------------------ adjoint
 // Workspace of the tendency adjoint for S states.
 struct TendAdjWS {
-    double2 *FIs, *lam5, *FIl, *Ga, *lam4;
+    double2 *FIs, *FIl, *Ga, *lam4;
 };
 TendAdjWS carve_tadj(Carve& c, const shx_plan* pl, int S) {
     TendAdjWS t;
     const size_t fj = (size_t)S * pl->J * (pl->N + 1);
     t.FIs = c.take<double2>(fj * 4);
-    t.lam5 = c.take<double2>((size_t)S * pl->nspec_e * 5);
     t.FIl = c.take<double2>(fj * 5);
     t.Ga = c.take<double2>(fj * 4);
     t.lam4 = c.take<double2>((size_t)S * pl->nspec_e * 4);
@@ -399,12 +398,7 @@ int tendency_adj_impl(const shx_plan* pl, const swe_params& p, int S, const doub
                       const double2* lfe, double2* lstate, const TendAdjWS& t, hipStream_t st) {
     if (lfe) {
         HIPCHK(launch_leg_syn_swe(pl, p.a, state, t.FIs, S, st));
-        if (pl->prec == SHX_FP64) {
-            HIPCHK(launch_leg_syn_swe_adj(pl, p.a, lfe, t.FIl, S, st));
-        } else {
-            HIPCHK(launch_combine_adj(pl, p.a, lfe, t.lam5, S, st));
-            HIPCHK(launch_leg_syn(pl, t.lam5, t.FIl, 5, S, pl->nmax, st));
-        }
+        HIPCHK(launch_leg_syn_swe_adj(pl, p.a, lfe, t.FIl, S, st));
         HIPCHK(launch_swe_grid_adj(pl, t.FIs, t.FIl, t.Ga, S, p.omega, st));
         HIPCHK(launch_leg_an(pl, t.Ga, t.lam4, 4, S, pl->nmax, st));
     }
@@ -730,7 +724,7 @@ int swe_tendency_adj(const shx_plan* pl, const swe_params* prm, int nst, const d
         !aligned16(lfe) || !aligned16(lstate) || !aligned16(ws))
         return SHX_EINVAL;
     if (!alias_free(pl)) return SHX_ESHAPE;
-    if (lfe && !adjoint_length_supported(pl->I)) return SHX_EUNSUPPORTED;
+    if (pl->prec != SHX_FP64 || (lfe && !adjoint_length_supported(pl->I))) return SHX_EUNSUPPORTED;
     if (!ws || wsb < swe_adj_workspace_bytes(pl, nst)) return SHX_EWORKSPACE;
     Carve c{static_cast<char*>(ws)};
     TendAdjWS t = carve_tadj(c, pl, nst);
@@ -752,6 +746,7 @@ int imex_solve_adj(const shx_plan* pl, const swe_params* prm, int nst, double h,
 int sh_inverse_adj(const shx_plan* pl, int F, const double* grid_cot, double* spec_cot, void* ws, size_t wsb,
                    shx_stream_t stream) {
     if (!pl || F < 1 || !grid_cot || !spec_cot || !aligned16(grid_cot) || !aligned16(spec_cot)) return SHX_EINVAL;
+    if (pl->prec != SHX_FP64) return SHX_EUNSUPPORTED;
     if (!ws || wsb < shx_workspace_bytes(pl, F)) return SHX_EWORKSPACE;
     Carve c{static_cast<char*>(ws)};
     double2* cout = c.take<double2>((size_t)pl->nspec_e * F);
@@ -766,6 +761,7 @@ int sh_inverse_adj(const shx_plan* pl, int F, const double* grid_cot, double* sp
 int sh_forward_adj(const shx_plan* pl, int F, const double* spec_cot, double* grid_cot, void* ws, size_t wsb,
                    shx_stream_t stream) {
     if (!pl || F < 1 || !grid_cot || !spec_cot || !aligned16(grid_cot) || !aligned16(spec_cot)) return SHX_EINVAL;
+    if (pl->prec != SHX_FP64) return SHX_EUNSUPPORTED;
     if (!ws || wsb < shx_workspace_bytes(pl, F)) return SHX_EWORKSPACE;
     Carve c{static_cast<char*>(ws)};
     double2* cin = c.take<double2>((size_t)pl->nspec_e * F);
@@ -793,7 +789,8 @@ int mlsdc_step_adj(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o
     if (cl && (cl->kind != fl->kind || cl->plan->N >= fl->plan->N || cl->nnodes > fl->nnodes))
         return SHX_EINVAL;
     if (!alias_free(fl->plan) || (cl && !alias_free(cl->plan))) return SHX_ESHAPE;
-    if (!adjoint_length_supported(fl->plan->I) || (cl && !adjoint_length_supported(cl->plan->I)))
+    if (!adjoint_length_supported(fl->plan->I) || (cl && !adjoint_length_supported(cl->plan->I)) ||
+        fl->plan->prec != SHX_FP64 || (cl && cl->plan->prec != SHX_FP64))
         return SHX_EUNSUPPORTED;
     if (!ws || wsb < mlsdc_adj_workspace_bytes(fl, cl, o)) return SHX_EWORKSPACE;
     Carve cv{static_cast<char*>(ws)};

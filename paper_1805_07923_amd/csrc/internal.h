@@ -193,8 +193,7 @@ hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state
                               hipStream_t st);
 // Synthesis of the five cotangent fields of the tendency adjoint straight
 // from the F_E cotangents [S][3][nspec]: swe_combine_adj_row feeds the
-// staging (FP64 plans; other working precisions run the combine transpose
-// and the synthesis as two launches).
+// staging (FP64 plans).
 hipError_t launch_leg_syn_swe_adj(const shx_plan* pl, double a, const double2* lfe, double2* out, int S,
                                   hipStream_t st);
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
@@ -267,7 +266,6 @@ hipError_t launch_status(const shx_plan* pl, const double* partial, int nblk, in
 int residual_blocks(const shx_plan* pl);
 // adjoint.hip
 bool adjoint_length_supported(int L);
-hipError_t launch_combine_adj(const shx_plan* pl, double a, const double2* lfe, double2* lam5, int S, hipStream_t st);
 hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double2* lam4, const double2* lfi,
                            double2* lstate, int S, int has_fe, hipStream_t st);
 hipError_t launch_swe_grid_adj(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S,

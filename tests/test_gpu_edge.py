@@ -9,7 +9,7 @@ tolerance as the other parity tests (1e-12 normwise per field):
     only: the time transfers are identities);
   * zero iterations (the step returns the spread initial value);
   * empty inputs (no fields, no states) rejected with SHX_EINVAL before any
-    launch."""
+    launch, and the adjoints' refusal of reduced-precision plans."""
 import ctypes
 
 import numpy as np
@@ -144,4 +144,17 @@ def test_empty_inputs_rejected(pk):
     par = pk.swe_params()
     assert L.swe_tendency(plan.h, ctypes.byref(par), 0, p, p, p, ws.data_ptr(), nb, None) == -1
     assert L.imex_solve(plan.h, ctypes.byref(par), 0, ctypes.c_double(1.0), p, p, None) == -1
+    torch.cuda.synchronize()
+
+
+def test_adjoint_rejects_reduced_precision(pk):
+    """The adjoints are FP64 only: a plan of reduced working precision gives
+    SHX_EUNSUPPORTED (and no launch)."""
+    print("CASE adjoint reduced precision", flush=True)
+    plan = pk.Plan(31, 48, 96, pk.SHX_FP32)
+    st = seeded(31, 90)[None].to("cuda").contiguous()
+    with pytest.raises(pk.ShxError, match="unsupported"):
+        pk.tendency_adj(plan, pk.swe_params(), st, lam_fe=torch.ones_like(st))
+    with pytest.raises(pk.ShxError, match="unsupported"):
+        plan.inverse_adj(torch.zeros(1, 48, 96, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
