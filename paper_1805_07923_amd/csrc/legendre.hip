@@ -21,6 +21,7 @@
 namespace {
 
 constexpr int UNR = 8;   // table loads in flight per lane
+constexpr int AN_JC = 256;   // latitudes staged per chunk in the analysis
 
 // Double-double arithmetic (an unevaluated sum hi + lo of two FP64 numbers,
 // about 106 significant bits) from FP64 operations: error-free sum (Knuth)
@@ -251,9 +252,10 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
 // Analysis: cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
 // gx (N+1) 2 blocks (gx = ceil(K/64), numbered by leg_tile), 256 threads: lane = degree row k, the four
 // wavefronts split the latitude sum into quarters.  The combined Fourier
-// data g_jp = G_north +/- G_south of this (m, p) is staged in LDS once per
-// state (dynamic LDS: Jh * NF double2) and read by broadcast; the partial
-// sums of waves 1..3 are added by wave 0 through LDS.
+// data g_jp = G_north +/- G_south of this (m, p) is staged in LDS per state
+// and chunk of AN_JC latitudes (dynamic LDS: min(Jh, AN_JC) * NF double2) and
+// read by broadcast; the partial sums of waves 1..3 are added by wave 0
+// through LDS.
 template <int NF>
 __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                                                 const long long* __restrict__ off,
@@ -272,47 +274,54 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
     const bool active = k < K;
     const int Ktab = kcount(nmax_tab, m, p);
     const int Jh = J / 2;
-    const int jq = (Jh + 3) / 4;
-    const int j0 = wv * jq, j1 = min(Jh, j0 + jq);
     const double* P = pan + off[2 * m + p] + (active ? k : 0);
     const double sg = p ? -1.0 : 1.0;
     const long long rowstride = (long long)(N + 1) * F;
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
-        __syncthreads();                                // previous state's readers are done
-        for (int i = threadIdx.x; i < Jh * NF; i += 256) {
-            const int jp = i / NF, f = i - jp * NF;
-            const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
-            gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
-        }
-        __syncthreads();
         double ar[NF], ai[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        int jp = j0;
-        for (; jp + UNR <= j1; jp += UNR) {
-            double pv[UNR];
+        // latitudes in chunks of at most AN_JC (one chunk up to T255): the
+        // LDS footprint stays under AN_JC * NF double2, so that several
+        // blocks share a CU at T511 and T1023 too
+        for (int c0 = 0; c0 < Jh; c0 += AN_JC) {
+            const int cj = min(AN_JC, Jh - c0);
+            __syncthreads();                            // previous chunk's / state's readers are done
+            for (int i = threadIdx.x; i < cj * NF; i += 256) {
+                const int jl = i / NF, f = i - jl * NF, jp = c0 + jl;
+                const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+                gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+            }
+            __syncthreads();
+            const int jq = (cj + 3) / 4;
+            const int j0 = min(cj, wv * jq), j1 = min(cj, j0 + jq);   // this wave's quarter of the chunk
+            const double* Pc = P + (long long)c0 * Ktab;
+            int jp = j0;
+            for (; jp + UNR <= j1; jp += UNR) {
+                double pv[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
+                for (int u = 0; u < UNR; ++u) pv[u] = Pc[(long long)(jp + u) * Ktab];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const double2* gg = gsh + (jp + u) * NF;
+                for (int u = 0; u < UNR; ++u) {
+                    const double2* gg = gsh + (jp + u) * NF;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const double2 x = gg[f];
+                        ar[f] = fma(pv[u], x.x, ar[f]);
+                        ai[f] = fma(pv[u], x.y, ai[f]);
+                    }
+                }
+            }
+            for (; jp < j1; ++jp) {
+                const double pv = Pc[(long long)jp * Ktab];
+                const double2* gg = gsh + jp * NF;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     const double2 x = gg[f];
-                    ar[f] = fma(pv[u], x.x, ar[f]);
-                    ai[f] = fma(pv[u], x.y, ai[f]);
+                    ar[f] = fma(pv, x.x, ar[f]);
+                    ai[f] = fma(pv, x.y, ai[f]);
                 }
-            }
-        }
-        for (; jp < j1; ++jp) {
-            const double pv = P[(long long)jp * Ktab];
-            const double2* gg = gsh + jp * NF;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const double2 x = gg[f];
-                ar[f] = fma(pv, x.x, ar[f]);
-                ai[f] = fma(pv, x.y, ai[f]);
             }
         }
         if (wv > 0) {
@@ -354,7 +363,7 @@ template <int NF>
 void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
               hipStream_t st) {
     const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
-    const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
+    const size_t lds = (size_t)(pl->Jh < AN_JC ? pl->Jh : AN_JC) * NF * sizeof(double2);
     k_leg_an<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
                                                       pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
                                                       pl->nspec_e * F, gx);
