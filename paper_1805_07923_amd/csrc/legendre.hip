@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn
 // and chunk of AN_JC latitudes (dynamic LDS: min(Jh, AN_JC) * NF double2) and
 // read by broadcast; the partial sums of waves 1..3 are added by wave 0
 // through LDS.
-template <int NF>
+template <int NF, bool CHUNK>
 __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                                                 const long long* __restrict__ off,
                                                 const double2* __restrict__ G,
@@ -273,35 +273,34 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
     if (tile.x * 64 >= K) return;                       // whole block idle (uniform)
     const bool active = k < K;
     const int Ktab = kcount(nmax_tab, m, p);
-    const int Jh = J / 2;
-    const double* P = pan + off[2 * m + p] + (active ? k : 0);
-    const double sg = p ? -1.0 : 1.0;
-    const long long rowstride = (long long)(N + 1) * F;
-    for (int s = 0; s < S; ++s) {
-        const double2* g = G + s * G_stride + (long long)m * F + f0;
-        double ar[NF], ai[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        // latitudes in chunks of at most AN_JC (one chunk up to T255): the
-        // LDS footprint stays under AN_JC * NF double2, so that several
-        // blocks share a CU at T511 and T1023 too
-        for (int c0 = 0; c0 < Jh; c0 += AN_JC) {
-            const int cj = min(AN_JC, Jh - c0);
-            __syncthreads();                            // previous chunk's / state's readers are done
-            for (int i = threadIdx.x; i < cj * NF; i += 256) {
-                const int jl = i / NF, f = i - jl * NF, jp = c0 + jl;
+    // Two bodies: up to T255 (Jh <= AN_JC) all latitudes are staged at once;
+    // beyond, in chunks of AN_JC latitudes.  The single-chunk case keeps its
+    // own loop structure (running it through the chunk loop measured slower
+    // for 7 and 8 fields).
+    if constexpr (!CHUNK) {
+        const int Jh = J / 2;
+        const int jq = (Jh + 3) / 4;
+        const int j0 = wv * jq, j1 = min(Jh, j0 + jq);
+        const double* P = pan + off[2 * m + p] + (active ? k : 0);
+        const double sg = p ? -1.0 : 1.0;
+        const long long rowstride = (long long)(N + 1) * F;
+        for (int s = 0; s < S; ++s) {
+            const double2* g = G + s * G_stride + (long long)m * F + f0;
+            __syncthreads();                                // previous state's readers are done
+            for (int i = threadIdx.x; i < Jh * NF; i += 256) {
+                const int jp = i / NF, f = i - jp * NF;
                 const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
                 gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
             }
             __syncthreads();
-            const int jq = (cj + 3) / 4;
-            const int j0 = min(cj, wv * jq), j1 = min(cj, j0 + jq);   // this wave's quarter of the chunk
-            const double* Pc = P + (long long)c0 * Ktab;
+            double ar[NF], ai[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
             int jp = j0;
             for (; jp + UNR <= j1; jp += UNR) {
                 double pv[UNR];
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) pv[u] = Pc[(long long)(jp + u) * Ktab];
+                for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
                     const double2* gg = gsh + (jp + u) * NF;
@@ -314,7 +313,7 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                 }
             }
             for (; jp < j1; ++jp) {
-                const double pv = Pc[(long long)jp * Ktab];
+                const double pv = P[(long long)jp * Ktab];
                 const double2* gg = gsh + jp * NF;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -323,27 +322,102 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                     ai[f] = fma(pv, x.y, ai[f]);
                 }
             }
-        }
-        if (wv > 0) {
+            if (wv > 0) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                red[wv - 1][2 * f][lane] = ar[f];
-                red[wv - 1][2 * f + 1][lane] = ai[f];
+                for (int f = 0; f < NF; ++f) {
+                    red[wv - 1][2 * f][lane] = ar[f];
+                    red[wv - 1][2 * f + 1][lane] = ai[f];
+                }
+            }
+            __syncthreads();
+            if (wv == 0 && active) {
+                double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    // fixed summation order: wave 0, 1, 2, 3
+                    double xr = ar[f], xi = ai[f];
+#pragma unroll
+                    for (int w = 0; w < 3; ++w) {
+                        xr += red[w][2 * f][lane];
+                        xi += red[w][2 * f + 1][lane];
+                    }
+                    o[f] = make_double2(xr, xi);
+                }
             }
         }
-        __syncthreads();
-        if (wv == 0 && active) {
-            double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+    } else {
+        const int Jh = J / 2;
+        const double* P = pan + off[2 * m + p] + (active ? k : 0);
+        const double sg = p ? -1.0 : 1.0;
+        const long long rowstride = (long long)(N + 1) * F;
+        for (int s = 0; s < S; ++s) {
+            const double2* g = G + s * G_stride + (long long)m * F + f0;
+            double ar[NF], ai[NF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                // fixed summation order: wave 0, 1, 2, 3
-                double xr = ar[f], xi = ai[f];
-#pragma unroll
-                for (int w = 0; w < 3; ++w) {
-                    xr += red[w][2 * f][lane];
-                    xi += red[w][2 * f + 1][lane];
+            for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
+            // latitudes in chunks of at most AN_JC (one chunk up to T255): the
+            // LDS footprint stays under AN_JC * NF double2, so that several
+            // blocks share a CU at T511 and T1023 too
+            for (int c0 = 0; c0 < Jh; c0 += AN_JC) {
+                const int cj = min(AN_JC, Jh - c0);
+                __syncthreads();                            // previous chunk's / state's readers are done
+                for (int i = threadIdx.x; i < cj * NF; i += 256) {
+                    const int jl = i / NF, f = i - jl * NF, jp = c0 + jl;
+                    const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+                    gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
                 }
-                o[f] = make_double2(xr, xi);
+                __syncthreads();
+                const int jq = (cj + 3) / 4;
+                const int j0 = min(cj, wv * jq), j1 = min(cj, j0 + jq);   // this wave's quarter of the chunk
+                const double* Pc = P + (long long)c0 * Ktab;
+                int jp = j0;
+                for (; jp + UNR <= j1; jp += UNR) {
+                    double pv[UNR];
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) pv[u] = Pc[(long long)(jp + u) * Ktab];
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        const double2* gg = gsh + (jp + u) * NF;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) {
+                            const double2 x = gg[f];
+                            ar[f] = fma(pv[u], x.x, ar[f]);
+                            ai[f] = fma(pv[u], x.y, ai[f]);
+                        }
+                    }
+                }
+                for (; jp < j1; ++jp) {
+                    const double pv = Pc[(long long)jp * Ktab];
+                    const double2* gg = gsh + jp * NF;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const double2 x = gg[f];
+                        ar[f] = fma(pv, x.x, ar[f]);
+                        ai[f] = fma(pv, x.y, ai[f]);
+                    }
+                }
+            }
+            if (wv > 0) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    red[wv - 1][2 * f][lane] = ar[f];
+                    red[wv - 1][2 * f + 1][lane] = ai[f];
+                }
+            }
+            __syncthreads();
+            if (wv == 0 && active) {
+                double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    // fixed summation order: wave 0, 1, 2, 3
+                    double xr = ar[f], xi = ai[f];
+#pragma unroll
+                    for (int w = 0; w < 3; ++w) {
+                        xr += red[w][2 * f][lane];
+                        xi += red[w][2 * f + 1][lane];
+                    }
+                    o[f] = make_double2(xr, xi);
+                }
             }
         }
     }
@@ -364,9 +438,16 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
               hipStream_t st) {
     const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
     const size_t lds = (size_t)(pl->Jh < AN_JC ? pl->Jh : AN_JC) * NF * sizeof(double2);
-    k_leg_an<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
-                                                      pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
-                                                      pl->nspec_e * F, gx);
+    if (pl->Jh > AN_JC)
+        k_leg_an<NF, true><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
+                                                                nmax_use, pl->J, F, f0, S,
+                                                                (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
+                                                                gx);
+    else
+        k_leg_an<NF, false><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
+                                                                 nmax_use, pl->J, F, f0, S,
+                                                                 (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
+                                                                 gx);
 }
 
 }  // namespace

@@ -28,6 +28,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int U4 = 8;     // FP32 MFMA: chunks of 4 reduction elements per batch of loads
 constexpr int U16 = 2;    // bf16 MFMA: chunks of 16 reduction elements per batch of loads
+constexpr int AN_JC = 256;   // latitudes staged per chunk in the analysis (a multiple of 16)
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short f2bf(float x) {
@@ -120,111 +121,119 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
     const long long rowstride = (long long)(N + 1) * F;
     const int k0 = kb + 16 * wv;                        // this wave's row tile
     const bool wave_on = k0 < K;
+    const int row = k0 + (lane & 15);
+    const bool row_ok = row < K;
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
-        __syncthreads();
-        // stage g: FP32 as [jp][CW]; bf16 planes as [q][c][Jhp].  One thread
-        // per complex value (both columns of a field), in rounds of 4 per
-        // thread whose loads (indices clamped to the range) are all issued
-        // before any is used.
-        constexpr int CH = CW / 2;
-        const int tot = Jhp * CH;
-        for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * 256) {
-            double2 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = min(i0 + u * 256, tot - 1);
-                const int jp = i / CH, f = i - jp * CH;
-                const bool in = jp < Jh && f < NF;
-                const int jc = in ? jp : 0, fc = in ? f : 0;
-                const double2 a = g[jc * rowstride + fc], b = g[(J - 1 - jc) * rowstride + fc];
-                v[u] = in ? make_double2(a.x + sg * b.x, a.y + sg * b.y) : make_double2(0.0, 0.0);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u * 256;
-                if (i >= tot) break;
-                const int jp = i / CH, f = i - jp * CH;
-                if constexpr (MODE == 1) {
-                    float* d = reinterpret_cast<float*>(smem) + jp * CW + 2 * f;
-                    d[0] = (float)v[u].x;
-                    d[1] = (float)v[u].y;
-                } else {
-                    unsigned short hr[NP], hi[NP];
-                    split_bf16<NP>(v[u].x, hr);
-                    split_bf16<NP>(v[u].y, hi);
-                    unsigned short* d = reinterpret_cast<unsigned short*>(smem);
-#pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        d[q * Jhp * CW + (2 * f) * Jhp + jp] = hr[q];
-                        d[q * Jhp * CW + (2 * f + 1) * Jhp + jp] = hi[q];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (!wave_on) continue;
         floatx4 acc0[NCT], acc1[NCT];
 #pragma unroll
         for (int t = 0; t < NCT; ++t) {
             acc0[t] = floatx4{0.f, 0.f, 0.f, 0.f};
             acc1[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-        const int row = k0 + (lane & 15);
-        const bool row_ok = row < K;
-        if constexpr (MODE == 1) {
-            const float* P = static_cast<const float*>(tab) + off[2 * m + p] + (row_ok ? row : 0);
-            const float* gs = reinterpret_cast<const float*>(smem);
-            // U4 chunks of 4 latitudes: their table loads are issued before the MFMAs
-            for (int jc = 0; jc < Jh; jc += 4 * U4) {
-                float a[U4];
+        // latitudes in chunks of at most AN_JC (a multiple of 16; one chunk
+        // up to T255), so that the staged operand stays small at T511 / T1023
+        for (int c0 = 0; c0 < Jh; c0 += AN_JC) {
+            const int cj = min(AN_JC, Jh - c0);
+            const int cjp = (cj + 15) / 16 * 16;        // bf16 reduction rows of this chunk
+            __syncthreads();                            // previous chunk's / state's readers are done
+            // stage g: FP32 as [jp][CW]; bf16 planes as [q][c][cjp].  One thread
+            // per complex value (both columns of a field), in rounds of 4 per
+            // thread whose loads (indices clamped to the range) are all issued
+            // before any is used.
+            constexpr int CH = CW / 2;
+            const int tot = cjp * CH;
+            for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * 256) {
+                double2 v[4];
 #pragma unroll
-                for (int u = 0; u < U4; ++u) {
-                    const int jp = jc + 4 * u + (lane >> 4);
-                    a[u] = (row_ok && jp < Jh) ? P[(long long)jp * Ktab] : 0.f;
+                for (int u = 0; u < 4; ++u) {
+                    const int i = min(i0 + u * 256, tot - 1);
+                    const int jl = i / CH, f = i - jl * CH;
+                    const bool in = jl < cj && f < NF;
+                    const int jc = in ? c0 + jl : 0, fc = in ? f : 0;
+                    const double2 a = g[jc * rowstride + fc], b = g[(J - 1 - jc) * rowstride + fc];
+                    v[u] = in ? make_double2(a.x + sg * b.x, a.y + sg * b.y) : make_double2(0.0, 0.0);
                 }
 #pragma unroll
-                for (int u = 0; u < U4; ++u) {
-                    const int jp = jc + 4 * u + (lane >> 4);
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * 256;
+                    if (i >= tot) break;
+                    const int jl = i / CH, f = i - jl * CH;
+                    if constexpr (MODE == 1) {
+                        float* d = reinterpret_cast<float*>(smem) + jl * CW + 2 * f;
+                        d[0] = (float)v[u].x;
+                        d[1] = (float)v[u].y;
+                    } else {
+                        unsigned short hr[NP], hi[NP];
+                        split_bf16<NP>(v[u].x, hr);
+                        split_bf16<NP>(v[u].y, hi);
+                        unsigned short* d = reinterpret_cast<unsigned short*>(smem);
 #pragma unroll
-                    for (int t = 0; t < NCT; ++t) {
-                        const float b = (jp < Jh) ? gs[jp * CW + 16 * t + (lane & 15)] : 0.f;
-                        acc0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc0[t], 0, 0, 0);
+                        for (int q = 0; q < NP; ++q) {
+                            d[q * cjp * CW + (2 * f) * cjp + jl] = hr[q];
+                            d[q * cjp * CW + (2 * f + 1) * cjp + jl] = hi[q];
+                        }
                     }
                 }
             }
-        } else {
-            const unsigned short* P = static_cast<const unsigned short*>(tab);
-            const long long base = off[2 * m + p] + (long long)(row_ok ? row : 0) * Jhp;
-            const unsigned short* gs = reinterpret_cast<const unsigned short*>(smem);
-            for (int jc = 0; jc < Jhp; jc += 16 * U16) {
-                shortx4 a[U16][NP];
+            __syncthreads();
+            if (!wave_on) continue;                     // no rows: staging and barriers only
+            if constexpr (MODE == 1) {
+                const float* P = static_cast<const float*>(tab) + off[2 * m + p] + (long long)c0 * Ktab +
+                                 (row_ok ? row : 0);
+                const float* gs = reinterpret_cast<const float*>(smem);
+                // U4 chunks of 4 latitudes: their table loads are issued before the MFMAs
+                for (int jc = 0; jc < cj; jc += 4 * U4) {
+                    float a[U4];
 #pragma unroll
-                for (int u = 0; u < U16; ++u) {
-                    const int q4 = jc + 16 * u + 4 * (lane >> 4);
+                    for (int u = 0; u < U4; ++u) {
+                        const int jp = jc + 4 * u + (lane >> 4);
+                        a[u] = (row_ok && jp < cj) ? P[(long long)jp * Ktab] : 0.f;
+                    }
 #pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        const shortx4 v = (q4 < Jhp) ? *reinterpret_cast<const shortx4*>(P + q * plane + base + q4)
-                                                     : shortx4{0, 0, 0, 0};
-                        a[u][q] = row_ok ? v : shortx4{0, 0, 0, 0};
+                    for (int u = 0; u < U4; ++u) {
+                        const int jp = jc + 4 * u + (lane >> 4);
+#pragma unroll
+                        for (int t = 0; t < NCT; ++t) {
+                            const float b = (jp < cj) ? gs[jp * CW + 16 * t + (lane & 15)] : 0.f;
+                            acc0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc0[t], 0, 0, 0);
+                        }
                     }
                 }
+            } else {
+                const unsigned short* P = static_cast<const unsigned short*>(tab);
+                const long long base = off[2 * m + p] + (long long)(row_ok ? row : 0) * Jhp + c0;
+                const unsigned short* gs = reinterpret_cast<const unsigned short*>(smem);
+                for (int jc = 0; jc < cjp; jc += 16 * U16) {
+                    shortx4 a[U16][NP];
 #pragma unroll
-                for (int u = 0; u < U16; ++u) {
-                    const int q4 = jc + 16 * u + 4 * (lane >> 4);
-                    if (jc + 16 * u >= Jhp) break;
+                    for (int u = 0; u < U16; ++u) {
+                        const int q4 = jc + 16 * u + 4 * (lane >> 4);
 #pragma unroll
-                    for (int t = 0; t < NCT; ++t) {
-                        shortx4 b[NP];
-                        const int c = 16 * t + (lane & 15);
+                        for (int q = 0; q < NP; ++q) {
+                            const shortx4 v = (q4 < cjp) ? *reinterpret_cast<const shortx4*>(P + q * plane + base + q4)
+                                                         : shortx4{0, 0, 0, 0};
+                            a[u][q] = row_ok ? v : shortx4{0, 0, 0, 0};
+                        }
+                    }
 #pragma unroll
-                        for (int q = 0; q < NP; ++q)
-                            b[q] = *reinterpret_cast<const shortx4*>(gs + q * Jhp * CW + c * Jhp + q4);
-                        mfma_split<MODE>(a[u], b, acc0[t], acc1[t]);
+                    for (int u = 0; u < U16; ++u) {
+                        const int q4 = jc + 16 * u + 4 * (lane >> 4);
+                        if (jc + 16 * u >= cjp) break;
+#pragma unroll
+                        for (int t = 0; t < NCT; ++t) {
+                            shortx4 b[NP];
+                            const int c = 16 * t + (lane & 15);
+#pragma unroll
+                            for (int q = 0; q < NP; ++q)
+                                b[q] = *reinterpret_cast<const shortx4*>(gs + q * cjp * CW + c * cjp + q4);
+                            mfma_split<MODE>(a[u], b, acc0[t], acc1[t]);
+                        }
                     }
                 }
             }
         }
+        if (!wave_on) continue;
         // D[4 (l/16) + r][l % 16]: row k0 + 4 (l/16) + r, column 16 t + l % 16
 #pragma unroll
         for (int t = 0; t < NCT; ++t) {
@@ -403,7 +412,8 @@ void an_mx(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, i
     const unsigned grid = gx * (pl->N + 1) * 2;
     const int Jhp = (pl->Jh + 15) / 16 * 16;
     const int NP = MODE == 1 ? 1 : MODE;
-    const size_t lds = (MODE == 1) ? (size_t)Jhp * 16 * NCT * 4 : (size_t)NP * Jhp * 16 * NCT * 2;
+    const int JC = Jhp < AN_JC ? Jhp : AN_JC;
+    const size_t lds = (MODE == 1) ? (size_t)JC * 16 * NCT * 4 : (size_t)NP * JC * 16 * NCT * 2;
     const void* tab = (MODE == 1) ? (const void*)pl->pan32 : (const void*)pl->an16;
     k_leg_an_mx<MODE, NCT><<<grid, 256, lds, st>>>(tab, pl->an16_plane, MODE == 1 ? pl->off : pl->off_an16, G, cout,
                                                     pl->N, pl->nmax, nmax_use, pl->J, F, f0, NF, S,
