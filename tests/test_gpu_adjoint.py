@@ -96,6 +96,29 @@ def test_tendency_adjoint_vs_autograd(pk, N, J, I, S):
             assert relerr(got[s, f], x.grad[f]) < 1e-12, (s, f, relerr(got[s, f], x.grad[f]))
 
 
+@pytest.mark.parametrize("which", ["fi", "fe"])
+def test_tendency_adjoint_one_cotangent(pk, which):
+    """The entry point with one of the two cotangents NULL (T31, 2 states)."""
+    print("CASE tendency adjoint one cotangent", which, flush=True)
+    N, J, I, S = 31, 48, 96, 2
+    g = ogrid(N, J, I)
+    p = OW.SWEParams()
+    gen = torch.Generator().manual_seed(11)
+    states = torch.stack([seeded(N, 95 + s) for s in range(S)])
+    lam = crandn(states.shape, gen)
+    plan = pk.Plan(N, J, I)
+    if which == "fi":
+        got = pk.tendency_adj(plan, pk.swe_params(), states.cuda(), lam_fi=lam.cuda())
+    else:
+        got = pk.tendency_adj(plan, pk.swe_params(), states.cuda(), lam_fe=lam.cuda())
+    for s in range(S):
+        x = states[s].clone().requires_grad_(True)
+        out = OW.f_implicit(x, N, p) if which == "fi" else OW.f_explicit(x, g, p)
+        (out.real * lam[s].real + out.imag * lam[s].imag).sum().backward()
+        for f in range(3):
+            assert relerr(got[s, f], x.grad[f]) < 1e-12, (which, s, f, relerr(got[s, f], x.grad[f]))
+
+
 def test_solve_adjoint_dot(pk):
     N = 63
     gen = torch.Generator().manual_seed(3)
