@@ -81,6 +81,43 @@ def test_pair_mixed(pk, mode, N, J, I, F):
 
 
 @pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("nmax_plus", [0, 1])
+def test_legendre_steps_mixed(pk, mode, nmax_plus):
+    """The Legendre-only entry points of a reduced-precision plan, T40 on 64 x
+    128 (ragged tiles), 9 fields (two MFMA column tiles), degrees <= N (some
+    (m, parity) blocks then have no rows) and <= N + 1, within the pair bound
+    of the FP64 oracle."""
+    print("CASE mixed legendre steps", mode, nmax_plus, flush=True)
+    N, J, I, F = 40, 64, 128, 9
+    nmax = N + nmax_plus
+    g = ogrid(N, J, I)
+    plan = pk.Plan(N, J, I, MODES[mode])
+    gen = torch.Generator().manual_seed(21)
+    ne = OH.nspec(N, N + 1)
+    spec = torch.complex(torch.randn(ne, F, generator=gen, dtype=torch.float64),
+                         torch.randn(ne, F, generator=gen, dtype=torch.float64))
+    m0 = torch.tensor([m == 0 for m in OH.orders(N, N + 1).tolist()])
+    spec[m0] = spec[m0].real.to(torch.complex128)
+    keep = (OH.degrees(N, N + 1) <= nmax)[:, None]
+    spec = torch.where(keep, spec, torch.zeros_like(spec))
+    four = torch.empty(2, J // 2, N + 1, F, dtype=torch.complex128, device="cuda")
+    pk.legendre_synthesis(plan, F, nmax, spec.to("cuda").contiguous(), four)
+    four = four.cpu()
+    got = torch.cat([four[0] + four[1], (four[0] - four[1]).flip(0)], dim=0)      # [J][N+1][F]
+    for f in range(F):
+        ref = g.legendre_synthesis(spec[:, f], N + 1)
+        assert relerr(got[:, :, f], ref) < BOUND_PAIR[mode], ("synthesis", f)
+    fin = torch.complex(torch.randn(J, N + 1, F, generator=gen, dtype=torch.float64),
+                        torch.randn(J, N + 1, F, generator=gen, dtype=torch.float64))
+    out = torch.zeros(ne, F, dtype=torch.complex128, device="cuda")
+    pk.legendre_analysis(plan, F, nmax, fin.to("cuda").contiguous(), out)
+    out = out.cpu()
+    for f in range(F):
+        ref = g.legendre_analysis(fin[:, :, f], torch.ones(J, dtype=torch.float64), N + 1)
+        assert relerr(out[:, f][keep[:, 0]], ref[keep[:, 0]]) < BOUND_PAIR[mode], ("analysis", f)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 def test_plan_tables_mixed(pk, mode):
     N, J, I = 63, 96, 192
     plan = pk.Plan(N, J, I, MODES[mode])
