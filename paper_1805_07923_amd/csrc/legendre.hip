@@ -423,6 +423,94 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
     }
 }
 
+// The analysis with 128-row degree tiles: waves (w & 1) take the two 64-row
+// halves, waves (w >> 1) the two latitude halves; a (m, parity) block stages
+// its Fourier rows once for up to 128 rows instead of twice.  Measured faster
+// than k_leg_an for 7 and 8 fields (the 15-field transform: 53.8 -> 48.0 us)
+// and slower for 5 (17.1 -> 22.3 us), so the launcher takes it for NF >= 7.
+template <int NF>
+__global__ __launch_bounds__(256) void k_leg_an128(const double* __restrict__ pan,
+                                                   const long long* __restrict__ off,
+                                                   const double2* __restrict__ G,
+                                                   double2* __restrict__ cout, int N, int nmax_tab,
+                                                   int nmax_use, int J, int F, int f0, int S,
+                                                   long long G_stride, long long cout_stride, int gx) {
+    extern __shared__ double2 gsh[];                    // [Jh][NF]
+    __shared__ double red[2][2 * NF][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kh = wv & 1, jh = wv >> 1;
+    const LegTile tile = leg_tile(gx, N + 1);
+    const int k = tile.x * 128 + kh * 64 + lane;
+    const int m = tile.m, p = tile.p;
+    const int K = kcount(nmax_use, m, p);
+    if (tile.x * 128 >= K) return;
+    const bool active = k < K;
+    const int Ktab = kcount(nmax_tab, m, p);
+    const int Jh = J / 2;
+    const int jq = (Jh + 1) / 2;
+    const int j0 = jh * jq, j1 = min(Jh, j0 + jq);
+    const double* P = pan + off[2 * m + p] + (active ? k : 0);
+    const double sg = p ? -1.0 : 1.0;
+    const long long rowstride = (long long)(N + 1) * F;
+    const bool wave_rows = tile.x * 128 + kh * 64 < K;     // uniform: this wave has rows
+    for (int s = 0; s < S; ++s) {
+        const double2* g = G + s * G_stride + (long long)m * F + f0;
+        __syncthreads();                                // previous state's readers are done
+        for (int i = threadIdx.x; i < Jh * NF; i += 256) {
+            const int jp = i / NF, f = i - jp * NF;
+            const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+            gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+        }
+        __syncthreads();
+        double ar[NF], ai[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
+        if (wave_rows) {
+            int jp = j0;
+            for (; jp + UNR <= j1; jp += UNR) {
+                double pv[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const double2* gg = gsh + (jp + u) * NF;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const double2 x = gg[f];
+                        ar[f] = fma(pv[u], x.x, ar[f]);
+                        ai[f] = fma(pv[u], x.y, ai[f]);
+                    }
+                }
+            }
+            for (; jp < j1; ++jp) {
+                const double pv = P[(long long)jp * Ktab];
+                const double2* gg = gsh + jp * NF;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const double2 x = gg[f];
+                    ar[f] = fma(pv, x.x, ar[f]);
+                    ai[f] = fma(pv, x.y, ai[f]);
+                }
+            }
+        }
+        if (jh == 1) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                red[kh][2 * f][lane] = ar[f];
+                red[kh][2 * f + 1][lane] = ai[f];
+            }
+        }
+        __syncthreads();
+        if (jh == 0 && active) {
+            // fixed summation order: latitude half 0, then half 1
+            double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                o[f] = make_double2(ar[f] + red[kh][2 * f][lane], ai[f] + red[kh][2 * f + 1][lane]);
+        }
+    }
+}
+
 template <int NF>
 void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S,
                int nmax_use, hipStream_t st) {
@@ -438,16 +526,25 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
               hipStream_t st) {
     const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
     const size_t lds = (size_t)(pl->Jh < AN_JC ? pl->Jh : AN_JC) * NF * sizeof(double2);
-    if (pl->Jh > AN_JC)
+    if (pl->Jh > AN_JC) {
         k_leg_an<NF, true><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
                                                                 nmax_use, pl->J, F, f0, S,
                                                                 (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
                                                                 gx);
-    else
+        return;
+    }
+    if constexpr (NF >= 7) {
+        const int gx2 = (kcount(nmax_use, 0, 0) + 127) / 128;
+        k_leg_an128<NF><<<gx2 * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
+                                                                 nmax_use, pl->J, F, f0, S,
+                                                                 (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
+                                                                 gx2);
+    } else {
         k_leg_an<NF, false><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
                                                                  nmax_use, pl->J, F, f0, S,
                                                                  (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
                                                                  gx);
+    }
 }
 
 }  // namespace
