@@ -36,6 +36,9 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->off_an16);
     (void)hipFree(p->off_syn16);
     (void)hipFree(p->off);
+    (void)hipFree(p->ck);
+    (void)hipFree(p->ckoff);
+    (void)hipFree(p->rc);
     (void)hipFree(p->ord);
     (void)hipFree(p->deg);
     (void)hipFree(p->ord_e);
@@ -592,6 +595,12 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
             acc += (long long)kcount(p->nmax, m, q) * p->Jh;
         }
     p->table_elems = acc;
+    std::vector<long long> ckoff(N + 1);
+    long long ck_elems = 0;
+    for (int m = 0; m <= N; ++m) {
+        ckoff[m] = ck_elems;
+        ck_elems += 4LL * seg_rounds(p->nmax - m + 1) * p->Jh;
+    }
     std::vector<int> ord(p->nspec), deg(p->nspec), orde(p->nspec_e), dege(p->nspec_e);
     for (int m = 0; m <= N; ++m) {
         for (int n = m; n <= N; ++n) {
@@ -608,7 +617,11 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
               dalloc(&p->tw, I) == hipSuccess && dalloc(&p->psyn, acc) == hipSuccess &&
               dalloc(&p->pan, acc) == hipSuccess && dalloc(&p->off, p->h_off.size()) == hipSuccess &&
               dalloc(&p->ord, p->nspec) == hipSuccess && dalloc(&p->deg, p->nspec) == hipSuccess &&
-              dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess;
+              dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess &&
+              dalloc(&p->ck, ck_elems) == hipSuccess && dalloc(&p->ckoff, N + 1) == hipSuccess &&
+              dalloc(&p->rc, p->nspec_e) == hipSuccess;
+    ok = ok && hipMemcpy(p->ckoff, ckoff.data(), (N + 1) * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(p->ck, 0, ck_elems * sizeof(double2)) == hipSuccess;
     ok = ok && hipMemcpy(p->mu, p->h_mu.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->sint, p->h_sint.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->cos2, p->h_cos2.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;

@@ -121,6 +121,16 @@ __device__ inline void swe_combine_adj_row(const double2* __restrict__ lfe, long
 // staging reads hit that XCD's L2; orders are dealt to the XCDs round robin
 // (m = xcd, xcd + 8, ...), which keeps the XCDs' shares of work even.
 // np = 1 for launches that take both parities of an order in one block.
+// Restart segmentation of the in-kernel Legendre recurrence: the K degrees
+// of an order are cut into 4 R segments of L degrees (a multiple of 8),
+// R = ceil(K / 256), so that no segment runs more than 64 plain FP64
+// recurrence steps.
+__host__ __device__ inline int seg_rounds(int K) { return (K + 255) / 256; }
+__host__ __device__ inline int seg_len(int K) {
+    const int R = seg_rounds(K);
+    return 8 * ((K + 32 * R - 1) / (32 * R));
+}
+
 struct LegTile {
     int x, p, m;
 };
@@ -156,6 +166,14 @@ struct shx_plan {
     long long* off_an16 = nullptr;    // device [(N+1)*2] offsets into a bf16 plane
     long long* off_syn16 = nullptr;
     long long* off = nullptr;       // device [(N+1)*2] table offsets (elements)
+    // Recurrence data of the FP64 kernels that generate P^m_n in registers:
+    // ck[ckoff[m] + g * Jh + jp] = (P^m_{m+g*L}, P^m_{m+g*L+1}) at mu_jp for the
+    // 4 R segments g of the order (L = seg_len, R = seg_rounds of its
+    // nmax - m + 1 degrees; zero past nmax), from the double-double recurrence;
+    // rc[ext(m, n)] = (1/eps^m_n, eps^m_{n-1}/eps^m_n) for n >= m + 2.
+    double2* ck = nullptr;
+    long long* ckoff = nullptr;     // device [N+1]
+    double2* rc = nullptr;          // device [nspec_e]
     int* ord = nullptr;             // device [nspec] zonal order of each entry
     int* deg = nullptr;             // device [nspec] degree of each entry
     int* ord_e = nullptr;           // device [nspec_e]

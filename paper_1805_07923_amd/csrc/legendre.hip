@@ -10,18 +10,21 @@
 //              north = E + O, south = E - O;
 //   analysis   xi^m_n = sum_{j < J/2} P^m_n(mu_j) (g_north +/- g_south).
 // The tables are built once per plan by a double-double recurrence (FP64
-// operations) on the device, rounded to FP64, and
-// kept in two layouts so that both kernels read them with unit stride across
-// the 64 lanes of a wavefront: psyn[m][p][k][jp] (lanes = latitudes) and
-// pan[m][p][jp][k] (lanes = degrees).  The second operand of each
-// contraction (spectral coefficients resp. Fourier coefficients of one
-// latitude) is the same for every lane and is read through the scalar cache.
+// operations) on the device, rounded to FP64, in two layouts:
+// pan[m][p][jp][k] (lanes = degrees), streamed by the FP64 analysis, and
+// psyn[m][p][k][jp], the source of the reduced-precision tables and of the
+// table export.  The FP64 synthesis reads no table: it generates P^m_n with
+// the recurrence on the fly from exact restart values and contracts on the
+// matrix cores (k_leg_syn_m).  The second operand of the analysis (the
+// Fourier coefficients of one latitude) is the same for every lane and is
+// staged in LDS.
 #include "internal.h"
 
 namespace {
 
 constexpr int UNR = 8;   // table loads in flight per lane
 constexpr int AN_JC = 256;   // latitudes staged per chunk in the analysis
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Double-double arithmetic (an unevaluated sum hi + lo of two FP64 numbers,
 // about 106 significant bits) from FP64 operations: error-free sum (Knuth)
@@ -84,10 +87,17 @@ __device__ __forceinline__ dd dd_eps(int n, int m) {
 // each value is rounded to FP64: in plain FP64 the forward recurrence
 // amplifies rounding errors roughly like n^2 near the poles (about 1e-12 of
 // the column maximum at degree 1000), which the Laplacian's n(n+1) turns
-// into visible errors of the divergence tendency at T1023.
+// into visible errors of the divergence tendency at T1023.  Besides the two
+// tables the kernel stores the restart values of the FP64 kernels that
+// generate P^m_n themselves (at the start of every seg_len segment, so that
+// their plain FP64 recurrence never runs more than 64 steps from an exact
+// value) and
+// the recurrence coefficients 1/eps^m_n and eps^m_{n-1}/eps^m_n.
 __global__ void k_plm_table(const double* __restrict__ mu, const double* __restrict__ sint,
                             const long long* __restrict__ off, double* __restrict__ psyn,
-                            double* __restrict__ pan, int N, int nmax, int Jh) {
+                            double* __restrict__ pan, double2* __restrict__ ck,
+                            const long long* __restrict__ ckoff, double2* __restrict__ rc, int N, int nmax,
+                            int Jh) {
     const int jp = blockIdx.x * blockDim.x + threadIdx.x;
     const int m = blockIdx.y;
     if (jp >= Jh) return;
@@ -102,8 +112,12 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
     double* pa1 = pan + off[2 * m + 1];
     dd p2{0.0, 0.0}, p1 = pmm;   // P_{n-2}, P_{n-1}
     dd e_prev = (m + 1 <= nmax) ? dd_eps(m + 1, m) : dd{1.0, 0.0};
+    double2* ckm = ck + ckoff[m] + jp;
+    const int L = seg_len(nmax - m + 1);
+    double2* rcm = rc + ext_idx(N, m, m);
     for (int n = m; n <= nmax; ++n) {
         dd pn;
+        double2 r = make_double2(0.0, 0.0);
         if (n == m) {
             pn = pmm;
         } else if (n == m + 1) {
@@ -111,10 +125,16 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
         } else {
             const dd en = dd_eps(n, m);
             pn = dd_div(dd_sub(dd_mul_d(p1, x), dd_mul(e_prev, p2)), en);
+            const dd ra = dd_div(dd{1.0, 0.0}, en), rb = dd_div(e_prev, en);
+            r = make_double2(ra.h + ra.l, rb.h + rb.l);
             e_prev = en;
         }
+        if (jp == 0) rcm[n - m] = r;
         if (n > m) { p2 = p1; p1 = pn; }
         const double v = pn.h + pn.l;
+        const int g = (n - m) / L, gr = (n - m) - g * L;
+        if (gr == 0) ckm[(long long)g * Jh] = make_double2(v, 0.0);
+        if (gr == 1) ckm[(long long)g * Jh].y = v;
         const int p = (n - m) & 1, k = (n - m) >> 1;
         if (p == 0) {
             ps0[(long long)k * Jh + jp] = v;
@@ -127,123 +147,127 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
 }
 #pragma clang fp contract(fast)
 
-// Synthesis: out[s][p][jp][m][f0+f] = sum_k P[m][p][k][jp] cin[s][ext(m, m+2k+p)][f0+f].
-// gx (N+1) 2 blocks (gx = ceil(Jh/64), numbered by leg_tile), 256 threads: lane = latitude jp, the four
-// wavefronts split the degree sum into quarters.  The coefficients of this
-// (m, p) are the same for every lane: they are staged in LDS (dynamic LDS:
-// K * NF double2) and read by broadcast.  Wave 0 adds the partial sums of
-// waves 1..3 (LDS) in a fixed order.  STAGE = 1: cin holds states
-// [S][3][nspec] and the staged rows are the tendency's grid fields
-// (swe_prep_row; NF = F = 4).  STAGE = 2: cin holds F_E cotangents
-// [S][3][nspec] and the staged rows are the cotangents of the five weighted
-// analyses (swe_combine_adj_row; NF = F = 5).
+// Synthesis on the matrix cores with P^m_n generated in registers instead of
+// read from the table: out[s][p][jp][m][f0+f] = sum_{n = m+p mod 2} P^m_n(mu_jp) cin[s][ext(m, n)][f0+f].
+// gx (N+1) blocks (gx = ceil(Jh/64), all blocks of an order on one XCD),
+// 256 threads, one wavefront per 16 latitudes.  Per order the sum over n is
+// a (16 latitudes) x (n) x (2 NF real columns) product, done by
+// v_mfma_f64_16x16x4f64 with the 4-deep inner dimension taken by four
+// degree segments: lane (i, q) = (lane % 16, lane / 16) owns latitude i and
+// segment q of the current round, starts from the stored exact pair
+// (P_{m+gL}, P_{m+gL+1}) and advances two degrees per step with the
+// three-term recurrence of the orthonormal functions (Sec. 3),
+// P_n = (mu P_{n-1} - eps_{n-1} P_{n-2}) / eps_n, in FP64.  Each step feeds
+// one even-degree and one odd-degree product (E and O accumulators, the two
+// hemisphere halves); the B operand is the lane's coefficient row of that
+// degree, column lane % 16.  STAGE = 0: cin holds coefficients in the ext
+// layout, F per entry; STAGE = 1: cin holds states [S][3][nspec] and the
+// staged rows are the tendency's grid fields (swe_prep_row; NF = F = 4);
+// STAGE = 2: cin holds F_E cotangents [S][3][nspec] and the staged rows are
+// the cotangents of the five weighted analyses (swe_combine_adj_row;
+// NF = F = 5).  The coefficient rows
+// and the recurrence coefficients of the round's 4 L degrees are staged in
+// LDS; each lane reads those of its next eight degrees in one batch
+// (clamped to the staged rows: degrees past nmax_use enter with P = 0)
+// before it advances through them.
 template <int NF, int STAGE = 0>
-__global__ __launch_bounds__(256) void k_leg_syn(const double* __restrict__ psyn,
-                                                 const long long* __restrict__ off,
-                                                 const double2* __restrict__ cin,
-                                                 double2* __restrict__ out, int N, int nmax_use,
-                                                 int Jh, int F, int f0, int S, long long cin_stride,
-                                                 long long out_stride, int gx, long long nspec, double a) {
-    extern __shared__ double2 csh[];                    // [K][NF]
-    __shared__ double red[3][2 * NF][64];
+__global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ ck,
+                                                   const long long* __restrict__ ckoff,
+                                                   const double2* __restrict__ rc,
+                                                   const double* __restrict__ mu,
+                                                   const double2* __restrict__ cin,
+                                                   double2* __restrict__ out, int N, int nmax_tab,
+                                                   int nmax_use, int Jh, int F, int f0, int S,
+                                                   long long cin_stride, long long out_stride, int gx,
+                                                   long long nspec, double a) {
+    static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
+    constexpr int U = 8;                                // degrees per batch of LDS reads
+    extern __shared__ double2 csh[];                    // [4L][NF] rows of the round, then [4L] rc
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const LegTile tile = leg_tile(gx, N + 1);
-    const int jp = tile.x * 64 + lane;
-    const int m = tile.m, p = tile.p;
+    const int i = lane & 15, q = lane >> 4;
+    const int ic = i < 2 * NF ? i : 2 * NF - 1;         // B column (clamped; columns >= 2 NF unused)
+    const LegTile tile = leg_tile(gx, N + 1, 1);
+    const int m = tile.m;
+    const int jw = tile.x * 64 + wv * 16;               // first latitude of this wavefront
+    const int jp = jw + i;
     const bool active = jp < Jh;
-    const int K = kcount(nmax_use, m, p);
-    const int kq = (K + 3) / 4;
-    const int k0 = min(K, wv * kq), k1 = min(K, k0 + kq);
-    const double* P = psyn + off[2 * m + p] + (active ? jp : 0);
-    const long long e0 = ext_idx(N, m, m + p);
-    // The lane's first UNR table values do not depend on the staged rows:
-    // they are requested before the staging so that the table stream is
-    // under way while the coefficients are fetched (rows clamped to the
-    // table, which holds at least one row for every (m, p)).
-    double pf[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) pf[u] = P[(long long)min(k0 + u, max(K - 1, 0)) * Jh];
+    const int Kt = nmax_tab - m + 1, Ku = nmax_use - m + 1;
+    const int R = seg_rounds(Kt), L = seg_len(Kt);
+    const double x = mu[active ? jp : 0];
+    const double2* ckm = ck + ckoff[m] + (active ? jp : 0);
+    double2* rsh = csh + 4 * L * NF;
+    const double* cd = reinterpret_cast<const double*>(csh);
+    const double2* rcm = rc + ext_idx(N, m, m);
     for (int s = 0; s < S; ++s) {
-        if (s > 0) __syncthreads();                     // previous state's readers are done
-        if constexpr (STAGE == 1) {
-            static_assert(NF == 4, "the tendency synthesis has four fields");
-            for (int kk = threadIdx.x; kk < K; kk += 256) {
-                double2 o[4];
-                swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * kk, o);
+        v4d accE = {0.0, 0.0, 0.0, 0.0}, accO = {0.0, 0.0, 0.0, 0.0};
+        for (int r = 0; r < R; ++r) {
+            const int kr0 = 4 * r * L;
+            if (kr0 >= Ku) break;                       // uniform
+            const int kc1 = min(kr0 + 4 * L, Ku), kt1 = min(kr0 + 4 * L, Kt);
+            const int g = 4 * r + q;
+            const double2 c0 = ckm[(long long)g * Jh];  // in flight during the staging
+            __syncthreads();                            // previous readers of the rows are done
+            if constexpr (STAGE == 1) {
+                static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
+                for (int kk = kr0 + threadIdx.x; kk < kc1; kk += 256) {
+                    double2 o[4];
+                    swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
 #pragma unroll
-                for (int f = 0; f < 4; ++f) csh[kk * 4 + f] = o[f];
-            }
-        } else if constexpr (STAGE == 2) {
-            static_assert(NF == 5, "the tendency adjoint synthesises five fields");
-            for (int kk = threadIdx.x; kk < K; kk += 256) {
-                double2 o[5];
-                swe_combine_adj_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * kk, o);
+                    for (int f = 0; f < 4; ++f) csh[(kk - kr0) * 4 + f] = o[f];
+                }
+            } else if constexpr (STAGE == 2) {
+                static_assert(STAGE != 2 || NF == 5, "the tendency adjoint synthesises five fields");
+                for (int kk = kr0 + threadIdx.x; kk < kc1; kk += 256) {
+                    double2 o[5];
+                    swe_combine_adj_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
 #pragma unroll
-                for (int f = 0; f < 5; ++f) csh[kk * 5 + f] = o[f];
-            }
-        } else {
-            const double2* cg = cin + s * cin_stride + e0 * F + f0;
-            for (int i = threadIdx.x; i < K * NF; i += 256) {
-                const int kk = i / NF, f = i - kk * NF;
-                csh[i] = cg[(long long)(2 * kk) * F + f];
-            }
-        }
-        __syncthreads();
-        const double2* c = csh;
-        double ar[NF], ai[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        auto batch = [&](const double* pv, int k) {
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const double2* ck = c + (k + u) * NF;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    ar[f] = fma(pv[u], ck[f].x, ar[f]);
-                    ai[f] = fma(pv[u], ck[f].y, ai[f]);
+                    for (int f = 0; f < 5; ++f) csh[(kk - kr0) * 5 + f] = o[f];
+                }
+            } else {
+                const double2* cg = cin + s * cin_stride + (ext_idx(N, m, m) + kr0) * F + f0;
+                for (int t = threadIdx.x; t < (kc1 - kr0) * NF; t += 256) {
+                    const int kk = t / NF, f = t - kk * NF;
+                    csh[t] = cg[(long long)kk * F + f];
                 }
             }
-        };
-        int k = k0;
-        if (s == 0 && k + UNR <= k1) {
-            batch(pf, k);
-            k += UNR;
-        }
-        // UNR table loads in flight per lane before the FMAs consume them
-        for (; k + UNR <= k1; k += UNR) {
-            double pv[UNR];
+            for (int kk = threadIdx.x; kk < kt1 - kr0; kk += 256) rsh[kk] = rcm[kr0 + kk];
+            __syncthreads();
+            if (jw >= Jh) continue;                     // uniform: no latitudes for this wavefront
+            const int k0 = g * L;
+            double pe = c0.x, po = c0.y;                // P_{m+k0}, P_{m+k0+1}
+            for (int t = 0; t < L; t += U) {
+                double2 rr[U];
+                double bb[U];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(k + u) * Jh];
-            batch(pv, k);
-        }
-        for (; k < k1; ++k) {
-            const double pv = P[(long long)k * Jh];
-            const double2* ck = c + k * NF;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                ar[f] = fma(pv, ck[f].x, ar[f]);
-                ai[f] = fma(pv, ck[f].y, ai[f]);
-            }
-        }
-        if (wv > 0) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                red[wv - 1][2 * f][lane] = ar[f];
-                red[wv - 1][2 * f + 1][lane] = ai[f];
-            }
-        }
-        __syncthreads();
-        if (wv == 0 && active) {
-            double2* o = out + s * out_stride + (((long long)p * Jh + jp) * (N + 1) + m) * F + f0;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                double xr = ar[f], xi = ai[f];
-#pragma unroll
-                for (int w = 0; w < 3; ++w) {
-                    xr += red[w][2 * f][lane];
-                    xi += red[w][2 * f + 1][lane];
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + t + u;
+                    rr[u] = rsh[min(k, kt1 - 1) - kr0];
+                    bb[u] = cd[(min(k, kc1 - 1) - kr0) * 2 * NF + ic];
                 }
-                o[f] = make_double2(xr, xi);
+#pragma unroll
+                for (int u = 0; u < U; u += 2) {
+                    const int ke = k0 + t + u;
+                    if (u > 0 || t > 0) {
+                        const double ne = fma(rr[u].x * x, po, -(rr[u].y * pe));
+                        po = fma(rr[u + 1].x * x, ne, -(rr[u + 1].y * po));
+                        pe = ne;
+                    }
+                    accE = __builtin_amdgcn_mfma_f64_16x16x4f64(ke < Ku ? pe : 0.0, bb[u], accE, 0, 0, 0);
+                    accO = __builtin_amdgcn_mfma_f64_16x16x4f64(ke + 1 < Ku ? po : 0.0, bb[u + 1], accO, 0, 0, 0);
+                }
+            }
+        }
+        // D layout (f64 16x16x4): the lane holds rows q + 4 rr (latitudes) of column i
+        if (jw < Jh && i < 2 * NF) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int jr = jw + q + 4 * rr;
+                if (jr < Jh) {
+                    double* o0 = reinterpret_cast<double*>(out + s * out_stride +
+                                                           ((long long)jr * (N + 1) + m) * F + f0) + i;
+                    o0[0] = accE[rr];
+                    o0[(long long)Jh * (N + 1) * F * 2] = accO[rr];
+                }
             }
         }
     }
@@ -511,14 +535,22 @@ __global__ __launch_bounds__(256) void k_leg_an128(const double* __restrict__ pa
     }
 }
 
+template <int NF, int STAGE = 0>
+void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S, int nmax_use,
+           long long cin_stride, double a, hipStream_t st) {
+    const int gx = (pl->Jh + 63) / 64;
+    int Lmax = 0;                                       // longest segment over the orders
+    for (int m = 0; m <= pl->N; ++m) Lmax = seg_len(pl->nmax - m + 1) > Lmax ? seg_len(pl->nmax - m + 1) : Lmax;
+    const size_t lds = (size_t)4 * Lmax * (NF + 1) * sizeof(double2);
+    k_leg_syn_m<NF, STAGE><<<gx * (pl->N + 1), 256, lds, st>>>(pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N,
+                                                              pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride,
+                                                              (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a);
+}
+
 template <int NF>
 void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S,
                int nmax_use, hipStream_t st) {
-    const int gx = (pl->Jh + 63) / 64;
-    const size_t lds = (size_t)kcount(nmax_use, 0, 0) * NF * sizeof(double2);
-    k_leg_syn<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, cin, out, pl->N, nmax_use, pl->Jh, F,
-                                                       f0, S, pl->nspec_e * F,
-                                                       (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, 0.0);
+    syn_r<NF>(pl, cin, out, F, f0, S, nmax_use, pl->nspec_e * F, 0.0, st);
 }
 
 template <int NF>
@@ -551,7 +583,8 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
 
 hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
     dim3 grid((pl->Jh + 63) / 64, pl->N + 1);
-    k_plm_table<<<grid, 64, 0, st>>>(pl->mu, pl->sint, pl->off, pl->psyn, pl->pan, pl->N, pl->nmax, pl->Jh);
+    k_plm_table<<<grid, 64, 0, st>>>(pl->mu, pl->sint, pl->off, pl->psyn, pl->pan, pl->ck, pl->ckoff, pl->rc,
+                                     pl->N, pl->nmax, pl->Jh);
     return hipGetLastError();
 }
 
@@ -578,22 +611,14 @@ hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, 
 hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
                               hipStream_t st) {
     if (pl->prec != SHX_FP64) return launch_leg_syn_mixed_swe(pl, a, state, out, S, st);
-    const int gx = (pl->Jh + 63) / 64;
-    const size_t lds = (size_t)kcount(pl->nmax, 0, 0) * 4 * sizeof(double2);
-    k_leg_syn<4, 1><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, state, out, pl->N, pl->nmax,
-                                                         pl->Jh, 4, 0, S, 3 * pl->nspec,
-                                                         (long long)pl->J * (pl->N + 1) * 4, gx, pl->nspec, a);
+    syn_r<4, 1>(pl, state, out, 4, 0, S, pl->nmax, 3 * pl->nspec, a, st);
     return hipGetLastError();
 }
 
 hipError_t launch_leg_syn_swe_adj(const shx_plan* pl, double a, const double2* lfe, double2* out, int S,
                                   hipStream_t st) {
     if (pl->prec != SHX_FP64) return hipErrorInvalidValue;
-    const int gx = (pl->Jh + 63) / 64;
-    const size_t lds = (size_t)kcount(pl->nmax, 0, 0) * 5 * sizeof(double2);
-    k_leg_syn<5, 2><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->psyn, pl->off, lfe, out, pl->N, pl->nmax,
-                                                         pl->Jh, 5, 0, S, 3 * pl->nspec,
-                                                         (long long)pl->J * (pl->N + 1) * 5, gx, pl->nspec, a);
+    syn_r<5, 2>(pl, lfe, out, 5, 0, S, pl->nmax, 3 * pl->nspec, a, st);
     return hipGetLastError();
 }
 
