@@ -39,6 +39,7 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->ck);
     (void)hipFree(p->ckoff);
     (void)hipFree(p->rc);
+    (void)hipFree(p->anblk);
     (void)hipFree(p->ord);
     (void)hipFree(p->deg);
     (void)hipFree(p->ord_e);
@@ -601,6 +602,23 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
         ckoff[m] = ck_elems;
         ck_elems += 4LL * seg_rounds(p->nmax - m + 1) * p->Jh;
     }
+    // analysis blocks: per XCD x the (m, g) of the orders m = x mod 8, in order
+    std::vector<std::vector<int>> xl(8);
+    for (int m = 0; m <= N; ++m)
+        for (int g = 0; g < 4 * seg_rounds(p->nmax - m + 1); ++g) {
+            xl[m % 8].push_back(m);
+            xl[m % 8].push_back(g);
+        }
+    size_t nslot = 0;
+    for (auto& v : xl) nslot = v.size() / 2 > nslot ? v.size() / 2 : nslot;
+    std::vector<int> anblk(16 * nslot, -1);
+    for (size_t t = 0; t < nslot; ++t)
+        for (int x = 0; x < 8; ++x)
+            if (2 * t < xl[x].size()) {
+                anblk[2 * (8 * t + x)] = xl[x][2 * t];
+                anblk[2 * (8 * t + x) + 1] = xl[x][2 * t + 1];
+            }
+    p->an_nblk = (int)(8 * nslot);
     std::vector<int> ord(p->nspec), deg(p->nspec), orde(p->nspec_e), dege(p->nspec_e);
     for (int m = 0; m <= N; ++m) {
         for (int n = m; n <= N; ++n) {
@@ -619,7 +637,8 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
               dalloc(&p->ord, p->nspec) == hipSuccess && dalloc(&p->deg, p->nspec) == hipSuccess &&
               dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess &&
               dalloc(&p->ck, ck_elems) == hipSuccess && dalloc(&p->ckoff, N + 1) == hipSuccess &&
-              dalloc(&p->rc, p->nspec_e) == hipSuccess;
+              dalloc(&p->rc, p->nspec_e) == hipSuccess && dalloc(&p->anblk, anblk.size()) == hipSuccess;
+    ok = ok && hipMemcpy(p->anblk, anblk.data(), anblk.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->ckoff, ckoff.data(), (N + 1) * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(p->ck, 0, ck_elems * sizeof(double2)) == hipSuccess;
     ok = ok && hipMemcpy(p->mu, p->h_mu.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;

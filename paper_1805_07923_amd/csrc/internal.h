@@ -174,6 +174,11 @@ struct shx_plan {
     double2* ck = nullptr;
     long long* ckoff = nullptr;     // device [N+1]
     double2* rc = nullptr;          // device [nspec_e]
+    // Blocks of the FP64 analysis, (m, segment g) pairs [2 an_nblk]: all
+    // blocks of an order on one XCD (block b runs on XCD b mod 8), (-1, -1)
+    // for padding.
+    int* anblk = nullptr;
+    int an_nblk = 0;
     int* ord = nullptr;             // device [nspec] zonal order of each entry
     int* deg = nullptr;             // device [nspec] degree of each entry
     int* ord_e = nullptr;           // device [nspec_e]

@@ -23,8 +23,16 @@
 namespace {
 
 constexpr int UNR = 8;   // table loads in flight per lane
-constexpr int AN_JC = 256;   // latitudes staged per chunk in the analysis
+constexpr int AN_JC = 256;   // latitude pairs up to which the table analysis is used
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Value of lane src (wave-uniform) of a per-lane double, for every lane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Double-double arithmetic (an unevaluated sum hi + lo of two FP64 numbers,
 // about 106 significant bits) from FP64 operations: error-free sum (Knuth)
@@ -273,14 +281,145 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
     }
 }
 
-// Analysis: cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
+// Analysis on the matrix cores with P^m_n generated in registers instead of
+// read from the table:
+// cout[s][ext(m, n)][f0+f] = sum_jp P^m_n(mu_jp) (G[s][jp][m][f0+f] + (-1)^{n-m} G[s][J-1-jp][m][f0+f]).
+// One block of nw = min(4, ceil(Jh/64)) wavefronts (64 nw threads) per (order m, restart
+// segment g) of the synthesis segmentation (degrees m + gL .. m + gL + L - 1,
+// L <= 64), listed XCD by XCD in blist so that all blocks of an order share
+// one L2.  Wavefront w takes the latitude groups w, w + nw, ... of 64
+// latitudes; for each, lane = latitude runs the three-term recurrence of the
+// orthonormal functions (Sec. 3) from the stored exact pair (P_{m+gL},
+// P_{m+gL+1}) in FP64 and stores the P of 32 degrees in a wave-private LDS
+// tile, split by parity ([latitude][16] for even and for odd degrees,
+// rows padded to 17 so that both the stores and the operand reads are
+// free of bank conflicts).  v_mfma_f64_16x16x4f64 then contracts 16 degrees
+// of one parity x 4 latitudes x 16 real columns; the B operand, the
+// north +/- south combination of the Fourier coefficients, is read by each
+// lane straight from G (column lane % 16 of latitude 4 c + lane / 16).  The
+// partial sums of the latitude groups are added through LDS in wavefront
+// order.
+template <int NF>
+__global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
+                                                  const double2* __restrict__ ck,
+                                                  const long long* __restrict__ ckoff,
+                                                  const double2* __restrict__ rc,
+                                                  const double* __restrict__ mu,
+                                                  const double2* __restrict__ G,
+                                                  double2* __restrict__ cout, int N, int nmax_tab,
+                                                  int nmax_use, int J, int F, int f0, int S,
+                                                  long long G_stride, long long cout_stride, int nw) {
+    static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
+    constexpr int TP = 17;                              // padded tile row
+    extern __shared__ double lsh[];                     // [nw][2][64][TP]; then the partial sums
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, q = lane >> 4;
+    const int m = blist[2 * blockIdx.x], g = blist[2 * blockIdx.x + 1];
+    if (m < 0) return;                                  // padding block (uniform)
+    const int Jh = J / 2;
+    const int Kt = nmax_tab - m + 1, Ku = nmax_use - m + 1;
+    const int L = seg_len(Kt);
+    const int k0 = g * L;
+    if (k0 >= Ku) return;                               // uniform
+    const int kend = min(k0 + L, Ku);                   // degrees k0 .. kend-1 are this block's
+    const int ntp = (kend - k0 + 31) / 32;              // 32-degree tile pairs (1 or 2)
+    const int ngrp = (Jh + 63) / 64;
+    double* PE = lsh + wv * (2 * 64 * TP);
+    double* PO = PE + 64 * TP;
+    double* red = lsh;                                  // [nw][2 ntp][4][64] after the products
+    const double2* rcm = rc + ext_idx(N, m, m);
+    const long long rs = (long long)(N + 1) * F * 2;    // latitude row stride of G in doubles
+    const int jc = i < 2 * NF ? i : 2 * NF - 1;         // B column (clamped; columns >= 2 NF unused)
+    for (int s = 0; s < S; ++s) {
+        v4d acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = v4d{0.0, 0.0, 0.0, 0.0};
+        const double* gs = reinterpret_cast<const double*>(G + s * G_stride + (long long)m * F + f0) + jc;
+        for (int lg = wv; lg < ngrp; lg += nw) {
+            const int jp = lg * 64 + lane;
+            const bool act = jp < Jh;
+            const double x = mu[act ? jp : 0];
+            const double2 c0 = act ? ck[ckoff[m] + (long long)g * Jh + jp] : make_double2(0.0, 0.0);
+            double be[16], bo[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int jb = lg * 64 + 4 * c + q;
+                const bool ab = jb < Jh;
+                const int jr = ab ? jb : 0;
+                const double vn = gs[jr * rs], vs = gs[(J - 1 - jr) * rs];
+                be[c] = ab ? vn + vs : 0.0;
+                bo[c] = ab ? vn - vs : 0.0;
+            }
+            double pe = c0.x, po = c0.y;                // P_{m+k0}, P_{m+k0+1}
+            // recurrence coefficients of the 64 degrees: lane t holds degree k0 + t
+            const double2 rcv = rcm[min(k0 + lane, Kt - 1)];
+            for (int tp = 0; tp < ntp; ++tp) {
+#pragma unroll
+                for (int i2 = 0; i2 < 16; ++i2) {
+                    if (tp > 0 || i2 > 0) {
+                        const int t = 32 * tp + 2 * i2;     // wave-uniform lane of the degree
+                        const double r0x = lane_bcast(rcv.x, t), r0y = lane_bcast(rcv.y, t);
+                        const double r1x = lane_bcast(rcv.x, t + 1), r1y = lane_bcast(rcv.y, t + 1);
+                        const double ne = fma(r0x * x, po, -(r0y * pe));
+                        po = fma(r1x * x, ne, -(r1y * po));
+                        pe = ne;
+                    }
+                    PE[lane * TP + i2] = pe;
+                    PO[lane * TP + i2] = po;
+                }
+                // same-wavefront LDS accesses complete in order: the tile is
+                // complete for the reads below
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    const double ae = PE[(4 * c + q) * TP + i];
+                    const double ao = PO[(4 * c + q) * TP + i];
+                    if (tp == 0) {
+                        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, be[c], acc[0][0], 0, 0, 0);
+                        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao, bo[c], acc[0][1], 0, 0, 0);
+                    } else {
+                        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, be[c], acc[1][0], 0, 0, 0);
+                        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao, bo[c], acc[1][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();                                // all tile reads done
+        {
+            for (int tp = 0; tp < ntp; ++tp)
+#pragma unroll
+                for (int eo = 0; eo < 2; ++eo)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        red[(((wv * 2 + tp) * 2 + eo) * 4 + rr) * 64 + lane] = acc[tp][eo][rr];
+        }
+        __syncthreads();
+        // wavefront w writes the tiles (tp, eo) = (u / 2, u % 2), u = w, w + nw, ...;
+        // D layout (f64 16x16x4): the lane holds rows q + 4 rr (degree pairs) of column i
+        for (int u = wv; u < 2 * ntp && i < 2 * NF; u += nw) {
+            const int tp = u >> 1, eo = u & 1;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int k = k0 + 32 * tp + 2 * (q + 4 * rr) + eo;
+                if (k < kend) {
+                    double v = 0.0;
+                    for (int w = 0; w < nw; ++w) v += red[(((w * 2 + tp) * 2 + eo) * 4 + rr) * 64 + lane];
+                    reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + k) * F + f0)[i] = v;
+                }
+            }
+        }
+        __syncthreads();                                // before the next state's tiles
+    }
+}
+
+// Analysis from the table (up to AN_JC latitude pairs and 6 fields, where
+// streaming the FP64 table measured faster than k_leg_an_m):
+// cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
 // gx (N+1) 2 blocks (gx = ceil(K/64), numbered by leg_tile), 256 threads: lane = degree row k, the four
 // wavefronts split the latitude sum into quarters.  The combined Fourier
 // data g_jp = G_north +/- G_south of this (m, p) is staged in LDS per state
-// and chunk of AN_JC latitudes (dynamic LDS: min(Jh, AN_JC) * NF double2) and
-// read by broadcast; the partial sums of waves 1..3 are added by wave 0
-// through LDS.
-template <int NF, bool CHUNK>
+// (dynamic LDS: Jh * NF double2) and read by broadcast; the partial sums of
+// waves 1..3 are added by wave 0 through LDS.
+template <int NF>
 __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                                                 const long long* __restrict__ off,
                                                 const double2* __restrict__ G,
@@ -297,11 +436,7 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
     if (tile.x * 64 >= K) return;                       // whole block idle (uniform)
     const bool active = k < K;
     const int Ktab = kcount(nmax_tab, m, p);
-    // Two bodies: up to T255 (Jh <= AN_JC) all latitudes are staged at once;
-    // beyond, in chunks of AN_JC latitudes.  The single-chunk case keeps its
-    // own loop structure (running it through the chunk loop measured slower
-    // for 7 and 8 fields).
-    if constexpr (!CHUNK) {
+    {
         const int Jh = J / 2;
         const int jq = (Jh + 3) / 4;
         const int j0 = wv * jq, j1 = min(Jh, j0 + jq);
@@ -369,171 +504,9 @@ __global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
                 }
             }
         }
-    } else {
-        const int Jh = J / 2;
-        const double* P = pan + off[2 * m + p] + (active ? k : 0);
-        const double sg = p ? -1.0 : 1.0;
-        const long long rowstride = (long long)(N + 1) * F;
-        for (int s = 0; s < S; ++s) {
-            const double2* g = G + s * G_stride + (long long)m * F + f0;
-            double ar[NF], ai[NF];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-            // latitudes in chunks of at most AN_JC (one chunk up to T255): the
-            // LDS footprint stays under AN_JC * NF double2, so that several
-            // blocks share a CU at T511 and T1023 too
-            for (int c0 = 0; c0 < Jh; c0 += AN_JC) {
-                const int cj = min(AN_JC, Jh - c0);
-                __syncthreads();                            // previous chunk's / state's readers are done
-                for (int i = threadIdx.x; i < cj * NF; i += 256) {
-                    const int jl = i / NF, f = i - jl * NF, jp = c0 + jl;
-                    const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
-                    gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
-                }
-                __syncthreads();
-                const int jq = (cj + 3) / 4;
-                const int j0 = min(cj, wv * jq), j1 = min(cj, j0 + jq);   // this wave's quarter of the chunk
-                const double* Pc = P + (long long)c0 * Ktab;
-                int jp = j0;
-                for (; jp + UNR <= j1; jp += UNR) {
-                    double pv[UNR];
-#pragma unroll
-                    for (int u = 0; u < UNR; ++u) pv[u] = Pc[(long long)(jp + u) * Ktab];
-#pragma unroll
-                    for (int u = 0; u < UNR; ++u) {
-                        const double2* gg = gsh + (jp + u) * NF;
-#pragma unroll
-                        for (int f = 0; f < NF; ++f) {
-                            const double2 x = gg[f];
-                            ar[f] = fma(pv[u], x.x, ar[f]);
-                            ai[f] = fma(pv[u], x.y, ai[f]);
-                        }
-                    }
-                }
-                for (; jp < j1; ++jp) {
-                    const double pv = Pc[(long long)jp * Ktab];
-                    const double2* gg = gsh + jp * NF;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const double2 x = gg[f];
-                        ar[f] = fma(pv, x.x, ar[f]);
-                        ai[f] = fma(pv, x.y, ai[f]);
-                    }
-                }
-            }
-            if (wv > 0) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    red[wv - 1][2 * f][lane] = ar[f];
-                    red[wv - 1][2 * f + 1][lane] = ai[f];
-                }
-            }
-            __syncthreads();
-            if (wv == 0 && active) {
-                double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    // fixed summation order: wave 0, 1, 2, 3
-                    double xr = ar[f], xi = ai[f];
-#pragma unroll
-                    for (int w = 0; w < 3; ++w) {
-                        xr += red[w][2 * f][lane];
-                        xi += red[w][2 * f + 1][lane];
-                    }
-                    o[f] = make_double2(xr, xi);
-                }
-            }
-        }
     }
 }
 
-// The analysis with 128-row degree tiles: waves (w & 1) take the two 64-row
-// halves, waves (w >> 1) the two latitude halves; a (m, parity) block stages
-// its Fourier rows once for up to 128 rows instead of twice.  Measured faster
-// than k_leg_an for 7 and 8 fields (the 15-field transform: 53.8 -> 48.0 us)
-// and slower for 5 (17.1 -> 22.3 us), so the launcher takes it for NF >= 7.
-template <int NF>
-__global__ __launch_bounds__(256) void k_leg_an128(const double* __restrict__ pan,
-                                                   const long long* __restrict__ off,
-                                                   const double2* __restrict__ G,
-                                                   double2* __restrict__ cout, int N, int nmax_tab,
-                                                   int nmax_use, int J, int F, int f0, int S,
-                                                   long long G_stride, long long cout_stride, int gx) {
-    extern __shared__ double2 gsh[];                    // [Jh][NF]
-    __shared__ double red[2][2 * NF][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int kh = wv & 1, jh = wv >> 1;
-    const LegTile tile = leg_tile(gx, N + 1);
-    const int k = tile.x * 128 + kh * 64 + lane;
-    const int m = tile.m, p = tile.p;
-    const int K = kcount(nmax_use, m, p);
-    if (tile.x * 128 >= K) return;
-    const bool active = k < K;
-    const int Ktab = kcount(nmax_tab, m, p);
-    const int Jh = J / 2;
-    const int jq = (Jh + 1) / 2;
-    const int j0 = jh * jq, j1 = min(Jh, j0 + jq);
-    const double* P = pan + off[2 * m + p] + (active ? k : 0);
-    const double sg = p ? -1.0 : 1.0;
-    const long long rowstride = (long long)(N + 1) * F;
-    const bool wave_rows = tile.x * 128 + kh * 64 < K;     // uniform: this wave has rows
-    for (int s = 0; s < S; ++s) {
-        const double2* g = G + s * G_stride + (long long)m * F + f0;
-        __syncthreads();                                // previous state's readers are done
-        for (int i = threadIdx.x; i < Jh * NF; i += 256) {
-            const int jp = i / NF, f = i - jp * NF;
-            const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
-            gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
-        }
-        __syncthreads();
-        double ar[NF], ai[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-        if (wave_rows) {
-            int jp = j0;
-            for (; jp + UNR <= j1; jp += UNR) {
-                double pv[UNR];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const double2* gg = gsh + (jp + u) * NF;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const double2 x = gg[f];
-                        ar[f] = fma(pv[u], x.x, ar[f]);
-                        ai[f] = fma(pv[u], x.y, ai[f]);
-                    }
-                }
-            }
-            for (; jp < j1; ++jp) {
-                const double pv = P[(long long)jp * Ktab];
-                const double2* gg = gsh + jp * NF;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const double2 x = gg[f];
-                    ar[f] = fma(pv, x.x, ar[f]);
-                    ai[f] = fma(pv, x.y, ai[f]);
-                }
-            }
-        }
-        if (jh == 1) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                red[kh][2 * f][lane] = ar[f];
-                red[kh][2 * f + 1][lane] = ai[f];
-            }
-        }
-        __syncthreads();
-        if (jh == 0 && active) {
-            // fixed summation order: latitude half 0, then half 1
-            double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-                o[f] = make_double2(ar[f] + red[kh][2 * f][lane], ai[f] + red[kh][2 * f + 1][lane]);
-        }
-    }
-}
 
 template <int NF, int STAGE = 0>
 void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S, int nmax_use,
@@ -556,27 +529,20 @@ void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int 
 template <int NF>
 void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
               hipStream_t st) {
-    const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
-    const size_t lds = (size_t)(pl->Jh < AN_JC ? pl->Jh : AN_JC) * NF * sizeof(double2);
-    if (pl->Jh > AN_JC) {
-        k_leg_an<NF, true><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
-                                                                nmax_use, pl->J, F, f0, S,
-                                                                (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
-                                                                gx);
+    if (NF <= 6 && pl->Jh <= AN_JC) {
+        const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
+        const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
+        k_leg_an<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
+                                                            pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
+                                                            pl->nspec_e * F, gx);
         return;
     }
-    if constexpr (NF >= 7) {
-        const int gx2 = (kcount(nmax_use, 0, 0) + 127) / 128;
-        k_leg_an128<NF><<<gx2 * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
-                                                                 nmax_use, pl->J, F, f0, S,
-                                                                 (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
-                                                                 gx2);
-    } else {
-        k_leg_an<NF, false><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax,
-                                                                 nmax_use, pl->J, F, f0, S,
-                                                                 (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
-                                                                 gx);
-    }
+    const int ngrp = (pl->Jh + 63) / 64;
+    const int nw = ngrp < 4 ? ngrp : 4;
+    const size_t lds = (size_t)nw * 2 * 64 * 17 * sizeof(double);
+    k_leg_an_m<NF><<<pl->an_nblk, 64 * nw, lds, st>>>(pl->anblk, pl->ck, pl->ckoff, pl->rc, pl->mu, G, cout, pl->N,
+                                                     pl->nmax, nmax_use, pl->J, F, f0, S,
+                                                     (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F, nw);
 }
 
 }  // namespace
