@@ -100,9 +100,14 @@ def test_sh_pair(pk, N, J, I, F):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("N,J,I,F,nmax_plus", [(31, 48, 96, 5, 1), (63, 96, 192, 3, 0)])
+@pytest.mark.parametrize("N,J,I,F,nmax_plus", [(31, 48, 96, 5, 1), (63, 96, 192, 3, 0), (100, 152, 384, 8, 1),
+                                               (100, 152, 384, 13, 0), (40, 64, 128, 7, 1)])
 def test_legendre_steps(pk, N, J, I, F, nmax_plus):
-    """The Legendre-only entry points on their documented layouts."""
+    """The Legendre-only entry points on their documented layouts.  Chunks
+    of 7-8 fields take the analysis on the matrix cores: 76 latitude pairs
+    are two groups of 64 latitudes, the second ragged (12); 13 fields mix a
+    matrix-core chunk (8) and a table chunk (5) in one call; 32 latitude
+    pairs leave half of the single group's lanes empty."""
     print_case("legendre steps", N, J, I, F)
     nmax = N + nmax_plus
     g = ogrid(N, J, I)
