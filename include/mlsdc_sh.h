@@ -89,7 +89,10 @@ size_t shx_nspec(int ntrunc);
  * 16 <= nlon <= 3072 (else SHX_EUNSUPPORTED).  Computes the Gaussian
  * latitudes and weights on the host in quad precision, the FFT twiddles in
  * extended precision, and the P^m_n tables (n <= ntrunc + 1) on the current
- * device with an FP64 recurrence, stored in `precision`.  Synchronises the
+ * device with a double-double recurrence built from FP64 operations, stored
+ * in `precision`, together with the exact restart values and recurrence
+ * coefficients from which the FP64 Legendre kernels regenerate P^m_n (at
+ * most 64 degrees of plain FP64 recurrence per restart).  Synchronises the
  * current device.  *out receives the plan (library-owned). */
 int shx_plan_create(int ntrunc, int nlat, int nlon, int precision, shx_plan** out);
 void shx_plan_destroy(shx_plan* plan);
