@@ -297,8 +297,10 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
 // of one parity x 4 latitudes x 16 real columns; the B operand, the
 // north +/- south combination of the Fourier coefficients, is read by each
 // lane straight from G (column lane % 16 of latitude 4 c + lane / 16).  The
-// partial sums of the latitude groups are added through LDS in wavefront
-// order.
+// recurrence coefficients of the segment's degrees are loaded one per lane
+// and broadcast with readlane (a scalar load per degree would make every
+// step wait on the counter it shares with the LDS stores).  The partial sums
+// of the latitude groups are added through LDS in wavefront order.
 template <int NF>
 __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
                                                   const double2* __restrict__ ck,
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
     const int ngrp = (Jh + 63) / 64;
     double* PE = lsh + wv * (2 * 64 * TP);
     double* PO = PE + 64 * TP;
-    double* red = lsh;                                  // [nw][2 ntp][4][64] after the products
+    double* red = lsh;                                  // [nw][2 tile pairs][2 parities][4][64] afterwards
     const double2* rcm = rc + ext_idx(N, m, m);
     const long long rs = (long long)(N + 1) * F * 2;    // latitude row stride of G in doubles
     const int jc = i < 2 * NF ? i : 2 * NF - 1;         // B column (clamped; columns >= 2 NF unused)
