@@ -1,7 +1,7 @@
 """Benchmark of the MLSDC-SH hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-graph]
-                    [--no-extra] [--only legendre|mixed|adjoint|large]
+                    [--no-extra] [--only legendre|mixed|adjoint|large|dome] [--dome-hours H]
 
 A step is one two-level MLSDC time step (Algorithm 1 of the paper) on the
 headline workload: fine level T255 on the 768 x 384 Gaussian grid with 5
@@ -19,9 +19,14 @@ T127/T63 configuration, Legendre GFLOP/s of the 15-field T255 transform pair
 and steps/s per working precision with the error against FP64, the adjoint's
 seconds per step (T127/T63, 20 checkpointed steps) and the large
 T1023/T511 Gauss-Radau configuration per precision.
+
+`--only dome` runs the Gaussian-dome temporal refinement study instead (one
+simulated day at T255/T127 per scheme and time step; errors, observed orders,
+GPU seconds, observed MLSDC speedups at matched error).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -307,6 +312,99 @@ def large_extra(pk, torch, workload, graph):
     return extra
 
 
+# Gaussian-dome temporal refinement (Sec. 5.2): schemes as (name, fine
+# Gauss-Lobatto nodes, coarse nodes or None, iterations), one fine and one
+# coarse sweep per iteration (the paper's setting), fine T255 / coarse T127.
+DOME_SCHEMES = (("SDC(3,4)", 3, None, 4), ("MLSDC(3,2,2,1/2)", 3, 2, 2), ("SDC(5,8)", 5, None, 8),
+                ("MLSDC(5,3,4,1/2)", 5, 3, 4), ("MLSDC(5,3,7,1/2)", 5, 3, 7))
+DOME_DTS = (30.0, 60.0, 120.0, 240.0, 480.0, 960.0)
+DOME_REF_DT = 15.0
+
+
+def advance(torch, stepper, x0, dt, nsteps):
+    """nsteps steps from x0: the first eager (it also sizes the workspaces),
+    the others as replays of a captured one-step graph.  Returns the state
+    and the seconds per replayed step."""
+    a = x0.clone()
+    b = torch.empty_like(a)
+    stepper.step(dt, a, b)
+    a, b = b, a
+    if nsteps == 1:
+        torch.cuda.synchronize()
+        return a, float("nan")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            stepper.step(dt, a, b)
+            a.copy_(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps - 1):
+        g.replay()
+    torch.cuda.synchronize()
+    return a, (time.perf_counter() - t0) / (nsteps - 1)
+
+
+def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
+    """Temporal refinement on the Gaussian dome over t_end seconds: L_inf
+    errors of the geopotential and vorticity on the fine grid against
+    SDC(5,8) at dt = 60 s, observed orders between successive dt, seconds
+    per step, and the observed speedup of each MLSDC scheme over its
+    single-level counterpart at matched geopotential error (cost of the
+    single-level scheme interpolated log-log in its error)."""
+    par = pk.swe_params(phibar=workload.dome_phibar())
+    pf = pk.Plan(FINE["N"], FINE["J"], FINE["I"])
+    pc = pk.Plan(COARSE["N"], COARSE["J"], COARSE["I"])
+    mu = pf.latitudes()[0]
+    grid = torch.tensor(workload.dome_grid(mu, FINE["I"])[None], device="cuda")
+    x0 = torch.zeros(3, workload.nspec(FINE["N"]), dtype=torch.complex128, device="cuda")
+    x0[0] = pf.forward(grid)[0]
+
+    def stepper(nf, nc, k):
+        lf = pk.Level(pf, par, pk.SDC_GAUSS_LOBATTO, nf)
+        lc = pk.Level(pc, par, pk.SDC_GAUSS_LOBATTO, nc) if nc else None
+        return pk.Stepper(lf, lc, niter=k, nsweep_fine=1, nsweep_coarse=1)
+
+    def fields(x):
+        return pf.inverse(x[0:2].contiguous())
+
+    ref, _ = advance(torch, stepper(5, None, 8), x0, DOME_REF_DT, int(round(t_end / DOME_REF_DT)))
+    rg = fields(ref)
+    out = {"t_end_s": t_end, "reference": f"SDC(5,8), dt = {DOME_REF_DT:g} s", "dt_s": list(DOME_DTS),
+           "alpha": workload.DOME["alpha"], "schemes": {}}
+    out["dt_s"] = list(dts)
+    for name, nf, nc, k in DOME_SCHEMES:
+        errs, errz, cost = [], [], []
+        st = stepper(nf, nc, k)
+        for dt in dts:
+            x, sps = advance(torch, st, x0, dt, int(round(t_end / dt)))
+            d = fields(x) - rg
+            errs.append(d[0].abs().max().item())
+            errz.append(d[1].abs().max().item())
+            cost.append(sps * t_end / dt)
+        order = [math.log2(errs[i + 1] / errs[i]) if errs[i] > 0 and errs[i + 1] > 0 else float("nan")
+                 for i in range(len(errs) - 1)]
+        out["schemes"][name] = {"linf_phi": errs, "linf_zeta": errz, "order_phi": order,
+                                "gpu_seconds": cost}
+    for ml, sl in (("MLSDC(3,2,2,1/2)", "SDC(3,4)"), ("MLSDC(5,3,4,1/2)", "SDC(5,8)")):
+        m, s1 = out["schemes"][ml], out["schemes"][sl]
+        pts = [(a, b) for a, b in zip(s1["linf_phi"], s1["gpu_seconds"]) if a > 0 and math.isfinite(a)]
+        le = np.log(np.array([a for a, _ in pts]))
+        lc = np.log(np.array([b for _, b in pts]))
+        sp = []
+        for e, c in zip(m["linf_phi"], m["gpu_seconds"]):
+            ok = len(pts) > 1 and e > 0 and le.min() <= math.log(e) <= le.max()
+            if not ok:
+                sp.append(float("nan"))
+                continue
+            o = np.argsort(le)
+            sp.append(float(np.exp(np.interp(math.log(e), le[o], lc[o])) / c))
+        m["speedup_vs_" + sl] = sp
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,9 +413,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--only", choices=["legendre", "mixed", "adjoint", "large"], default=None,
+    ap.add_argument("--only", choices=["legendre", "mixed", "adjoint", "large", "dome"], default=None,
                     help="run only this group of secondary measurements and print them as one JSON line "
                          "(for profiler runs)")
+    ap.add_argument("--dome-hours", type=float, default=24.0,
+                    help="simulated time of the Gaussian-dome refinement study (--only dome)")
+    ap.add_argument("--dome-dts", default=",".join(f"{v:g}" for v in DOME_DTS),
+                    help="comma-separated time steps (s) of the Gaussian-dome study")
+    ap.add_argument("--dome-alpha", type=float, default=None,
+                    help="dome width parameter alpha in exp(-alpha (d/a)^2) (default: the workload's)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -334,6 +438,8 @@ def main():
         sys.exit(1)
     pk.lib()
     torch.cuda.set_device(0)
+    if args.dome_alpha is not None:
+        workload.DOME["alpha"] = args.dome_alpha
     state_np = workload.state(FINE["N"], SEED)
     x0 = torch.tensor(state_np, device="cuda")
     if args.only:
@@ -341,7 +447,9 @@ def main():
         run = {"legendre": lambda: legendre_extra(pk, torch, workload),
                "mixed": lambda: mixed_steps_extra(pk, torch, x0, args.steps, graph),
                "adjoint": lambda: adjoint_extra(pk, torch, workload),
-               "large": lambda: large_extra(pk, torch, workload, graph)}[args.only]
+               "large": lambda: large_extra(pk, torch, workload, graph),
+               "dome": lambda: dome_extra(pk, torch, workload, args.dome_hours * 3600.0,
+                                          tuple(float(v) for v in args.dome_dts.split(",")))}[args.only]
         print(json.dumps({"only": args.only, "extra": run()}), flush=True)
         return
 

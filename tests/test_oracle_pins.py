@@ -502,3 +502,29 @@ def test_theoretical_speedup_from_evaluation_counts():
         assert abs(S - formula) < 1e-12
         # the paper prints the formula rounded to two decimals (1.654 -> "about 1.66")
         assert abs(S - d["value"]) <= d["rounding"], (key, S)
+
+
+def test_dome_sdc_temporal_order():
+    """The oracle's SDC(3,4) (three Gauss-Lobatto nodes, four sweeps) is
+    fourth order in time (collocation order 2M - 2 = 4 reached after four
+    sweeps, Sec. 4.2) on the Gaussian dome of Sec. 5.2 at T15: the errors at
+    dt = 450, 225, 112.5 s after 30 minutes, against SDC(5,8) at 112.5 s,
+    fall by 2^4 per halving (observed orders within 3.5 .. 4.5)."""
+    import workload
+    N, J, I = 15, 24, 48
+    p = swe.SWEParams(phibar=workload.dome_phibar())
+    g = sht.Grid(N, J, I)
+    x0 = torch.zeros(3, workload.nspec(N), dtype=torch.complex128)
+    x0[0] = g.sh_forward(torch.tensor(workload.dome_grid(g.mu.numpy(), I))[None])[0]
+
+    def run(nodes, K, dt, T=1800.0):
+        lev = sdc.Level(swe.SWEProblem(N, J, I, p), "lobatto", nodes)
+        x = x0.clone()
+        for _ in range(int(round(T / dt))):
+            x = sdc.mlsdc_step(lev, None, dt, x, niter=K)
+        return x
+
+    ref = run(5, 8, 112.5)
+    err = [(run(3, 4, dt)[0] - ref[0]).abs().max().item() for dt in (450.0, 225.0, 112.5)]
+    orders = [math.log2(err[i] / err[i + 1]) for i in range(2)]
+    assert all(3.5 < o < 4.5 for o in orders), (err, orders)

@@ -90,3 +90,31 @@ SEEDS = {
     "mlsdc_T1023": [1004],
     "mlsdc_T255": [1005],
 }
+
+
+# Gaussian dome (Sec. 5.2 of the paper, after the third case of Swarztrauber
+# et al. 2004): h = hbar + A exp(-alpha (d/a)^2), d the chord distance to
+# (lam_c, phi_c), no initial wind.  The paper does not state alpha: 400 here
+# (e-folding distance a/20, about 320 km), for which the geopotential
+# coefficients beyond degree 128 are of order 1e-1 m^2/s^2 or less, as the
+# paper's spectrum shows for its dome.
+DOME = dict(hbar=29400.0, A=6000.0, lam_c=np.pi, phi_c=np.pi / 4, alpha=400.0, g=9.80616)
+
+
+def dome_phibar():
+    """Mean geopotential g * hbar of the dome case (m^2/s^2)."""
+    return DOME["g"] * DOME["hbar"]
+
+
+def dome_grid(mu, nlon):
+    """Geopotential perturbation g A exp(-alpha (d/a)^2) on the grid
+    [len(mu)][nlon], latitudes given by mu = sin(phi), longitudes 2 pi i / nlon."""
+    mu = np.asarray(mu, dtype=np.float64)
+    cphi = np.sqrt(np.maximum(0.0, 1.0 - mu * mu))[:, None]
+    sphi = mu[:, None]
+    lam = 2.0 * np.pi * np.arange(nlon, dtype=np.float64)[None, :] / nlon
+    lc, pc = DOME["lam_c"], DOME["phi_c"]
+    x = np.cos(lam) * cphi - np.cos(lc) * np.cos(pc)
+    y = np.sin(lam) * cphi - np.sin(lc) * np.cos(pc)
+    z = sphi - np.sin(pc)
+    return DOME["g"] * DOME["A"] * np.exp(-DOME["alpha"] * (x * x + y * y + z * z))
