@@ -169,3 +169,68 @@ def spectral_transfer(N_f, N_c):
     def interp(x):
         return zero_pad(x, N_c, N_f)
     return restrict, interp
+
+
+def mlsdc_step_multi(levels, dt, theta_n, niter, nsweeps, transfers, history=None):
+    """One time step of multi-level MLSDC: the V-cycle that Algorithm 1 is
+    the two-level case of (Sec. 4.3), for levels[0] (finest) .. levels[L-1].
+    transfers[l] = (restrict_space, interp_space) between levels l and l+1;
+    nsweeps[l] sweeps on level l per iteration.  Per iteration: sweep the
+    finest level; going down, restrict the nodes 1..M of level l into level
+    l+1, evaluate, save the restriction, form the FAS term
+    tau_{l+1} = A_{l+1}(R Theta_l) - R A_l(Theta_l) + R tau_l (eq.
+    tau_term_level_l+1, tau_l = 0 on the finest level) and sweep with it;
+    going up, add the interpolated corrections of Theta, F_I and F_E of
+    level l+1 to level l.  Node 0 of every coarser level is the restricted
+    initial value, evaluated once per step.  With two levels this is
+    mlsdc_step."""
+    L = len(levels)
+    M = [lv.M for lv in levels]
+    p0 = levels[0].problem
+    fi0, fe0 = p0.evaluate(theta_n)
+    th = [[theta_n] * (M[0] + 1)]
+    fi = [[fi0] * (M[0] + 1)]
+    fe = [[fe0] * (M[0] + 1)]
+    P_down, P_up, x0 = [], [], [theta_n]
+    for l in range(1, L):
+        P_down.append(transfer_matrix(levels[l - 1].mat, levels[l].mat))
+        P_up.append(transfer_matrix(levels[l].mat, levels[l - 1].mat))
+        x0.append(transfers[l - 1][0](x0[l - 1]))
+    f0 = [None] + [levels[l].problem.evaluate(x0[l]) for l in range(1, L)]
+    for _ in range(niter):
+        for _s in range(nsweeps[0]):
+            th[0], fi[0], fe[0] = sweep(levels[0], dt, th[0], fi[0], fe[0])
+        saved = [None] * L
+        tau = [None] * L
+        del th[1:], fi[1:], fe[1:]
+        for l in range(1, L):
+            lv, restrict = levels[l], transfers[l - 1][0]
+            t_l = [x0[l]] + [None] * M[l]
+            i_l = [f0[l][0]] + [None] * M[l]
+            e_l = [f0[l][1]] + [None] * M[l]
+            for m in range(1, M[l] + 1):
+                t_l[m] = restrict(_wsum(P_down[l - 1][m], th[l - 1]))
+                i_l[m], e_l[m] = lv.problem.evaluate(t_l[m])
+            saved[l] = (list(t_l), list(i_l), list(e_l))
+            tau[l] = fas_tau(levels[l - 1], lv, dt, fi[l - 1], fe[l - 1], i_l, e_l, restrict, P_down[l - 1])
+            if tau[l - 1] is not None:
+                rt = [restrict(_wsum(P_down[l - 1][i], tau[l - 1])) for i in range(M[l] + 1)]
+                tau[l] = [tau[l][i] + rt[i] for i in range(M[l] + 1)]
+            for _s in range(nsweeps[l]):
+                t_l, i_l, e_l = sweep(lv, dt, t_l, i_l, e_l, tau[l])
+            th.append(t_l)
+            fi.append(i_l)
+            fe.append(e_l)
+        for l in range(L - 1, 0, -1):
+            interp = transfers[l - 1][1]
+            st, si, se = saved[l]
+            d_th = [th[l][i] - st[i] for i in range(M[l] + 1)]
+            d_fi = [fi[l][i] - si[i] for i in range(M[l] + 1)]
+            d_fe = [fe[l][i] - se[i] for i in range(M[l] + 1)]
+            for m in range(1, M[l - 1] + 1):
+                th[l - 1][m] = th[l - 1][m] + interp(_wsum(P_up[l - 1][m], d_th))
+                fi[l - 1][m] = fi[l - 1][m] + interp(_wsum(P_up[l - 1][m], d_fi))
+                fe[l - 1][m] = fe[l - 1][m] + interp(_wsum(P_up[l - 1][m], d_fe))
+        if history is not None:
+            history.append(list(th[0]))
+    return th[0][M[0]]
