@@ -172,6 +172,14 @@ def variants_extra(pk, torch, workload, x0, steps, graph):
     sdc_rate = max(5, steps // 2) / ssdc
     extra["steps_per_s_T255_SDC_5_8"] = sdc_rate
     extra["speedup_MLSDC_5_3_4_vs_SDC_5_8"] = extra["steps_per_s_T255_T127_sweeps_1_1"] / sdc_rate
+    # three levels (mlsdc_step_multi): T255 / T127 / T63 with 5 / 3 / 2
+    # nodes, one sweep per level, 4 iterations, against the two-level
+    # (1+1) x 4 step above
+    lv3 = [pk.Level(pk.Plan(c["N"], c["J"], c["I"]), par, pk.SDC_GAUSS_LOBATTO, c["nodes"])
+           for c in (FINE, COARSE, dict(N=63, J=96, I=192, nodes=2))]
+    st3 = pk.MultiStepper(lv3, niter=NITER, nsweeps=1)
+    s3, _ = run_steps(torch, st3, x0, max(5, steps // 2), 2, graph)
+    extra["steps_per_s_T255_T127_T63_three_levels_1_1_1"] = max(5, steps // 2) / s3
     return extra
 
 

@@ -214,6 +214,28 @@ int mlsdc_step(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts*
                double dt, const double* theta_n_dev, double* theta_np1_dev,
                double* status_dev, void* ws_dev, size_t ws_bytes, shx_stream_t stream);
 
+/* Multi-level MLSDC: the V-cycle of which Algorithm 1 is the two-level case
+ * (Sec. 4.3; more than two levels are the paper's future work), over
+ * levels[0] (finest) .. levels[nlevels-1], 1 <= nlevels <= SHX_MAX_LEVELS.
+ * Per iteration: nsweep[0] sweeps on the finest level; going down, level l
+ * takes the restriction of level l-1 at its nodes 1..M, evaluates it, forms
+ * its FAS term tau_l = A_l(R Theta_{l-1}) - R A_{l-1}(Theta_{l-1}) + R tau_{l-1}
+ * (eq. tau_term_level_l+1) and runs nsweep[l] sweeps; going up, the
+ * corrections of Theta, F_I and F_E of level l are interpolated into level
+ * l-1.  Node 0 of every coarser level is the restricted initial value,
+ * evaluated once per step.  Levels: one node kind, strictly decreasing
+ * truncation, non-increasing node counts, alias-free grids.  With two levels
+ * this launches what mlsdc_step launches (no residual check).
+ * theta_n_dev, theta_np1_dev: [3][nspec] of levels[0]'s plan (may alias);
+ * ws: device workspace of mlsdc_multi_workspace_bytes bytes (16-byte
+ * aligned).  Errors: SHX_EINVAL (arguments, level order), SHX_ESHAPE (grid
+ * not alias free), SHX_EWORKSPACE.  Asynchronous on `stream`. */
+#define SHX_MAX_LEVELS 4
+size_t mlsdc_multi_workspace_bytes(const sdc_level* const* levels, int nlevels);
+int mlsdc_step_multi(const sdc_level* const* levels, int nlevels, int niter, const int* nsweep,
+                     double dt, const double* theta_n_dev, double* theta_np1_dev, void* ws_dev,
+                     size_t ws_bytes, shx_stream_t stream);
+
 /* -------------------------------------------------------------- adjoints
  * Transposes of the Jacobians above (reverse mode), FP64.  Inner products:
  * spectral arrays <x, y> = sum over the stored coefficients of

@@ -51,6 +51,8 @@ _SIGS = {
     "sdc_sweep": (_I, [_P, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "mlsdc_workspace_bytes": (_SZ, [_P, _P, ctypes.POINTER(MlsdcOpts)]),
     "mlsdc_step": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P, _SZ, _P]),
+    "mlsdc_multi_workspace_bytes": (_SZ, [_P, _I]),
+    "mlsdc_step_multi": (_I, [_P, _I, _I, _P, _D, _P, _P, _P, _SZ, _P]),
     "sh_inverse_adj": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
     "sh_forward_adj": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
     "swe_adj_workspace_bytes": (_SZ, [_P, _I]),
@@ -402,6 +404,38 @@ class Stepper:
         _check(lib().mlsdc_step(self.fine.h, self.coarse.h if self.coarse else None, ctypes.byref(self.opts),
                                 float(dt), _ptr(theta_n), _ptr(theta_np1), _ptr(status), _ptr(w), self.nbytes,
                                 _stream()), "mlsdc_step")
+        return theta_np1
+
+
+class MultiStepper:
+    """mlsdc_step_multi over levels[0] (finest) .. levels[-1] with a
+    persistent workspace; nsweeps: sweeps per level and iteration (an int for
+    all levels, or one per level)."""
+
+    def __init__(self, levels, niter=4, nsweeps=1):
+        self.levels = list(levels)
+        L = len(self.levels)
+        ns = [nsweeps] * L if isinstance(nsweeps, int) else list(nsweeps)
+        if len(ns) != L:
+            raise ShxError("one sweep count per level")
+        self.niter = niter
+        self._lv = (ctypes.c_void_p * L)(*[lv.h for lv in self.levels])
+        self._ns = (ctypes.c_int * L)(*ns)
+        self.ws = Workspace()
+        self.nbytes = lib().mlsdc_multi_workspace_bytes(self._lv, L)
+        if self.nbytes == 0:
+            raise ShxError("mlsdc_step_multi: invalid level list")
+
+    def step(self, dt, theta_n, theta_np1=None):
+        import torch
+        n = 3 * self.levels[0].plan.nspec
+        _need(theta_n, torch.complex128, n, "theta_n")
+        if theta_np1 is None:
+            theta_np1 = torch.empty_like(theta_n)
+        _need(theta_np1, torch.complex128, n, "theta_np1")
+        w = self.ws.get(self.nbytes)
+        _check(lib().mlsdc_step_multi(self._lv, len(self.levels), self.niter, self._ns, float(dt), _ptr(theta_n),
+                                      _ptr(theta_np1), _ptr(w), self.nbytes, _stream()), "mlsdc_step_multi")
         return theta_np1
 
 

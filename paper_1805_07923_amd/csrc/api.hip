@@ -382,6 +382,143 @@ int step_body(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, dou
 
 namespace {
 
+// ---------------------------------------------------- multi-level V-cycle
+// Per-level buffers of mlsdc_step_multi.  Level 0 (finest): th, fi[2],
+// fe[2] and a one-state tendency workspace, as the fine level of step_body.
+// Level l >= 1: th (iterate), tht / fit / fet (the restriction and its F,
+// kept for the correction), fi[2] / fe[2] (sweep outputs), tau, tmp (the
+// restricted tau of level l-1) and an M-state tendency workspace.
+struct LevelWS {
+    double2 *th, *tht, *fit, *fet, *fi[2], *fe[2], *tau, *tmp;
+    TendWS t;
+};
+LevelWS carve_level(Carve& c, const sdc_level* lv, bool finest) {
+    LevelWS w{};
+    const size_t n = (size_t)lv->nnodes * 3 * lv->plan->nspec;
+    w.th = c.take<double2>(n);
+    for (int b = 0; b < 2; ++b) {
+        w.fi[b] = c.take<double2>(n);
+        w.fe[b] = c.take<double2>(n);
+    }
+    if (finest) {
+        w.t = carve_tend(c, lv->plan, 1);
+        return w;
+    }
+    w.tht = c.take<double2>(n);
+    w.fit = c.take<double2>(n);
+    w.fet = c.take<double2>(n);
+    w.tau = c.take<double2>(n);
+    w.tmp = c.take<double2>(n);
+    w.t = carve_tend(c, lv->plan, lv->nnodes - 1 > 1 ? lv->nnodes - 1 : 1);
+    return w;
+}
+
+bool valid_levels(const sdc_level* const* lv, int L) {
+    if (!lv || L < 1 || L > SHX_MAX_LEVELS) return false;
+    for (int l = 0; l < L; ++l) {
+        if (!lv[l]) return false;
+        if (l > 0 && (lv[l]->kind != lv[0]->kind || lv[l]->plan->N >= lv[l - 1]->plan->N ||
+                      lv[l]->nnodes > lv[l - 1]->nnodes))
+            return false;
+    }
+    return true;
+}
+
+// One step of the V-cycle over L levels (validated arguments); with L = 2
+// the same launches as step_body without tape and status.
+int step_multi_body(const sdc_level* const* lv, int L, int niter, const int* ns, double dt, const double2* th_n,
+                    double2* out, LevelWS* w, hipStream_t st) {
+    const shx_plan* p0 = lv[0]->plan;
+    const int M0 = lv[0]->nnodes - 1;
+    size_t n3[SHX_MAX_LEVELS];
+    for (int l = 0; l < L; ++l) n3[l] = 3 * (size_t)lv[l]->plan->nspec;
+    // spread on the finest level
+    HIPCHK(hipMemcpyAsync(w[0].th, th_n, n3[0] * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    int rc = tendency_impl(p0, lv[0]->p, 1, w[0].th, w[0].fi[0], w[0].fe[0], w[0].t, st);
+    if (rc) return rc;
+    {
+        NodeCopies nc{};
+        nc.add(w[0].th, w[0].th, 1, M0);
+        nc.add(w[0].fi[0], w[0].fi[0], 1, M0);
+        nc.add(w[0].fe[0], w[0].fe[0], 1, M0);
+        nc.add(w[0].fi[0], w[0].fi[1], 0, 0);
+        nc.add(w[0].fe[0], w[0].fe[1], 0, 0);
+        HIPCHK(launch_node_copies(nc, (long long)n3[0], st));
+    }
+    // transfer matrices of each pair (l-1, l) and node 0 of the coarser levels
+    Mat9x9 Pdn[SHX_MAX_LEVELS]{}, Pup[SHX_MAX_LEVELS]{}, PQ[SHX_MAX_LEVELS]{}, Qc[SHX_MAX_LEVELS]{};
+    for (int l = 1; l < L; ++l) {
+        const int nf = lv[l - 1]->nnodes, nc = lv[l]->nnodes;
+        double a[81], b[81];
+        if (shx_host_transfer(lv[0]->kind, nf, nc, a)) return SHX_EINVAL;   // [nc][nf]
+        if (shx_host_transfer(lv[0]->kind, nc, nf, b)) return SHX_EINVAL;   // [nf][nc]
+        Pdn[l] = to_mat(a, nc * nf);
+        Pup[l] = to_mat(b, nf * nc);
+        for (int i = 0; i < nc; ++i)
+            for (int j = 0; j < nf; ++j) {
+                double sum = 0.0;
+                for (int k = 0; k < nf; ++k) sum += a[i * nf + k] * lv[l - 1]->Q[k * nf + j];
+                PQ[l].a[i * nf + j] = sum;
+            }
+        Qc[l] = to_mat(lv[l]->Q, nc * nc);
+        Mat9x9 e0{};
+        e0.a[0] = 1.0;
+        HIPCHK(launch_restrict(p0, lv[l]->plan, e0, 1, 0, 1, th_n, w[l].th, w[l].tht, st));
+        rc = tendency_impl(lv[l]->plan, lv[l]->p, 1, w[l].tht, w[l].fit, w[l].fet, w[l].t, st);
+        if (rc) return rc;
+        NodeCopies nc0{};
+        for (int b2 = 0; b2 < 2; ++b2) {
+            nc0.add(w[l].fit, w[l].fi[b2], 0, 0);
+            nc0.add(w[l].fet, w[l].fe[b2], 0, 0);
+        }
+        HIPCHK(launch_node_copies(nc0, (long long)n3[l], st));
+    }
+    int fcur = 0;
+    for (int k = 0; k < niter; ++k) {
+        for (int s2 = 0; s2 < ns[0]; ++s2) {
+            rc = sweep_impl(lv[0], dt, w[0].th, w[0].fi[fcur], w[0].fe[fcur], w[0].fi[1 - fcur], w[0].fe[1 - fcur],
+                            nullptr, w[0].t, st);
+            if (rc) return rc;
+            fcur = 1 - fcur;
+        }
+        double2 *ci[SHX_MAX_LEVELS], *ce[SHX_MAX_LEVELS];   // current F of each level
+        ci[0] = w[0].fi[fcur];
+        ce[0] = w[0].fe[fcur];
+        for (int l = 1; l < L; ++l) {                     // down: restrict, FAS, sweep
+            const shx_plan *pf = lv[l - 1]->plan, *pc = lv[l]->plan;
+            const int nf = lv[l - 1]->nnodes, nc = lv[l]->nnodes, Mc = nc - 1;
+            HIPCHK(launch_restrict(pf, pc, Pdn[l], nf, 1, nc, w[l - 1].th, w[l].th, w[l].tht, st));
+            rc = tendency_impl(pc, lv[l]->p, Mc, w[l].tht + n3[l], w[l].fit + n3[l], w[l].fet + n3[l], w[l].t, st);
+            if (rc) return rc;
+            HIPCHK(launch_fas_tau(pf, pc, PQ[l], Qc[l], nf, nc, dt, ci[l - 1], ce[l - 1], w[l].fit, w[l].fet,
+                                  w[l].tau, st));
+            if (l >= 2) {                                 // + the restricted tau of level l-1
+                HIPCHK(launch_restrict(pf, pc, Pdn[l], nf, 0, nc, w[l - 1].tau, w[l].tmp, nullptr, st));
+                HIPCHK(launch_add(w[l].tmp, w[l].tau, (long long)nc * (long long)n3[l], st));
+            }
+            const double2 *fi_old = w[l].fit, *fe_old = w[l].fet;
+            for (int s2 = 0; s2 < ns[l]; ++s2) {
+                rc = sweep_impl(lv[l], dt, w[l].th, fi_old, fe_old, w[l].fi[s2 & 1], w[l].fe[s2 & 1], w[l].tau, w[l].t,
+                                st);
+                if (rc) return rc;
+                fi_old = w[l].fi[s2 & 1];
+                fe_old = w[l].fe[s2 & 1];
+            }
+            ci[l] = w[l].fi[(ns[l] - 1) & 1];
+            ce[l] = w[l].fe[(ns[l] - 1) & 1];
+        }
+        for (int l = L - 1; l >= 1; --l)                  // up: corrections of level l into level l-1
+            HIPCHK(launch_interp(lv[l - 1]->plan, lv[l]->plan, Pup[l], lv[l - 1]->nnodes, lv[l]->nnodes, w[l].th,
+                                 w[l].tht, ci[l], w[l].fit, ce[l], w[l].fet, w[l - 1].th, ci[l - 1], ce[l - 1], st));
+    }
+    HIPCHK(hipMemcpyAsync(out, w[0].th + M0 * n3[0], n3[0] * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    return SHX_OK;
+}
+
+}  // namespace
+
+namespace {
+
 // ------------------------------------------------------------------ adjoint
 // Workspace of the tendency adjoint for S states.
 struct TendAdjWS {
@@ -1083,6 +1220,30 @@ int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, do
     hipStream_t st = S(stream);
     return step_body(fl, cl, o, dt, reinterpret_cast<const double2*>(theta_n), reinterpret_cast<double2*>(theta_np1),
                      status, w, nullptr, st);
+}
+
+size_t mlsdc_multi_workspace_bytes(const sdc_level* const* levels, int nlevels) {
+    if (!valid_levels(levels, nlevels)) return 0;
+    Carve cv{nullptr};
+    for (int l = 0; l < nlevels; ++l) carve_level(cv, levels[l], l == 0);
+    return cv.used;
+}
+
+int mlsdc_step_multi(const sdc_level* const* levels, int nlevels, int niter, const int* nsweep, double dt,
+                     const double* theta_n, double* theta_np1, void* ws, size_t wsb, shx_stream_t stream) {
+    if (!valid_levels(levels, nlevels) || !nsweep || niter < 0 || !(dt > 0.0) || !theta_n || !theta_np1 ||
+        !aligned16(theta_n) || !aligned16(theta_np1) || !aligned16(ws))
+        return SHX_EINVAL;
+    for (int l = 0; l < nlevels; ++l) {
+        if (nsweep[l] < 1) return SHX_EINVAL;
+        if (!alias_free(levels[l]->plan)) return SHX_ESHAPE;
+    }
+    if (!ws || wsb < mlsdc_multi_workspace_bytes(levels, nlevels)) return SHX_EWORKSPACE;
+    Carve cv{static_cast<char*>(ws)};
+    LevelWS w[SHX_MAX_LEVELS];
+    for (int l = 0; l < nlevels; ++l) w[l] = carve_level(cv, levels[l], l == 0);
+    return step_multi_body(levels, nlevels, niter, nsweep, dt, reinterpret_cast<const double2*>(theta_n),
+                           reinterpret_cast<double2*>(theta_np1), w, S(stream));
 }
 
 }  // extern "C"
