@@ -320,11 +320,12 @@ def large_extra(pk, torch, workload, graph):
     return extra
 
 
-# Gaussian-dome temporal refinement (Sec. 5.2): schemes as (name, fine
-# Gauss-Lobatto nodes, coarse nodes or None, iterations), one fine and one
-# coarse sweep per iteration (the paper's setting), fine T255 / coarse T127.
-DOME_SCHEMES = (("SDC(3,4)", 3, None, 4), ("MLSDC(3,2,2,1/2)", 3, 2, 2), ("SDC(5,8)", 5, None, 8),
-                ("MLSDC(5,3,4,1/2)", 5, 3, 4), ("MLSDC(5,3,7,1/2)", 5, 3, 7))
+# Gaussian-dome temporal refinement (Sec. 5.2): schemes as (name, Gauss-
+# Lobatto nodes per level from the finest, iterations), one sweep per level
+# and iteration (the paper's setting); levels T255 / T127 / T63.
+DOME_SCHEMES = (("SDC(3,4)", (3,), 4), ("MLSDC(3,2,2,1/2)", (3, 2), 2), ("SDC(5,8)", (5,), 8),
+                ("MLSDC(5,3,4,1/2)", (5, 3), 4), ("MLSDC(5,3,7,1/2)", (5, 3), 7),
+                ("3-level MLSDC(5,3,2;4)", (5, 3, 2), 4))
 DOME_DTS = (30.0, 60.0, 120.0, 240.0, 480.0, 960.0)
 DOME_REF_DT = 15.0
 
@@ -363,29 +364,28 @@ def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
     single-level counterpart at matched geopotential error (cost of the
     single-level scheme interpolated log-log in its error)."""
     par = pk.swe_params(phibar=workload.dome_phibar())
-    pf = pk.Plan(FINE["N"], FINE["J"], FINE["I"])
-    pc = pk.Plan(COARSE["N"], COARSE["J"], COARSE["I"])
+    plans = [pk.Plan(c["N"], c["J"], c["I"]) for c in (FINE, COARSE, dict(N=63, J=96, I=192))]
+    pf = plans[0]
     mu = pf.latitudes()[0]
     grid = torch.tensor(workload.dome_grid(mu, FINE["I"])[None], device="cuda")
     x0 = torch.zeros(3, workload.nspec(FINE["N"]), dtype=torch.complex128, device="cuda")
     x0[0] = pf.forward(grid)[0]
 
-    def stepper(nf, nc, k):
-        lf = pk.Level(pf, par, pk.SDC_GAUSS_LOBATTO, nf)
-        lc = pk.Level(pc, par, pk.SDC_GAUSS_LOBATTO, nc) if nc else None
-        return pk.Stepper(lf, lc, niter=k, nsweep_fine=1, nsweep_coarse=1)
+    def stepper(nodes, k):
+        lv = [pk.Level(plans[l], par, pk.SDC_GAUSS_LOBATTO, n) for l, n in enumerate(nodes)]
+        return pk.MultiStepper(lv, niter=k, nsweeps=1)
 
     def fields(x):
         return pf.inverse(x[0:2].contiguous())
 
-    ref, _ = advance(torch, stepper(5, None, 8), x0, DOME_REF_DT, int(round(t_end / DOME_REF_DT)))
+    ref, _ = advance(torch, stepper((5,), 8), x0, DOME_REF_DT, int(round(t_end / DOME_REF_DT)))
     rg = fields(ref)
     out = {"t_end_s": t_end, "reference": f"SDC(5,8), dt = {DOME_REF_DT:g} s", "dt_s": list(DOME_DTS),
            "alpha": workload.DOME["alpha"], "schemes": {}}
     out["dt_s"] = list(dts)
-    for name, nf, nc, k in DOME_SCHEMES:
+    for name, nodes, k in DOME_SCHEMES:
         errs, errz, cost = [], [], []
-        st = stepper(nf, nc, k)
+        st = stepper(nodes, k)
         for dt in dts:
             x, sps = advance(torch, st, x0, dt, int(round(t_end / dt)))
             d = fields(x) - rg
@@ -396,7 +396,8 @@ def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
                  for i in range(len(errs) - 1)]
         out["schemes"][name] = {"linf_phi": errs, "linf_zeta": errz, "order_phi": order,
                                 "gpu_seconds": cost}
-    for ml, sl in (("MLSDC(3,2,2,1/2)", "SDC(3,4)"), ("MLSDC(5,3,4,1/2)", "SDC(5,8)")):
+    for ml, sl in (("MLSDC(3,2,2,1/2)", "SDC(3,4)"), ("MLSDC(5,3,4,1/2)", "SDC(5,8)"),
+                   ("3-level MLSDC(5,3,2;4)", "SDC(5,8)")):
         m, s1 = out["schemes"][ml], out["schemes"][sl]
         pts = [(a, b) for a, b in zip(s1["linf_phi"], s1["gpu_seconds"]) if a > 0 and math.isfinite(a)]
         le = np.log(np.array([a for a, _ in pts]))
