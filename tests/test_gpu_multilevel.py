@@ -4,8 +4,9 @@ the two-level case) on the HIP path:
   * one and two levels reproduce single-level SDC and mlsdc_step bit for
     bit (the same launches);
   * three levels (T31 / T15 / T7 with 5 / 3 / 2 Gauss-Lobatto nodes, one
-    sweep per level, dt = 300 s) against the oracle's V-cycle at the parity
-    tolerance, 1e-12 normwise per field, over three iterations;
+    sweep per level, dt = 300 s) and four levels (T31 / T15 / T10 / T7,
+    1 / 2 / 1 / 2 sweeps) against the oracle's V-cycle at the parity
+    tolerance, 1e-12 normwise per field;
   * iterated to convergence, the three-level step reaches the fine
     collocation solution (the same as single-level SDC iterated to
     convergence, within 1e-11), which needs the restricted middle-level FAS
@@ -22,7 +23,7 @@ from oracle import swe as OW
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-GRIDS = {31: (48, 96), 15: (24, 48), 7: (12, 48), 63: (96, 192)}
+GRIDS = {31: (48, 96), 15: (24, 48), 10: (16, 32), 7: (12, 48), 63: (96, 192)}
 
 
 @pytest.fixture(scope="module")
@@ -72,6 +73,22 @@ def test_multi_three_levels_parity(pk):
     olv = [OS.Level(OW.SWEProblem(N, *GRIDS[N]), "lobatto", nodes) for N, nodes in spec]
     tr = [OS.spectral_transfer(31, 15), OS.spectral_transfer(15, 7)]
     ref = OS.mlsdc_step_multi(olv, 300.0, x, 3, [1, 1, 1], tr)
+    for f in range(3):
+        assert relerr(got[f], ref[f]) < TOL, f
+
+
+def test_multi_four_levels_parity(pk):
+    """The deepest V-cycle the entry point takes: T31 / T15 / T10 / T7 with
+    5 / 3 / 3 / 2 nodes and 1 / 2 / 1 / 2 sweeps per level, two iterations."""
+    print("CASE multi 4 levels T31/T15/T10/T7", flush=True)
+    spec = [(31, 5), (15, 3), (10, 3), (7, 2)]
+    ns = [1, 2, 1, 2]
+    st = pk.MultiStepper(levels(pk, spec), niter=2, nsweeps=ns)
+    x = seeded(31, 95)
+    got = st.step(300.0, x.to("cuda"))
+    olv = [OS.Level(OW.SWEProblem(N, *GRIDS[N]), "lobatto", nodes) for N, nodes in spec]
+    tr = [OS.spectral_transfer(31, 15), OS.spectral_transfer(15, 10), OS.spectral_transfer(10, 7)]
+    ref = OS.mlsdc_step_multi(olv, 300.0, x, 2, ns, tr)
     for f in range(3):
         assert relerr(got[f], ref[f]) < TOL, f
 
