@@ -358,7 +358,8 @@ def advance(torch, stepper, x0, dt, nsteps):
 
 def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
     """Temporal refinement on the Gaussian dome over t_end seconds: L_inf
-    errors of the geopotential and vorticity on the fine grid against
+    errors of the geopotential and vorticity on the fine grid (and the
+    area-weighted L2 error of the geopotential) against
     SDC(5,8) at dt = 60 s, observed orders between successive dt, seconds
     per step, and the observed speedup of each MLSDC scheme over its
     single-level counterpart at matched geopotential error (cost of the
@@ -366,7 +367,8 @@ def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
     par = pk.swe_params(phibar=workload.dome_phibar())
     plans = [pk.Plan(c["N"], c["J"], c["I"]) for c in (FINE, COARSE, dict(N=63, J=96, I=192))]
     pf = plans[0]
-    mu = pf.latitudes()[0]
+    mu, _, wq = pf.latitudes()
+    wgt = torch.tensor(wq, device="cuda")[:, None] / (2.0 * FINE["I"])   # area weights, sum 1
     grid = torch.tensor(workload.dome_grid(mu, FINE["I"])[None], device="cuda")
     x0 = torch.zeros(3, workload.nspec(FINE["N"]), dtype=torch.complex128, device="cuda")
     x0[0] = pf.forward(grid)[0]
@@ -384,33 +386,35 @@ def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
            "alpha": workload.DOME["alpha"], "schemes": {}}
     out["dt_s"] = list(dts)
     for name, nodes, k in DOME_SCHEMES:
-        errs, errz, cost = [], [], []
+        errs, errz, err2, cost = [], [], [], []
         st = stepper(nodes, k)
         for dt in dts:
             x, sps = advance(torch, st, x0, dt, int(round(t_end / dt)))
             d = fields(x) - rg
             errs.append(d[0].abs().max().item())
             errz.append(d[1].abs().max().item())
+            err2.append(math.sqrt((wgt * d[0] * d[0]).sum().item()))
             cost.append(sps * t_end / dt)
         order = [math.log2(errs[i + 1] / errs[i]) if errs[i] > 0 and errs[i + 1] > 0 else float("nan")
                  for i in range(len(errs) - 1)]
-        out["schemes"][name] = {"linf_phi": errs, "linf_zeta": errz, "order_phi": order,
+        out["schemes"][name] = {"linf_phi": errs, "linf_zeta": errz, "l2_phi": err2, "order_phi": order,
                                 "gpu_seconds": cost}
     for ml, sl in (("MLSDC(3,2,2,1/2)", "SDC(3,4)"), ("MLSDC(5,3,4,1/2)", "SDC(5,8)"),
                    ("3-level MLSDC(5,3,2;4)", "SDC(5,8)")):
         m, s1 = out["schemes"][ml], out["schemes"][sl]
-        pts = [(a, b) for a, b in zip(s1["linf_phi"], s1["gpu_seconds"]) if a > 0 and math.isfinite(a)]
-        le = np.log(np.array([a for a, _ in pts]))
-        lc = np.log(np.array([b for _, b in pts]))
-        sp = []
-        for e, c in zip(m["linf_phi"], m["gpu_seconds"]):
-            ok = len(pts) > 1 and e > 0 and le.min() <= math.log(e) <= le.max()
-            if not ok:
-                sp.append(float("nan"))
-                continue
-            o = np.argsort(le)
-            sp.append(float(np.exp(np.interp(math.log(e), le[o], lc[o])) / c))
-        m["speedup_vs_" + sl] = sp
+        for key, tag in (("linf_phi", ""), ("l2_phi", "_l2")):
+            pts = [(a, b) for a, b in zip(s1[key], s1["gpu_seconds"]) if a > 0 and math.isfinite(a)]
+            le = np.log(np.array([a for a, _ in pts]))
+            lc = np.log(np.array([b for _, b in pts]))
+            sp = []
+            for e, c in zip(m[key], m["gpu_seconds"]):
+                ok = len(pts) > 1 and e > 0 and le.min() <= math.log(e) <= le.max()
+                if not ok:
+                    sp.append(float("nan"))
+                    continue
+                o = np.argsort(le)
+                sp.append(float(np.exp(np.interp(math.log(e), le[o], lc[o])) / c))
+            m["speedup" + tag + "_vs_" + sl] = sp
     return out
 
 
