@@ -227,6 +227,73 @@ def test_rigid_rotation_closed_form(t31):
     assert fe.abs().max().item() < 1e-13 * abs(expect)
 
 
+# Closed forms of the two flux rows of F_E (Sec. 2, eqs. geopotential_equation
+# and vorticity_equation; Sec. 4.1, eq. system_of_odes_explicit_part).  Each
+# helper returns the relative deviation of `fexp` (an F_E implementation with
+# the signature of swe.f_explicit) from the closed form, so that the same
+# checks can be run against a deliberately broken copy below.
+def _flux_pin_solid_body(fexp, g):
+    """Solid-body wind zeta = 2 w mu (u = w a cos(phi), v = 0), delta = 0, any
+    band-limited Phi': the flux divergence is pure advection in longitude,
+    -div(Phi' V) = -w dPhi'/dlambda, so F_E,Phi = -i m w Phi'^m_n."""
+    N, p = g.N, swe.SWEParams()
+    w = 1.0e-5
+    gen = torch.Generator().manual_seed(21)
+    st = torch.zeros(3, sht.nspec(N), dtype=CT)
+    st[0] = 100.0 * rand_spec(N, gen)
+    st[1, 1] = 2.0 * w / math.sqrt(1.5)                  # zeta = 2 w mu
+    expect = -1j * sht.orders(N).to(DT) * w * st[0]
+    return relerr(fexp(st, g, p)[0], expect)
+
+
+def _flux_pin_constant_geopotential(fexp, g):
+    """Phi' = c P^0_0 = c/sqrt(2) (constant), any zeta and delta:
+    -div(Phi' V) = -(c/sqrt(2)) div V, so F_E,Phi = -(c/sqrt(2)) delta."""
+    N, p = g.N, swe.SWEParams()
+    c = 300.0
+    gen = torch.Generator().manual_seed(22)
+    st = torch.zeros(3, sht.nspec(N), dtype=CT)
+    st[0, 0] = c
+    st[1] = 1e-5 * rand_spec(N, gen)
+    st[2] = 1e-6 * rand_spec(N, gen)
+    expect = -(c / math.sqrt(2.0)) * st[2]
+    return relerr(fexp(st, g, p)[0], expect)
+
+
+def _flux_pin_divergent_coriolis(fexp, g):
+    """delta = D P^0_1, zeta = Phi' = 0: chi = -D a^2 sqrt(3/2) mu / 2, the
+    cos-weighted northward wind is V = -D a sqrt(3/2) (1 - mu^2)/2, and with
+    eta = 2 Omega mu, -div(eta V) = -Omega D sqrt(3/2) (3 mu^2 - 1): a single
+    (n = 2, m = 0) coefficient -2 Omega D sqrt(3/5) of F_E,zeta; F_E,Phi = 0."""
+    N, p = g.N, swe.SWEParams()
+    D = 2.0e-6
+    st = torch.zeros(3, sht.nspec(N), dtype=CT)
+    st[2, 1] = D
+    expect = torch.zeros(sht.nspec(N), dtype=CT)
+    expect[2] = -2.0 * p.omega * D * math.sqrt(0.6)
+    fe = fexp(st, g, p)
+    return max(relerr(fe[1], expect), fe[0].abs().max().item() / abs(expect[2].item()))
+
+
+FLUX_PINS = [_flux_pin_solid_body, _flux_pin_constant_geopotential, _flux_pin_divergent_coriolis]
+
+
+@pytest.mark.parametrize("pin", FLUX_PINS, ids=lambda f: f.__name__[10:])
+def test_flux_rows_closed_forms(pin, t31):
+    assert pin(swe.f_explicit, t31) < 1e-13
+
+
+@pytest.mark.parametrize("row", [0, 1])
+def test_flux_pins_detect_a_sign_error(row, t31):
+    """A planted mistake in the oracle (one flux row of F_E negated) fails at
+    least one of the closed-form pins above."""
+    def broken(st, g, p):
+        fe = swe.f_explicit(st, g, p).clone()
+        fe[..., row, :] = -fe[..., row, :]
+        return fe
+    assert max(pin(broken, t31) for pin in FLUX_PINS) > 1e-3
+
+
 def _seeded_state(N, seed, wind=1e-5, phi=100.0):
     import workload
     raw = torch.tensor(workload.raw_spectrum(N, seed))
