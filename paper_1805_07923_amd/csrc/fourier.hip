@@ -88,63 +88,65 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_fwd(const double* __restrict_
     }
 }
 
-// Tendency grid kernel: one workgroup per (latitude row j, state s).
-// FI[s]: [2][Jh][N+1][4] (zeta, Phi', U, V); G[s]: [J][N+1][5] (A, B, C, D, E),
-// weighted for the analysis: w_j / (L cos^2 phi_j) for A..D, w_j / L for E.
+// Tendency grid kernel: one workgroup of five wavefronts per (latitude row
+// j, state s).  FI[s]: [2][Jh][N+1][4] (zeta, Phi', U, V); G[s]: [J][N+1][5]
+// (A, B, C, D, E), weighted for the analysis: w_j / (L cos^2 phi_j) for A..D,
+// w_j / L for E.  Wavefront f < 4 synthesises field f along the row on its
+// own (pack and inverse FFT, no workgroup barrier) while wavefront 4 copies
+// the twiddles; after a barrier the whole workgroup forms the five products
+// in place; after another, wavefront f analyses product row f on its own
+// (forward FFT, unpack, weights) and stores it.
+constexpr int GRID_T = 320;
 template <int L>
-__global__ __launch_bounds__(Cfg<L>::T) void k_swe_grid(const double2* __restrict__ FI,
-                                                        const double2* __restrict__ tw,
-                                                        const double* __restrict__ mu,
-                                                        const double* __restrict__ cos2,
-                                                        const double* __restrict__ w,
-                                                        double2* __restrict__ G, int N, int J,
-                                                        double two_omega) {
-    constexpr int L2 = L / 2, T = Cfg<L>::T, P = padded(L2);
-    // two 5-row buffers while the footprint stays small (L <= 384), else in place
-    constexpr bool PP = (10 * P + L2) * (int)sizeof(double2) <= rowfft::PP_LDS_MAX;
-    __shared__ double2 lds[(PP ? 10 : 5) * P];
+__global__ __launch_bounds__(GRID_T) void k_swe_grid(const double2* __restrict__ FI,
+                                                     const double2* __restrict__ tw,
+                                                     const double* __restrict__ mu,
+                                                     const double* __restrict__ cos2,
+                                                     const double* __restrict__ w,
+                                                     double2* __restrict__ G, int N, int J,
+                                                     double two_omega) {
+    constexpr int L2 = L / 2, P = padded(L2);
+    __shared__ double2 lds[5 * P];
     __shared__ double2 tws[L2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j = blockIdx.x, s = blockIdx.y;
     const int Jh = J / 2;
     const int jp = (j < Jh) ? j : J - 1 - j;
     const double sgn = (j < Jh) ? 1.0 : -1.0;
-    const long long pstride = (long long)Jh * (N + 1) * 4;
-    const double2* e = FI + (long long)s * J * (N + 1) * 4 + (long long)jp * (N + 1) * 4;
-    auto coef = [&](int f, int m) {
-        const double2 a = e[(long long)m * 4 + f], b = e[(long long)m * 4 + f + pstride];
-        return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
-    };
-    double2* other = lds + (PP ? 5 * P : 0);
-    rowfft::pack_rows<L, 4>(lds, tws, tw, N, coef);
-    __syncthreads();
-    double2* x = rowfft::fft<L2, T, 4, PP>(lds, other, tws, 1.0);
-    double2* y = (x == lds) ? other : lds;
-    const double fc = two_omega * mu[j];
-    const double hk = 0.5 / cos2[j];
-    for (int k = threadIdx.x; k < L2; k += T) {
-        // (x_{2k}, x_{2k+1}) of zeta, Phi', U, V; the five products in place
-        const int q = pidx(k);
-        const double2 z = x[q], ph = x[P + q], U = x[2 * P + q], V = x[3 * P + q];
-        const double2 eta = make_double2(z.x + fc, z.y + fc);
-        x[q] = make_double2(eta.x * U.x, eta.y * U.y);
-        x[P + q] = make_double2(eta.x * V.x, eta.y * V.y);
-        x[2 * P + q] = make_double2(ph.x * U.x, ph.y * U.y);
-        x[3 * P + q] = make_double2(ph.x * V.x, ph.y * V.y);
-        x[4 * P + q] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
+    if (wv < 4) {
+        const long long pstride = (long long)Jh * (N + 1) * 4;
+        const double2* e = FI + (long long)s * J * (N + 1) * 4 + (long long)jp * (N + 1) * 4 + wv;
+        rowfft::wpack<L>(lds + wv * P, tw, N, lane, [&](int m) {
+            const double2 a = e[(long long)m * 4], b = e[(long long)m * 4 + pstride];
+            return make_double2(a.x + sgn * b.x, a.y + sgn * b.y);
+        });
+    } else {
+        for (int t = lane; t < L2; t += 64) tws[t] = tw[t];
     }
     __syncthreads();
-    const double2* r = rowfft::fft<L2, T, 5, PP>(x, y, tws, -1.0);
-    const double sv = w[j] / (L * cos2[j]);
-    const double se = w[j] / L;
-    double2* out = G + ((long long)s * J + j) * (N + 1) * 5;
-    for (int m = threadIdx.x; m <= N; m += T) {
-        double2* o = out + (long long)m * 5;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            const double2 X = rowfft::unpack<L>(r + f * P, tws, m);
-            const double sc = (f < 4) ? sv : se;
-            o[f] = make_double2(sc * X.x, sc * X.y);
-        }
+    if (wv < 4) rowfft::wfft<L2>(lds + wv * P, tws, 1.0, lane);
+    __syncthreads();
+    const double fc = two_omega * mu[j];
+    const double hk = 0.5 / cos2[j];
+    for (int k = threadIdx.x; k < L2; k += GRID_T) {
+        // (x_{2k}, x_{2k+1}) of zeta, Phi', U, V; the five products in place
+        const int q = pidx(k);
+        const double2 z = lds[q], ph = lds[P + q], U = lds[2 * P + q], V = lds[3 * P + q];
+        const double2 eta = make_double2(z.x + fc, z.y + fc);
+        lds[q] = make_double2(eta.x * U.x, eta.y * U.y);
+        lds[P + q] = make_double2(eta.x * V.x, eta.y * V.y);
+        lds[2 * P + q] = make_double2(ph.x * U.x, ph.y * U.y);
+        lds[3 * P + q] = make_double2(ph.x * V.x, ph.y * V.y);
+        lds[4 * P + q] = make_double2((U.x * U.x + V.x * V.x) * hk, (U.y * U.y + V.y * V.y) * hk);
+    }
+    __syncthreads();
+    double2* row = lds + wv * P;
+    rowfft::wfft<L2>(row, tws, -1.0, lane);
+    const double sc = (wv < 4) ? w[j] / (L * cos2[j]) : w[j] / L;
+    double2* out = G + ((long long)s * J + j) * (N + 1) * 5 + wv;
+    for (int m = lane; m <= N; m += 64) {
+        const double2 X = rowfft::unpack<L>(row, tws, m);
+        out[(long long)m * 5] = make_double2(sc * X.x, sc * X.y);
     }
 }
 
@@ -163,7 +165,7 @@ hipError_t fwd_t(const shx_plan* pl, const double* grid, double2* G, int F, int 
 template <int L>
 hipError_t swe_t(const shx_plan* pl, const double2* FI, double2* G, int S, double omega, hipStream_t st) {
     dim3 g(pl->J, S);
-    k_swe_grid<L><<<g, Cfg<L>::T, 0, st>>>(FI, pl->tw, pl->mu, pl->cos2, pl->w, G, pl->N, pl->J,
+    k_swe_grid<L><<<g, GRID_T, 0, st>>>(FI, pl->tw, pl->mu, pl->cos2, pl->w, G, pl->N, pl->J,
                                                2.0 * omega);
     return hipGetLastError();
 }

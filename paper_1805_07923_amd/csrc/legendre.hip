@@ -173,11 +173,13 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
 // staged rows are the tendency's grid fields (swe_prep_row; NF = F = 4);
 // STAGE = 2: cin holds F_E cotangents [S][3][nspec] and the staged rows are
 // the cotangents of the five weighted analyses (swe_combine_adj_row;
-// NF = F = 5).  The coefficient rows
-// and the recurrence coefficients of the round's 4 L degrees are staged in
-// LDS; each lane reads those of its next eight degrees in one batch
-// (clamped to the staged rows: degrees past nmax_use enter with P = 0)
-// before it advances through them.
+// NF = F = 5).  The coefficient rows and the recurrence coefficients of the
+// round's 4 L degrees are staged in LDS, segment by segment, each segment
+// padded by 32 bytes so that the four segments' reads of one step fall on
+// different banks; rows past nmax_use are staged as zeros and recurrence
+// coefficients past the table as zeros (P then continues as 0), so every
+// lane reads its next eight degrees at fixed offsets from one address, with
+// no clamping and no per-degree selection.
 template <int NF, int STAGE = 0>
 __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ ck,
                                                    const long long* __restrict__ ckoff,
@@ -187,10 +189,10 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
                                                    double2* __restrict__ out, int N, int nmax_tab,
                                                    int nmax_use, int Jh, int F, int f0, int S,
                                                    long long cin_stride, long long out_stride, int gx,
-                                                   long long nspec, double a) {
+                                                   long long nspec, double a, int Lmax) {
     static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
     constexpr int U = 8;                                // degrees per batch of LDS reads
-    extern __shared__ double2 csh[];                    // [4L][NF] rows of the round, then [4L] rc
+    extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, q = lane >> 4;
     const int ic = i < 2 * NF ? i : 2 * NF - 1;         // B column (clamped; columns >= 2 NF unused)
@@ -201,67 +203,68 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
     const bool active = jp < Jh;
     const int Kt = nmax_tab - m + 1, Ku = nmax_use - m + 1;
     const int R = seg_rounds(Kt), L = seg_len(Kt);
+    const int SC = L * NF + 2, SR = L + 2;              // padded segment strides (double2)
     const double x = mu[active ? jp : 0];
     const double2* ckm = ck + ckoff[m] + (active ? jp : 0);
-    double2* rsh = csh + 4 * L * NF;
-    const double* cd = reinterpret_cast<const double*>(csh);
+    double2* rsh = csh + 4 * (Lmax * NF + 2);
+    const double* cq = reinterpret_cast<const double*>(csh + q * SC) + ic;   // segment q, column ic
+    const double2* rq = rsh + q * SR;
     const double2* rcm = rc + ext_idx(N, m, m);
     for (int s = 0; s < S; ++s) {
         v4d accE = {0.0, 0.0, 0.0, 0.0}, accO = {0.0, 0.0, 0.0, 0.0};
         for (int r = 0; r < R; ++r) {
             const int kr0 = 4 * r * L;
             if (kr0 >= Ku) break;                       // uniform
-            const int kc1 = min(kr0 + 4 * L, Ku), kt1 = min(kr0 + 4 * L, Kt);
             const int g = 4 * r + q;
             const double2 c0 = ckm[(long long)g * Jh];  // in flight during the staging
             __syncthreads();                            // previous readers of the rows are done
-            if constexpr (STAGE == 1) {
-                static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
-                for (int kk = kr0 + threadIdx.x; kk < kc1; kk += 256) {
-                    double2 o[4];
-                    swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
+            for (int kl = threadIdx.x; kl < 4 * L; kl += 256) {
+                const int qs = kl / L, ts = kl - qs * L, kk = kr0 + kl;
+                double2* row = csh + qs * SC + ts * NF;
+                if (kk < Ku) {
+                    if constexpr (STAGE == 1) {
+                        static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
+                        double2 o[4];
+                        swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) csh[(kk - kr0) * 4 + f] = o[f];
-                }
-            } else if constexpr (STAGE == 2) {
-                static_assert(STAGE != 2 || NF == 5, "the tendency adjoint synthesises five fields");
-                for (int kk = kr0 + threadIdx.x; kk < kc1; kk += 256) {
-                    double2 o[5];
-                    swe_combine_adj_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
+                        for (int f = 0; f < 4; ++f) row[f] = o[f];
+                    } else if constexpr (STAGE == 2) {
+                        static_assert(STAGE != 2 || NF == 5, "the tendency adjoint synthesises five fields");
+                        double2 o[5];
+                        swe_combine_adj_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
 #pragma unroll
-                    for (int f = 0; f < 5; ++f) csh[(kk - kr0) * 5 + f] = o[f];
+                        for (int f = 0; f < 5; ++f) row[f] = o[f];
+                    } else {
+                        const double2* cg = cin + s * cin_stride + (ext_idx(N, m, m) + kk) * F + f0;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) row[f] = cg[f];
+                    }
+                } else {
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) row[f] = make_double2(0.0, 0.0);
                 }
-            } else {
-                const double2* cg = cin + s * cin_stride + (ext_idx(N, m, m) + kr0) * F + f0;
-                for (int t = threadIdx.x; t < (kc1 - kr0) * NF; t += 256) {
-                    const int kk = t / NF, f = t - kk * NF;
-                    csh[t] = cg[(long long)kk * F + f];
-                }
+                rsh[qs * SR + ts] = (kk < Kt) ? rcm[kk] : make_double2(0.0, 0.0);
             }
-            for (int kk = threadIdx.x; kk < kt1 - kr0; kk += 256) rsh[kk] = rcm[kr0 + kk];
             __syncthreads();
             if (jw >= Jh) continue;                     // uniform: no latitudes for this wavefront
-            const int k0 = g * L;
-            double pe = c0.x, po = c0.y;                // P_{m+k0}, P_{m+k0+1}
+            double pe = c0.x, po = c0.y;                // P_{m+gL}, P_{m+gL+1}
             for (int t = 0; t < L; t += U) {
                 double2 rr[U];
                 double bb[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int k = k0 + t + u;
-                    rr[u] = rsh[min(k, kt1 - 1) - kr0];
-                    bb[u] = cd[(min(k, kc1 - 1) - kr0) * 2 * NF + ic];
+                    rr[u] = rq[t + u];
+                    bb[u] = cq[(t + u) * 2 * NF];
                 }
 #pragma unroll
                 for (int u = 0; u < U; u += 2) {
-                    const int ke = k0 + t + u;
                     if (u > 0 || t > 0) {
                         const double ne = fma(rr[u].x * x, po, -(rr[u].y * pe));
                         po = fma(rr[u + 1].x * x, ne, -(rr[u + 1].y * po));
                         pe = ne;
                     }
-                    accE = __builtin_amdgcn_mfma_f64_16x16x4f64(ke < Ku ? pe : 0.0, bb[u], accE, 0, 0, 0);
-                    accO = __builtin_amdgcn_mfma_f64_16x16x4f64(ke + 1 < Ku ? po : 0.0, bb[u + 1], accO, 0, 0, 0);
+                    accE = __builtin_amdgcn_mfma_f64_16x16x4f64(pe, bb[u], accE, 0, 0, 0);
+                    accO = __builtin_amdgcn_mfma_f64_16x16x4f64(po, bb[u + 1], accO, 0, 0, 0);
                 }
             }
         }
@@ -516,10 +519,11 @@ void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, 
     const int gx = (pl->Jh + 63) / 64;
     int Lmax = 0;                                       // longest segment over the orders
     for (int m = 0; m <= pl->N; ++m) Lmax = seg_len(pl->nmax - m + 1) > Lmax ? seg_len(pl->nmax - m + 1) : Lmax;
-    const size_t lds = (size_t)4 * Lmax * (NF + 1) * sizeof(double2);
+    const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2);
     k_leg_syn_m<NF, STAGE><<<gx * (pl->N + 1), 256, lds, st>>>(pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N,
                                                               pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride,
-                                                              (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a);
+                                                              (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a,
+                                                              Lmax);
 }
 
 template <int NF>

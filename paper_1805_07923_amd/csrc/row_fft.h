@@ -317,4 +317,109 @@ __device__ __forceinline__ double2 unpack(const double2* row, const double2* tws
     return make_double2(E.x + wo.x, E.y + wo.y);
 }
 
+// ------------------------------------------------ one row per wavefront
+// The same transforms with one wavefront owning one row: the stages of a row
+// then need no workgroup barrier, only the wavefront's own LDS accesses in
+// program order (a wavefront's LDS instructions are executed in the order
+// issued; the fence keeps the compiler from moving a store of one lane's
+// butterfly above a load of another lane's, which it could otherwise do
+// where it proves that one lane's own addresses do not overlap).
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// One Stockham stage of a row of C complex values (padded), in place, by the
+// 64 lanes of one wavefront; Ns as in stage().
+template <int C, int Ns>
+__device__ __forceinline__ void wstage(double2* row, const double2* tws, double sg, int lane) {
+    constexpr int R = next_radix(C / Ns);
+    constexpr int NB = C / R;
+    constexpr int IPT = (NB + 63) / 64;
+    constexpr int TWS = C / (Ns * R) * 2;
+    double2 v[IPT][R];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int j = lane + it * 64, k = j % Ns;
+        if (NB % 64 == 0 || j < NB) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = row[pidx(j + r * NB)];
+                if (Ns > 1 && r > 0) {
+                    double2 w = tw_half(tws, r * k * TWS, C);
+                    w.y *= -sg;
+                    x = cmul(x, w);
+                }
+                v[it][r] = x;
+            }
+            dft<R>(v[it], sg);
+        }
+    }
+    wave_fence();
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int j = lane + it * 64, k = j % Ns;
+        if (NB % 64 == 0 || j < NB) {
+            const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) row[pidx(base + q * Ns)] = v[it][q];
+        }
+    }
+    wave_fence();
+}
+
+// All stages of one row, in place, by one wavefront.
+template <int C, int Ns = 1>
+__device__ __forceinline__ void wfft(double2* row, const double2* tws, double sg, int lane) {
+    if constexpr (C / Ns > 1) {
+        wstage<C, Ns>(row, tws, sg, lane);
+        wfft<C, Ns * next_radix(C / Ns)>(row, tws, sg, lane);
+    }
+}
+
+// Synthesis input of one real row by one wavefront (pack_rows for a single
+// row): lane l owns the index pairs (m, L2 - m), m = l, l + 64, ... < L2/2.
+// coef(m) gives X_m (called for m <= N only); twg is the global twiddle table.
+// Every load of the lane is issued before the first is used.
+template <int L, class Coef>
+__device__ __forceinline__ void wpack(double2* row, const double2* __restrict__ twg, int N, int lane, Coef coef) {
+    constexpr int L2 = L / 2, H = L2 / 2;
+    constexpr int IP = (H + 63) / 64;
+    double2 xa[IP], xb[IP], tm[IP];
+#pragma unroll
+    for (int ip = 0; ip < IP; ++ip) {
+        const int m = lane + ip * 64;
+        const int j = (m == 0) ? H : L2 - m;
+        const bool on = m < H;
+        const bool ina = on && m <= N, inb = on && j <= N;
+        const double2 va = coef(ina ? m : 0), vb = coef(inb ? j : 0);
+        tm[ip] = twg[on ? m : 0];
+        xa[ip] = ina ? va : make_double2(0.0, 0.0);
+        xb[ip] = inb ? vb : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int ip = 0; ip < IP; ++ip) {
+        const int m = lane + ip * 64, j = L2 - m;
+        if (m >= H) continue;
+        const double2 A = xa[ip], B = xb[ip];
+        if (m == 0) {
+            row[0] = make_double2(A.x, A.x);                    // Z_0 = X_0 + i X_0, X_0 real
+            row[pidx(H)] = make_double2(2.0 * B.x, -2.0 * B.y);
+            continue;
+        }
+        const double2 em = make_double2(tm[ip].x, -tm[ip].y);  // e^{+2 pi i m / L}
+        const double2 ej = make_double2(-tm[ip].x, -tm[ip].y); // e^{+2 pi i j / L}
+        {
+            const double2 s = make_double2(A.x + B.x, A.y - B.y);
+            const double2 d = make_double2(A.x - B.x, A.y + B.y);
+            const double2 ed = cmul(em, d);
+            row[pidx(m)] = make_double2(s.x - ed.y, s.y + ed.x);
+        }
+        {
+            const double2 s = make_double2(B.x + A.x, B.y - A.y);
+            const double2 d = make_double2(B.x - A.x, B.y + A.y);
+            const double2 ed = cmul(ej, d);
+            row[pidx(j)] = make_double2(s.x - ed.y, s.y + ed.x);
+        }
+    }
+    wave_fence();
+}
+
 }  // namespace rowfft
