@@ -39,7 +39,11 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->ck);
     (void)hipFree(p->ckoff);
     (void)hipFree(p->rc);
+    (void)hipFree(p->pf);
+    (void)hipFree(p->ninv);
+    (void)hipFree(p->nn1);
     (void)hipFree(p->anblk);
+    (void)hipFree(p->tblk);
     (void)hipFree(p->ord);
     (void)hipFree(p->deg);
     (void)hipFree(p->ord_e);
@@ -756,6 +760,35 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
                 anblk[2 * (8 * t + x) + 1] = xl[x][2 * t + 1];
             }
     p->an_nblk = (int)(8 * nslot);
+    // table-analysis blocks: per XCD x the (m, p, tile) of the orders m = x mod 8
+    std::vector<std::vector<int>> tl(8);
+    for (int m = 0; m <= N; ++m)
+        for (int q = 0; q < 2; ++q)
+            for (int t = 0; t * 64 < kcount(p->nmax, m, q); ++t) {
+                tl[m % 8].push_back(2 * m + q);
+                tl[m % 8].push_back(t);
+            }
+    size_t tslot = 0;
+    for (auto& v : tl) tslot = v.size() / 2 > tslot ? v.size() / 2 : tslot;
+    std::vector<int> tblk(16 * tslot, -1);
+    for (size_t t = 0; t < tslot; ++t)
+        for (int x = 0; x < 8; ++x)
+            if (2 * t < tl[x].size()) {
+                tblk[2 * (8 * t + x)] = tl[x][2 * t];
+                tblk[2 * (8 * t + x) + 1] = tl[x][2 * t + 1];
+            }
+    p->tb_nblk = (int)(8 * tslot);
+    // degree factors of the tendency rows (eps_nm as on the device: correctly
+    // rounded FP64 sqrt and division)
+    std::vector<double2> pf(p->nspec_e);
+    std::vector<double> ninv(N + 3), nn1(N + 3);
+    for (int m = 0; m <= N; ++m)
+        for (int n = m; n <= N + 1; ++n)
+            pf[ext_idx(N, m, n)] = make_double2((n - 1.0) * eps_nm(n, m), (n + 2.0) * eps_nm(n + 1, m));
+    for (int n = 0; n <= N + 2; ++n) {
+        nn1[n] = n * (n + 1.0);
+        ninv[n] = n > 0 ? -1.0 / nn1[n] : 0.0;
+    }
     std::vector<int> ord(p->nspec), deg(p->nspec), orde(p->nspec_e), dege(p->nspec_e);
     for (int m = 0; m <= N; ++m) {
         for (int n = m; n <= N; ++n) {
@@ -774,8 +807,15 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
               dalloc(&p->ord, p->nspec) == hipSuccess && dalloc(&p->deg, p->nspec) == hipSuccess &&
               dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess &&
               dalloc(&p->ck, ck_elems) == hipSuccess && dalloc(&p->ckoff, N + 1) == hipSuccess &&
-              dalloc(&p->rc, p->nspec_e) == hipSuccess && dalloc(&p->anblk, anblk.size()) == hipSuccess;
+              dalloc(&p->rc, p->nspec_e) == hipSuccess && dalloc(&p->anblk, anblk.size()) == hipSuccess &&
+              dalloc(&p->pf, p->nspec_e) == hipSuccess && dalloc(&p->ninv, N + 3) == hipSuccess &&
+              dalloc(&p->nn1, N + 3) == hipSuccess;
+    ok = ok && hipMemcpy(p->pf, pf.data(), pf.size() * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->ninv, ninv.data(), (N + 3) * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(p->nn1, nn1.data(), (N + 3) * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->anblk, anblk.data(), anblk.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && dalloc(&p->tblk, tblk.size()) == hipSuccess &&
+         hipMemcpy(p->tblk, tblk.data(), tblk.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->ckoff, ckoff.data(), (N + 1) * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(p->ck, 0, ck_elems * sizeof(double2)) == hipSuccess;
     ok = ok && hipMemcpy(p->mu, p->h_mu.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;

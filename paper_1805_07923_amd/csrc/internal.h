@@ -33,6 +33,12 @@ __host__ __device__ inline double eps_nm(int n, int m) {
 }
 
 // ------------------------------------------------ tendency input rows
+// Degree factors of the rows below, tabulated per plan so that the rows are
+// formed with loads and a few multiplications (no FP64 division or square
+// root, which would wait behind the matrix-core products of the wavefronts
+// sharing the SIMD): pf[ext(m, n)] = ((n-1) eps^m_n, (n+2) eps^m_{n+1}),
+// ninv[n] = -1 / (n (n+1)) (0 at n = 0), nn1[n] = n (n+1), n <= N+2.
+//
 // The four grid fields of the shallow-water tendency at (m, n), n <= N+1,
 // from a state (Phi', zeta, delta), each [nspec]: zeta, Phi' (zero above N)
 // and the cos-weighted wind (U, V) = (u, v) cos(phi) from the stream
@@ -40,29 +46,35 @@ __host__ __device__ inline double eps_nm(int n, int m) {
 // (L_n = n (n+1) / a^2, zero at n = 0):
 //   U_n = [(n-1) eps_n psi_{n-1} - (n+2) eps_{n+1} psi_{n+1} + i m chi_n] / a,
 //   V_n = [i m psi_n - (n-1) eps_n chi_{n-1} + (n+2) eps_{n+1} chi_{n+1}] / a.
-__device__ inline void swe_prep_row(const double2* __restrict__ state, long long nspec, int N, double a, int m,
-                                    int n, double2 o[4]) {
+// pfm = pf + ext(m, m); a2 = a^2, ia = 1/a.
+__device__ inline void swe_prep_row(const double2* __restrict__ state, long long nspec, int N, double a2,
+                                    double ia, const double2* __restrict__ pfm, const double* __restrict__ ninv,
+                                    int m, int n, double2 o[4]) {
     const double2* phi = state;
     const double2* zeta = state + nspec;
     const double2* delta = zeta + nspec;
-    const double a2 = a * a;
-    // -1/L_nn (zero outside the stored degrees and at nn = 0), one division per degree
-    auto neg_inv_l = [&](int nn) { return (nn < m || nn > N || nn < 1) ? 0.0 : -a2 / (nn * (nn + 1.0)); };
-    auto get = [&](const double2* x, int nn, double r) -> double2 {
-        if (r == 0.0) return make_double2(0.0, 0.0);
-        const double2 v = x[spec_idx(N, m, nn)];
-        return make_double2(r * v.x, r * v.y);
-    };
-    const double rd = neg_inv_l(n - 1), r0 = neg_inv_l(n), ru = neg_inv_l(n + 1);
-    const double c_dn = (n - 1.0) * eps_nm(n, m);
-    const double c_up = (n + 2.0) * eps_nm(n + 1, m);
-    const double2 psd = get(zeta, n - 1, rd), ps0 = get(zeta, n, r0), psu = get(zeta, n + 1, ru);
-    const double2 chd = get(delta, n - 1, rd), ch0 = get(delta, n, r0), chu = get(delta, n + 1, ru);
-    const double ia = 1.0 / a;
+    // every load is issued before the first is used: indices outside m..N
+    // are clamped to a stored entry of the order and their factor is zero
+    auto at = [&](int nn) { return spec_idx(N, m, nn < m ? m : (nn > N ? N : nn)); };
+    const long long id = at(n - 1), i0 = at(n), iu = at(n + 1);
+    const double2 zd = zeta[id], z0 = zeta[i0], zu = zeta[iu];
+    const double2 dd = delta[id], d0 = delta[i0], du = delta[iu];
+    const double2 p0 = phi[i0];
+    const double2 cf = pfm[n - m];
+    const double nd = ninv[n > 0 ? n - 1 : 0], n0 = ninv[n], nu = ninv[n + 1];
+    // -1/L_nn (zero outside the stored degrees and at nn = 0)
+    const double rd = (n - 1 < m || n - 1 > N) ? 0.0 : a2 * nd;
+    const double r0 = (n > N) ? 0.0 : a2 * n0;
+    const double ru = (n + 1 > N) ? 0.0 : a2 * nu;
+    const double c_dn = cf.x, c_up = cf.y;
+    auto sc = [](double r, double2 v) { return make_double2(r * v.x, r * v.y); };
+    const double2 psd = sc(rd, zd), ps0 = sc(r0, z0), psu = sc(ru, zu);
+    const double2 chd = sc(rd, dd), ch0 = sc(r0, d0), chu = sc(ru, du);
     const double2 U = make_double2(c_dn * psd.x - c_up * psu.x - m * ch0.y, c_dn * psd.y - c_up * psu.y + m * ch0.x);
     const double2 V = make_double2(-m * ps0.y - c_dn * chd.x + c_up * chu.x, m * ps0.x - c_dn * chd.y + c_up * chu.y);
-    o[0] = (n <= N) ? zeta[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
-    o[1] = (n <= N) ? phi[spec_idx(N, m, n)] : make_double2(0.0, 0.0);
+    const bool in = n <= N;
+    o[0] = in ? z0 : make_double2(0.0, 0.0);
+    o[1] = in ? p0 : make_double2(0.0, 0.0);
     o[2] = make_double2(ia * U.x, ia * U.y);
     o[3] = make_double2(ia * V.x, ia * V.y);
 }
@@ -75,22 +87,32 @@ __device__ inline void swe_prep_row(const double2* __restrict__ state, long long
 // X_n += -i m q_n / a, Y_n += [(n-1) eps_n q_{n-1} - (n+2) eps_{n+1} q_{n+1}] / a;
 // with the cotangent r of curl(X, Y): Y_n += -i m r_n / a,
 // X_n += [-(n-1) eps_n r_{n-1} + (n+2) eps_{n+1} r_{n+1}] / a.
-__device__ inline void swe_combine_adj_row(const double2* __restrict__ lfe, long long nspec, int N, double a, int m,
-                                           int n, double2 o[5]) {
+// pfm, nn1 as for swe_prep_row; ia = 1/a, ia2 = 1/a^2.
+__device__ inline void swe_combine_adj_row(const double2* __restrict__ lfe, long long nspec, int N, double ia,
+                                           double ia2, const double2* __restrict__ pfm,
+                                           const double* __restrict__ nn1, int m, int n, double2 o[5]) {
     const double2* lp = lfe;
     const double2* lz = lp + nspec;
     const double2* ld = lz + nspec;
-    auto get = [&](const double2* x, int k) {
-        return (k >= m && k <= N) ? x[spec_idx(N, m, k)] : make_double2(0.0, 0.0);
-    };
+    // every load is issued before the first is used: indices outside m..N
+    // are clamped to a stored entry of the order and masked afterwards
+    auto at = [&](int k) { return spec_idx(N, m, k < m ? m : (k > N ? N : k)); };
+    const long long id = at(n - 1), i0 = at(n), iu = at(n + 1);
+    const double2 vz0 = lz[i0], vzd = lz[id], vzu = lz[iu];
+    const double2 vp0 = lp[i0], vpd = lp[id], vpu = lp[iu];
+    const double2 vd0 = ld[i0], vdd = ld[id], vdu = ld[iu];
+    const double2 cf = pfm[n - m];
+    const double nn = nn1[n];
+    const bool k0 = n >= m && n <= N, kd = n - 1 >= m && n - 1 <= N, ku = n + 1 >= m && n + 1 <= N;
+    auto msk = [](bool b, double2 v) { return b ? v : make_double2(0.0, 0.0); };
     auto neg = [](double2 v) { return make_double2(-v.x, -v.y); };
     auto cim = [](double mu, double2 v) { return make_double2(-mu * v.y, mu * v.x); };   // i mu v
     auto axpy = [](double s, double2 x, double2 y) { return make_double2(fma(s, x.x, y.x), fma(s, x.y, y.y)); };
-    const double cdn = (n - 1.0) * eps_nm(n, m), cup = (n + 2.0) * eps_nm(n + 1, m);
+    const double cdn = cf.x, cup = cf.y;
     // q_AB = -lz, q_CD = -lp, r_AB = ld
-    const double2 qab0 = neg(get(lz, n)), qabd = neg(get(lz, n - 1)), qabu = neg(get(lz, n + 1));
-    const double2 qcd0 = neg(get(lp, n)), qcdd = neg(get(lp, n - 1)), qcdu = neg(get(lp, n + 1));
-    const double2 r0 = get(ld, n), rd = get(ld, n - 1), ru = get(ld, n + 1);
+    const double2 qab0 = neg(msk(k0, vz0)), qabd = neg(msk(kd, vzd)), qabu = neg(msk(ku, vzu));
+    const double2 qcd0 = neg(msk(k0, vp0)), qcdd = neg(msk(kd, vpd)), qcdu = neg(msk(ku, vpu));
+    const double2 r0 = msk(k0, vd0), rd = msk(kd, vdd), ru = msk(ku, vdu);
     double2 A = cim(-m, qab0);
     A = axpy(-cdn, rd, A);
     A = axpy(cup, ru, A);
@@ -101,9 +123,8 @@ __device__ inline void swe_combine_adj_row(const double2* __restrict__ lfe, long
     double2 D = make_double2(0.0, 0.0);
     D = axpy(cdn, qcdd, D);
     D = axpy(-cup, qcdu, D);
-    const double L = n * (n + 1.0) / (a * a);
+    const double L = nn * ia2;
     const double2 E = (n <= N) ? make_double2(L * r0.x, L * r0.y) : make_double2(0.0, 0.0);
-    const double ia = 1.0 / a;
     const double hm = (m == 0) ? ia : 0.5 * ia;          // 1/a and the halving for m >= 1
     const double he = (m == 0) ? 1.0 : 0.5;
     o[0] = make_double2(hm * A.x, hm * A.y);
@@ -174,11 +195,19 @@ struct shx_plan {
     double2* ck = nullptr;
     long long* ckoff = nullptr;     // device [N+1]
     double2* rc = nullptr;          // device [nspec_e]
+    double2* pf = nullptr;          // device [nspec_e], degree factors of swe_prep_row
+    double* ninv = nullptr;         // device [N+3], -1/(n(n+1)), 0 at n = 0
+    double* nn1 = nullptr;          // device [N+3], n(n+1)
     // Blocks of the FP64 analysis, (m, segment g) pairs [2 an_nblk]: all
     // blocks of an order on one XCD (block b runs on XCD b mod 8), (-1, -1)
     // for padding.
     int* anblk = nullptr;
     int an_nblk = 0;
+    // Blocks of the table analysis, (2 m + p, degree tile) pairs [2 tb_nblk]
+    // for the tiles of 64 degrees that hold rows (n <= N+1), listed XCD by XCD
+    // as anblk, (-1, -1) for padding.
+    int* tblk = nullptr;
+    int tb_nblk = 0;
     int* ord = nullptr;             // device [nspec] zonal order of each entry
     int* deg = nullptr;             // device [nspec] degree of each entry
     int* ord_e = nullptr;           // device [nspec_e]

@@ -189,7 +189,10 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
                                                    double2* __restrict__ out, int N, int nmax_tab,
                                                    int nmax_use, int Jh, int F, int f0, int S,
                                                    long long cin_stride, long long out_stride, int gx,
-                                                   long long nspec, double a, int Lmax) {
+                                                   long long nspec, double a, int Lmax,
+                                                   const double2* __restrict__ pf,
+                                                   const double* __restrict__ ninv,
+                                                   const double* __restrict__ nn1) {
     static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
     constexpr int U = 8;                                // degrees per batch of LDS reads
     extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc
@@ -210,6 +213,8 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
     const double* cq = reinterpret_cast<const double*>(csh + q * SC) + ic;   // segment q, column ic
     const double2* rq = rsh + q * SR;
     const double2* rcm = rc + ext_idx(N, m, m);
+    const double2* pfm = pf + ext_idx(N, m, m);
+    const double ia = 1.0 / a, a2 = a * a, ia2 = ia * ia;
     for (int s = 0; s < S; ++s) {
         v4d accE = {0.0, 0.0, 0.0, 0.0}, accO = {0.0, 0.0, 0.0, 0.0};
         for (int r = 0; r < R; ++r) {
@@ -225,13 +230,13 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
                     if constexpr (STAGE == 1) {
                         static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
                         double2 o[4];
-                        swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
+                        swe_prep_row(cin + s * cin_stride, nspec, N, a2, ia, pfm, ninv, m, m + kk, o);
 #pragma unroll
                         for (int f = 0; f < 4; ++f) row[f] = o[f];
                     } else if constexpr (STAGE == 2) {
                         static_assert(STAGE != 2 || NF == 5, "the tendency adjoint synthesises five fields");
                         double2 o[5];
-                        swe_combine_adj_row(cin + s * cin_stride, nspec, N, a, m, m + kk, o);
+                        swe_combine_adj_row(cin + s * cin_stride, nspec, N, ia, ia2, pfm, nn1, m, m + kk, o);
 #pragma unroll
                         for (int f = 0; f < 5; ++f) row[f] = o[f];
                     } else {
@@ -419,26 +424,28 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
 // Analysis from the table (up to AN_JC latitude pairs and 6 fields, where
 // streaming the FP64 table measured faster than k_leg_an_m):
 // cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
-// gx (N+1) 2 blocks (gx = ceil(K/64), numbered by leg_tile), 256 threads: lane = degree row k, the four
+// one block per (m, p, 64-degree tile holding rows) from the plan's list
+// (the blocks of an order on one XCD), 256 threads: lane = degree row k, the four
 // wavefronts split the latitude sum into quarters.  The combined Fourier
 // data g_jp = G_north +/- G_south of this (m, p) is staged in LDS per state
 // (dynamic LDS: Jh * NF double2) and read by broadcast; the partial sums of
 // waves 1..3 are added by wave 0 through LDS.
 template <int NF>
-__global__ __launch_bounds__(256) void k_leg_an(const double* __restrict__ pan,
+__global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, const double* __restrict__ pan,
                                                 const long long* __restrict__ off,
                                                 const double2* __restrict__ G,
                                                 double2* __restrict__ cout, int N, int nmax_tab,
                                                 int nmax_use, int J, int F, int f0, int S,
-                                                long long G_stride, long long cout_stride, int gx) {
+                                                long long G_stride, long long cout_stride) {
     extern __shared__ double2 gsh[];                    // [Jh][NF]
     __shared__ double red[3][2 * NF][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const LegTile tile = leg_tile(gx, N + 1);
-    const int k = tile.x * 64 + lane;
-    const int m = tile.m, p = tile.p;
+    const int mp = tblk[2 * blockIdx.x], tx = tblk[2 * blockIdx.x + 1];
+    if (mp < 0) return;                                 // padding block (uniform)
+    const int m = mp >> 1, p = mp & 1;
+    const int k = tx * 64 + lane;
     const int K = kcount(nmax_use, m, p);
-    if (tile.x * 64 >= K) return;                       // whole block idle (uniform)
+    if (tx * 64 >= K) return;                           // whole block idle (uniform)
     const bool active = k < K;
     const int Ktab = kcount(nmax_tab, m, p);
     {
@@ -523,7 +530,7 @@ void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, 
     k_leg_syn_m<NF, STAGE><<<gx * (pl->N + 1), 256, lds, st>>>(pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N,
                                                               pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride,
                                                               (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a,
-                                                              Lmax);
+                                                              Lmax, pl->pf, pl->ninv, pl->nn1);
 }
 
 template <int NF>
@@ -536,11 +543,10 @@ template <int NF>
 void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
               hipStream_t st) {
     if (NF <= 6 && pl->Jh <= AN_JC) {
-        const int gx = (kcount(nmax_use, 0, 0) + 63) / 64;
         const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
-        k_leg_an<NF><<<gx * (pl->N + 1) * 2, 256, lds, st>>>(pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
-                                                            pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
-                                                            pl->nspec_e * F, gx);
+        k_leg_an<NF><<<pl->tb_nblk, 256, lds, st>>>(pl->tblk, pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
+                                                   pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
+                                                   pl->nspec_e * F);
         return;
     }
     const int ngrp = (pl->Jh + 63) / 64;

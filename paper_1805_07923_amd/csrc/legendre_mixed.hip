@@ -260,7 +260,9 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
                                                     const double2* __restrict__ cin, double2* __restrict__ out,
                                                     int N, int nmax_tab, int nmax_use, int Jh, int F, int f0,
                                                     int NF, int S, long long cin_stride, long long out_stride,
-                                                    int gx, long long nspec, double a) {
+                                                    int gx, long long nspec, double a,
+                                                    const double2* __restrict__ pf,
+                                                    const double* __restrict__ ninv) {
     constexpr int NP = (MODE == 1) ? 1 : MODE;
     constexpr int CW = 16 * NCT;
     extern __shared__ unsigned char smem[];
@@ -294,7 +296,9 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
             for (int k = threadIdx.x; k < KL; k += 256) {
                 double2 o[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
                                 make_double2(0.0, 0.0)};
-                if (k < K) swe_prep_row(cin + s * cin_stride, nspec, N, a, m, m + p + 2 * k, o);
+                if (k < K)
+                    swe_prep_row(cin + s * cin_stride, nspec, N, a * a, 1.0 / a, pf + ext_idx(N, m, m), ninv, m,
+                                 m + p + 2 * k, o);
 #pragma unroll
                 for (int cc = 0; cc < CW; ++cc) {
                     const double2 x = o[(cc / 2) & 3];
@@ -433,7 +437,8 @@ void syn_mx(const shx_plan* pl, const double2* cin, double2* out, int F, int f0,
     const void* tab = (MODE == 1) ? (const void*)pl->psyn32 : (const void*)pl->syn16;
     k_leg_syn_mx<MODE, NCT, PREP><<<grid, 256, lds, st>>>(
         tab, pl->syn16_plane, MODE == 1 ? pl->off : pl->off_syn16, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F,
-        f0, NF, S, PREP ? 3 * pl->nspec : pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a);
+        f0, NF, S, PREP ? 3 * pl->nspec : pl->nspec_e * F, (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a,
+        pl->pf, pl->ninv);
 }
 
 template <int MODE>
