@@ -95,8 +95,18 @@ __global__ __launch_bounds__(Cfg<L>::T) void k_fft_fwd(const double* __restrict_
 // own (pack and inverse FFT, no workgroup barrier) while wavefront 4 copies
 // the twiddles; after a barrier the whole workgroup forms the five products
 // in place; after another, wavefront f analyses product row f on its own
-// (forward FFT, unpack, weights) and stores it.
+// (forward FFT, unpack, weights) and stores it.  Blocks are numbered so
+// that the two rows of a latitude pair (which read the same even / odd
+// Legendre sums) run one after the other on one XCD (workgroups go to the
+// XCDs round robin), where the second reads the sums from that XCD's L2.
 constexpr int GRID_T = 320;
+__device__ inline int grid_row(int b, int J) {
+    const int Jh = J / 2;
+    if (Jh % 8 != 0) return b;
+    const int x = b % 8, t = b / 8;                     // XCD, slot on it
+    const int k = 8 * (t / 2) + x;                      // latitude pair
+    return (t % 2 == 0) ? k : J - 1 - k;
+}
 template <int L>
 __global__ __launch_bounds__(GRID_T) void k_swe_grid(const double2* __restrict__ FI,
                                                      const double2* __restrict__ tw,
@@ -109,7 +119,7 @@ __global__ __launch_bounds__(GRID_T) void k_swe_grid(const double2* __restrict__
     __shared__ double2 lds[5 * P];
     __shared__ double2 tws[L2];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int j = blockIdx.x, s = blockIdx.y;
+    const int j = grid_row(blockIdx.x, J), s = blockIdx.y;
     const int Jh = J / 2;
     const int jp = (j < Jh) ? j : J - 1 - j;
     const double sgn = (j < Jh) ? 1.0 : -1.0;
