@@ -214,6 +214,25 @@ int mlsdc_step(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts*
                double dt, const double* theta_n_dev, double* theta_np1_dev,
                double* status_dev, void* ws_dev, size_t ws_bytes, shx_stream_t stream);
 
+/* mlsdc_step without a caller-supplied workspace and without any device
+ * allocation, for callers that cannot allocate device memory: code recorded
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The workspace is a library-owned array of
+ * SHX_NOALLOC_SCRATCH_BYTES on each device (a static device variable, held
+ * from the first use of the library on that device until the process ends;
+ * its address is looked up at sdc_level_create, or at the first call).
+ * Arguments and results as for mlsdc_step; the caller still owns theta_n,
+ * theta_np1 and status.  The limit covers the T255/T127 Gauss-Lobatto 5/3
+ * step (about 75 MB) without the residual check; larger configurations
+ * return SHX_EWORKSPACE (nothing is enqueued).  Every call on one device
+ * shares that device's array and leaves its contents behind: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  The step needs no zeroed workspace. */
+#define SHX_NOALLOC_SCRATCH_BYTES (96u * 1024u * 1024u)
+int mlsdc_step_noalloc(const sdc_level* fine, const sdc_level* coarse, const mlsdc_opts* opts, double dt,
+                       const double* theta_n_dev, double* theta_np1_dev, double* status_dev,
+                       shx_stream_t stream);
+
 /* Multi-level MLSDC: the V-cycle of which Algorithm 1 is the two-level case
  * (Sec. 4.3; more than two levels are the paper's future work), over
  * levels[0] (finest) .. levels[nlevels-1], 1 <= nlevels <= SHX_MAX_LEVELS.

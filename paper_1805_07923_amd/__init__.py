@@ -51,6 +51,7 @@ _SIGS = {
     "sdc_sweep": (_I, [_P, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "mlsdc_workspace_bytes": (_SZ, [_P, _P, ctypes.POINTER(MlsdcOpts)]),
     "mlsdc_step": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P, _SZ, _P]),
+    "mlsdc_step_noalloc": (_I, [_P, _P, ctypes.POINTER(MlsdcOpts), _D, _P, _P, _P, _P]),
     "mlsdc_multi_workspace_bytes": (_SZ, [_P, _I]),
     "mlsdc_step_multi": (_I, [_P, _I, _I, _P, _D, _P, _P, _P, _SZ, _P]),
     "sh_inverse_adj": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
@@ -404,6 +405,21 @@ class Stepper:
         _check(lib().mlsdc_step(self.fine.h, self.coarse.h if self.coarse else None, ctypes.byref(self.opts),
                                 float(dt), _ptr(theta_n), _ptr(theta_np1), _ptr(status), _ptr(w), self.nbytes,
                                 _stream()), "mlsdc_step")
+        return theta_np1
+
+    def step_noalloc(self, dt, theta_n, theta_np1, status=None):
+        """step() through mlsdc_step_noalloc: the library's per-device scratch
+        array is the workspace (no device allocation by the call; the output
+        tensors are the caller's)."""
+        import torch
+        n = 3 * self.fine.plan.nspec
+        _need(theta_n, torch.complex128, n, "theta_n")
+        _need(theta_np1, torch.complex128, n, "theta_np1")
+        if status is not None:
+            _need(status, torch.float64, 2, "status")
+        _check(lib().mlsdc_step_noalloc(self.fine.h, self.coarse.h if self.coarse else None, ctypes.byref(self.opts),
+                                        float(dt), _ptr(theta_n), _ptr(theta_np1), _ptr(status), _stream()),
+               "mlsdc_step_noalloc")
         return theta_np1
 
 

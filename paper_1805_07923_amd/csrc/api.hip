@@ -4,6 +4,7 @@
 // caller's stream; argument checks happen before anything is enqueued.
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -646,6 +647,36 @@ StepAdjWS carve_step_adj(Carve& c, const sdc_level* f, const sdc_level* cl, cons
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free step
+// The workspace of mlsdc_step_noalloc: one array per device, held from the
+// first use of the library on that device until the process ends.  In host
+// code the name `scratch` is only a stand-in for the device symbol; its
+// device address (different on every device) is looked up once per device
+// with hipGetSymbolAddress and cached, and only that address is passed on.
+namespace {
+static __device__ __align__(256) unsigned char scratch[SHX_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEV = 64;
+void* g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on device dev (looked up with dev current),
+// or nullptr if the lookup fails.
+void* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return g_scratch_ptr[dev];
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+    return ptr;
+}
+}  // namespace
+
 extern "C" {
 
 size_t shx_nspec(int ntrunc) { return ntrunc < 0 ? 0 : (size_t)nspec_of(ntrunc); }
@@ -1194,6 +1225,11 @@ int sdc_level_create(const shx_plan* pl, const swe_params* prm, int kind, int nn
         delete lv;
         return SHX_EINVAL;
     }
+    // set-up of the allocation-free step's scratch address on the plan's device
+    if (!scratch_ptr(pl->dev)) {
+        delete lv;
+        return SHX_EHIP;
+    }
     *out = lv;
     return SHX_OK;
 }
@@ -1260,6 +1296,17 @@ int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, do
     hipStream_t st = S(stream);
     return step_body(fl, cl, o, dt, reinterpret_cast<const double2*>(theta_n), reinterpret_cast<double2*>(theta_np1),
                      status, w, nullptr, st);
+}
+
+int mlsdc_step_noalloc(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, double dt,
+                       const double* theta_n, double* theta_np1, double* status, shx_stream_t stream) {
+    if (!fl) return SHX_EINVAL;
+    const size_t need = mlsdc_workspace_bytes(fl, cl, o);
+    if (need > (size_t)SHX_NOALLOC_SCRATCH_BYTES) return SHX_EWORKSPACE;
+    void* ptr = scratch_ptr(fl->plan->dev);
+    if (!ptr) return SHX_EHIP;
+    // the same launches as mlsdc_step, on the device's scratch array
+    return mlsdc_step(fl, cl, o, dt, theta_n, theta_np1, status, ptr, (size_t)SHX_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t mlsdc_multi_workspace_bytes(const sdc_level* const* levels, int nlevels) {
