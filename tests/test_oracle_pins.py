@@ -630,3 +630,35 @@ def test_mlsdc_three_levels_converge_to_collocation():
     res = [sdc.collocation_residual(L[0], 300.0, h) for h in hist]
     assert res[-1] < 1e-13, res
     assert res[0] > 1e-5, res
+
+
+def test_adjoint_jvp_golden_matches_oracle_reverse_mode():
+    """The stored forward-mode directional derivatives (tests/golden/
+    adjoint_jvp.json, T31/T15, 3 steps) equal the oracle's reverse-mode
+    gradient dotted with the same seeded directions: the two modes of
+    differentiation agree on the whole integration."""
+    import json
+    import os
+    import workload
+    from oracle import sdc as OS
+    from oracle import sht as OH
+    from oracle import swe as OW
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_jvp.json")) as f:
+        c = json.load(f)["T31_T15_3steps"]
+    lf = OS.Level(OW.SWEProblem(*c["fine"]), "lobatto", 5)
+    lc = OS.Level(OW.SWEProblem(*c["coarse"]), "lobatto", 3)
+    R, P = OS.spectral_transfer(c["fine"][0], c["coarse"][0])
+    th0 = torch.tensor(workload.state(c["fine"][0], c["seed_state"]))
+    x = th0.clone().requires_grad_(True)
+    y = x
+    for _ in range(c["nsteps"]):
+        y = OS.mlsdc_step(lf, lc, c["dt"], y, niter=4, nsweep_fine=2, nsweep_coarse=2, restrict_space=R,
+                          interp_space=P)
+    w = torch.where(OH.orders(c["fine"][0]) == 0, 1.0, 2.0).to(torch.float64)
+    (0.5 * (w * (y[0].real ** 2 + y[0].imag ** 2)).sum()).backward()
+    dirs = torch.tensor(workload.directions(c["fine"][0], c["ndirs"], c["seed_dirs"],
+                                            torch.linalg.vector_norm(th0[1]).item()))
+    g = x.grad[1]
+    got = torch.stack([(g.real * d.real + g.imag * d.imag).sum() for d in dirs]).numpy()
+    ref = np.array(c["dL"])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()

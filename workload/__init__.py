@@ -118,3 +118,23 @@ def dome_grid(mu, nlon):
     y = np.sin(lam) * cphi - np.sin(lc) * np.cos(pc)
     z = sphi - np.sin(pc)
     return DOME["g"] * DOME["A"] * np.exp(-DOME["alpha"] * (x * x + y * y + z * z))
+
+
+def directions(N, count, seed, norm):
+    """Seeded perturbation directions over one spectral field, complex128
+    [count, nspec(N)]: direction k uses draws re, im ~ N(0, 1) of length
+    nspec (re first, then im, in order k = 0, 1, ...) from
+    numpy.random.default_rng(seed); the imaginary part at m = 0 and the n = 0
+    entry are zero, and each direction is scaled to Euclidean norm `norm`."""
+    rng = np.random.default_rng(seed)
+    n = np.concatenate([np.arange(m, N + 1) for m in range(N + 1)])
+    m = np.concatenate([np.full(N + 1 - mm, mm) for mm in range(N + 1)])
+    out = np.empty((count, nspec(N)), dtype=np.complex128)
+    for k in range(count):
+        re = rng.standard_normal(nspec(N))
+        im = rng.standard_normal(nspec(N))
+        d = re + 1j * np.where(m == 0, 0.0, im)
+        d[n == 0] = 0.0
+        out[k] = d * (norm / np.linalg.norm(d))
+    return out
+
