@@ -63,6 +63,21 @@ enum shx_precision {
     SHX_SPLIT_BF16_3 = 3   /* bf16 three-way splits, 6 products, FP32 accum.  */
 };
 
+/* Where the normalised P^m_n(mu_j) of the contractions (Sec. 3, the P of eq.
+ * spectral_to_physical_space and eq. legendre_transform) come from. */
+enum shx_table_mode {
+    SHX_TABLE_HBM = 0,      /* tabulated once per plan and held in device memory
+                               (FP64, or rounded / split to the working
+                               precision): 2 x 8 B per (m, n, j) in FP64,
+                               4 B in FP32 (1.6 GB at T1023 on 1536 latitudes) */
+    SHX_TABLE_ONTHEFLY = 1  /* no table: every contraction regenerates P^m_n
+                               per order m by the FP64 three-term recurrence
+                               from exact restart values (at most 64 degrees
+                               apart; 126 MB at T1023) and, for a reduced
+                               working precision, rounds or splits it in
+                               registers right before the product */
+};
+
 enum sdc_node_kind {
     SDC_GAUSS_LOBATTO = 0, /* Sec. 4.2: Gauss-Lobatto nodes on [t^n, t^n + dt] */
     SDC_RADAU_RIGHT = 1    /* t^n followed by the Radau-IIA points            */
@@ -85,16 +100,18 @@ size_t shx_nspec(int ntrunc);
 /* Create a transform plan for T_ntrunc on nlat Gaussian latitudes and nlon
  * longitudes (Sec. 3, eqs. spectral_to_physical_space, fourier_transform,
  * legendre_transform).  Requires ntrunc >= 1, nlat even, nlon > 2 ntrunc,
- * nlat > ntrunc (else SHX_ESHAPE) and nlon = 2^k or 3*2^k with
- * 16 <= nlon <= 3072 (else SHX_EUNSUPPORTED).  Computes the Gaussian
- * latitudes and weights on the host in quad precision, the FFT twiddles in
- * extended precision, and the P^m_n tables (n <= ntrunc + 1) on the current
- * device with a double-double recurrence built from FP64 operations, stored
- * in `precision`, together with the exact restart values and recurrence
- * coefficients from which the FP64 Legendre kernels regenerate P^m_n (at
- * most 64 degrees of plain FP64 recurrence per restart).  Synchronises the
- * current device.  *out receives the plan (library-owned). */
-int shx_plan_create(int ntrunc, int nlat, int nlon, int precision, shx_plan** out);
+ * nlat > ntrunc (else SHX_ESHAPE), nlon = 2^k or 3*2^k with
+ * 16 <= nlon <= 3072 and a known precision (else SHX_EUNSUPPORTED), and
+ * table_mode SHX_TABLE_HBM or SHX_TABLE_ONTHEFLY (else SHX_EINVAL).
+ * Computes the Gaussian latitudes and weights on the host in quad precision,
+ * the FFT twiddles in extended precision, and on the current device, with a
+ * double-double recurrence built from FP64 operations, the exact restart
+ * values and recurrence coefficients from which the Legendre kernels
+ * regenerate P^m_n (n <= ntrunc + 1; at most 64 degrees of plain FP64
+ * recurrence per restart) and, with SHX_TABLE_HBM only, the P^m_n tables
+ * stored in `precision`.  Synchronises the current device.  *out receives
+ * the plan (library-owned). */
+int shx_plan_create(int ntrunc, int nlat, int nlon, int precision, int table_mode, shx_plan** out);
 void shx_plan_destroy(shx_plan* plan);
 
 /* Host copies of the plan's FP64 latitude data, each array [nlat]:
@@ -104,7 +121,8 @@ int shx_plan_latitudes(const shx_plan* plan, double* mu, double* sin_theta, doub
 /* Copy P^m_n(mu_j) (FP64 table values, or the working-precision table
  * values widened to FP64) for the northern latitudes j = 0..nlat/2-1 to the
  * host array out[nlat/2].  Requires 0 <= m <= n <= ntrunc + 1, m <= ntrunc.
- * Synchronous. */
+ * Plans without tables compute the row by the double-double recurrence (and
+ * round or split it as their contractions do).  Synchronous. */
 int shx_plan_legendre(const shx_plan* plan, int m, int n, double* out);
 
 /* ------------------------------------------------------- the SH pair */

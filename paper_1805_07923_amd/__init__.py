@@ -12,6 +12,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlsdc_sh.so")
 
 SHX_FP64, SHX_FP32, SHX_SPLIT_BF16_2, SHX_SPLIT_BF16_3 = 0, 1, 2, 3
+SHX_TABLE_HBM, SHX_TABLE_ONTHEFLY = 0, 1
 SDC_GAUSS_LOBATTO, SDC_RADAU_RIGHT = 0, 1
 
 _lib = None
@@ -32,7 +33,7 @@ _P, _D, _I, _SZ = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_
 _SIGS = {
     "shx_nspec": (_SZ, [_I]),
     "shx_strerror": (ctypes.c_char_p, [_I]),
-    "shx_plan_create": (_I, [_I, _I, _I, _I, ctypes.POINTER(_P)]),
+    "shx_plan_create": (_I, [_I, _I, _I, _I, _I, ctypes.POINTER(_P)]),
     "shx_plan_destroy": (None, [_P]),
     "shx_plan_latitudes": (_I, [_P, _P, _P, _P]),
     "shx_plan_legendre": (_I, [_P, _I, _I, _P]),
@@ -147,12 +148,14 @@ class Workspace:
 
 
 class Plan:
-    """Transform plan for truncation T_N on an nlat x nlon Gaussian grid."""
+    """Transform plan for truncation T_N on an nlat x nlon Gaussian grid
+    (table_mode: SHX_TABLE_HBM or SHX_TABLE_ONTHEFLY)."""
 
-    def __init__(self, N, nlat, nlon, precision=SHX_FP64):
+    def __init__(self, N, nlat, nlon, precision=SHX_FP64, table_mode=SHX_TABLE_HBM):
         self.N, self.nlat, self.nlon, self.precision = N, nlat, nlon, precision
+        self.table_mode = table_mode
         h = ctypes.c_void_p()
-        _check(lib().shx_plan_create(N, nlat, nlon, precision, ctypes.byref(h)), "shx_plan_create")
+        _check(lib().shx_plan_create(N, nlat, nlon, precision, table_mode, ctypes.byref(h)), "shx_plan_create")
         self.h = h
         self.nspec = nspec(N)
         self.ws = Workspace()

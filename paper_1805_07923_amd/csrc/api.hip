@@ -730,9 +730,10 @@ const char* shx_strerror(int s) {
     }
 }
 
-int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
+int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** out) {
     if (!out || N < 1 || J < 2 || I < 2) return SHX_EINVAL;
     *out = nullptr;
+    if (table_mode != SHX_TABLE_HBM && table_mode != SHX_TABLE_ONTHEFLY) return SHX_EINVAL;
     if (prec < SHX_FP64 || prec > SHX_SPLIT_BF16_3) return SHX_EUNSUPPORTED;
     if ((J & 1) || I <= 2 * N || J <= N) return SHX_ESHAPE;
     if (!fft_length_supported(I)) return SHX_EUNSUPPORTED;
@@ -742,6 +743,7 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
     p->J = J;
     p->I = I;
     p->prec = prec;
+    p->tmode = table_mode;
     p->nmax = N + 1;
     p->Jh = J / 2;
     p->nspec = nspec_of(N);
@@ -833,8 +835,10 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
     }
     bool ok = dalloc(&p->mu, J) == hipSuccess && dalloc(&p->sint, J) == hipSuccess &&
               dalloc(&p->cos2, J) == hipSuccess && dalloc(&p->w, J) == hipSuccess &&
-              dalloc(&p->tw, I) == hipSuccess && dalloc(&p->psyn, acc) == hipSuccess &&
-              dalloc(&p->pan, acc) == hipSuccess && dalloc(&p->off, p->h_off.size()) == hipSuccess &&
+              dalloc(&p->tw, I) == hipSuccess &&
+              (table_mode == SHX_TABLE_ONTHEFLY ||
+               (dalloc(&p->psyn, acc) == hipSuccess && dalloc(&p->pan, acc) == hipSuccess)) &&
+              dalloc(&p->off, p->h_off.size()) == hipSuccess &&
               dalloc(&p->ord, p->nspec) == hipSuccess && dalloc(&p->deg, p->nspec) == hipSuccess &&
               dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess &&
               dalloc(&p->ck, ck_elems) == hipSuccess && dalloc(&p->ckoff, N + 1) == hipSuccess &&
@@ -861,7 +865,7 @@ int shx_plan_create(int N, int J, int I, int prec, shx_plan** out) {
     ok = ok && hipMemcpy(p->deg_e, dege.data(), dege.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && launch_plm_table(p, 0) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
-    if (ok && prec != SHX_FP64) ok = convert_tables(p);
+    if (ok && prec != SHX_FP64 && table_mode == SHX_TABLE_HBM) ok = convert_tables(p);
     if (!ok) {
         plan_free(p);
         return SHX_EHIP;
@@ -886,6 +890,18 @@ int shx_plan_legendre(const shx_plan* pl, int m, int n, double* out) {
     if (!pl || !out || m < 0 || m > pl->N || n < m || n > pl->nmax) return SHX_EINVAL;
     const int p = (n - m) & 1, k = (n - m) >> 1;
     const long long o = pl->h_off[2 * m + p] + (long long)k * pl->Jh;   // row k of the [k][jp] layout
+    if (pl->tmode == SHX_TABLE_ONTHEFLY) {
+        // no table: the row from the recurrence, then the working precision's
+        // rounding (FP32) or split (sum of the bf16 pieces) that the contractions use
+        double* d = nullptr;
+        if (dalloc(&d, pl->Jh) != hipSuccess) return SHX_EHIP;
+        const bool ok = launch_plm_one(pl, m, n, d, 0) == hipSuccess &&
+                        hipMemcpy(out, d, pl->Jh * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
+        (void)hipFree(d);
+        if (!ok) return SHX_EHIP;
+        for (int j = 0; j < pl->Jh; ++j) out[j] = shx_host_working_value(pl->prec, out[j]);
+        return SHX_OK;
+    }
     if (pl->prec == SHX_FP64) {
         if (hipMemcpy(out, pl->psyn + o, pl->Jh * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return SHX_EHIP;
     } else if (pl->prec == SHX_FP32) {

@@ -169,6 +169,7 @@ __device__ inline LegTile leg_tile(int gx, int nm, int np = 2) {
 // -------------------------------------------------------------------- plans
 struct shx_plan {
     int N = 0, J = 0, I = 0, prec = 0, dev = 0;
+    int tmode = SHX_TABLE_HBM;      // P^m_n tables held in HBM, or regenerated on the fly (no tables)
     int nmax = 0;                   // N + 1: degree range of tables / ext layout
     int Jh = 0;                     // J / 2 latitude pairs
     long long nspec = 0, nspec_e = 0;
@@ -237,6 +238,9 @@ struct Mat9x9 {
 // ----------------------------------------------------- launch wrappers
 // legendre.hip
 hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st);
+// P^m_n at the northern latitudes by the double-double recurrence, rounded to
+// FP64, into out[Jh] (device): the table export of plans without tables.
+hipError_t launch_plm_one(const shx_plan* pl, int m, int n, double* out, hipStream_t st);
 hipError_t launch_leg_syn(const shx_plan* pl, const double2* cin, double2* out, int F, int S,
                           int nmax_use, hipStream_t st);
 // Synthesis of the tendency's four grid fields straight from S states

@@ -143,6 +143,7 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
         const int g = (n - m) / L, gr = (n - m) - g * L;
         if (gr == 0) ckm[(long long)g * Jh] = make_double2(v, 0.0);
         if (gr == 1) ckm[(long long)g * Jh].y = v;
+        if (!psyn) continue;                            // plan without tables: restart data only
         const int p = (n - m) & 1, k = (n - m) >> 1;
         if (p == 0) {
             ps0[(long long)k * Jh + jp] = v;
@@ -152,6 +153,32 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
             pa1[(long long)jp * K1 + k] = v;
         }
     }
+}
+
+// One row P^m_n(mu_jp), jp < Jh, by the same double-double recurrence.
+__global__ void k_plm_one(const double* __restrict__ mu, const double* __restrict__ sint, int m, int n, int Jh,
+                          double* __restrict__ out) {
+    const int jp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (jp >= Jh) return;
+    const double x = mu[jp], s = sint[jp];
+    dd pmm = dd_sqrt(dd{0.5, 0.0});
+    for (int k = 1; k <= m; ++k)
+        pmm = dd_mul_d(dd_mul(pmm, dd_sqrt(dd_div(dd{2.0 * k + 1.0, 0.0}, dd{2.0 * k, 0.0}))), s);
+    dd p2{0.0, 0.0}, p1 = pmm, pn = pmm;
+    if (n > m) {
+        pn = dd_mul_d(dd_mul(dd_sqrt(dd{2.0 * m + 3.0, 0.0}), pmm), x);
+        p2 = pmm;
+        p1 = pn;
+    }
+    dd e_prev = dd_eps(m + 1, m);
+    for (int k = m + 2; k <= n; ++k) {
+        const dd en = dd_eps(k, m);
+        pn = dd_div(dd_sub(dd_mul_d(p1, x), dd_mul(e_prev, p2)), en);
+        e_prev = en;
+        p2 = p1;
+        p1 = pn;
+    }
+    out[jp] = pn.h + pn.l;
 }
 #pragma clang fp contract(fast)
 
@@ -542,7 +569,7 @@ void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int 
 template <int NF>
 void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
               hipStream_t st) {
-    if (NF <= 6 && pl->Jh <= AN_JC) {
+    if (NF <= 6 && pl->Jh <= AN_JC && pl->pan) {
         const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
         k_leg_an<NF><<<pl->tb_nblk, 256, lds, st>>>(pl->tblk, pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
                                                    pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
@@ -563,6 +590,11 @@ hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
     dim3 grid((pl->Jh + 63) / 64, pl->N + 1);
     k_plm_table<<<grid, 64, 0, st>>>(pl->mu, pl->sint, pl->off, pl->psyn, pl->pan, pl->ck, pl->ckoff, pl->rc,
                                      pl->N, pl->nmax, pl->Jh);
+    return hipGetLastError();
+}
+
+hipError_t launch_plm_one(const shx_plan* pl, int m, int n, double* out, hipStream_t st) {
+    k_plm_one<<<(pl->Jh + 63) / 64, 64, 0, st>>>(pl->mu, pl->sint, m, n, pl->Jh, out);
     return hipGetLastError();
 }
 

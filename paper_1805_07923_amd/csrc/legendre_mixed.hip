@@ -409,6 +409,354 @@ __global__ __launch_bounds__(256) void k_leg_syn_mx(const void* __restrict__ tab
     }
 }
 
+// ------------------------------------------- without tables (on the fly)
+// Plans created with SHX_TABLE_ONTHEFLY hold no table: P^m_n comes from the
+// FP64 three-term recurrence of the orthonormal functions (Sec. 3), run from
+// the plan's exact restart values as in the FP64 matrix-core kernels of
+// legendre.hip, and is rounded to FP32 (MODE 1) or split into bf16 pieces
+// (MODE 2, 3) in registers right before the product; the other operand is
+// rounded / split the same way; FP32 accumulation.
+
+// Value of lane src (wave-uniform) of a per-lane double, for every lane.
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// NP bf16 pieces of four values, packed as the 4-element MFMA operands.
+template <int NP>
+__device__ __forceinline__ void split4(const double* v, shortx4* out) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        unsigned short h[NP];
+        split_bf16<NP>(v[r], h);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) out[q][r] = (short)h[q];
+    }
+}
+
+// Synthesis: the organisation of k_leg_syn_m (one wavefront per 16
+// latitudes, lane (i, q) = latitude i and restart segment q of the round,
+// two degrees per recurrence step, even / odd accumulators).  MODE 1:
+// v_mfma_f32_16x16x4_f32 per degree pair, A = P (lane's latitude, segment)
+// and B = the lane's coefficient, both rounded to FP32.  MODE 2, 3:
+// v_mfma_f32_16x16x16_bf16 per four degrees of one parity: the lane's four
+// P values (k slots 4q..4q+3) and its four coefficients are split into bf16
+// pieces (the lane supplies exactly the k slots of its own segment).  D:
+// D[4 (l/16) + r][l % 16] = latitude 4 (l/16) + r, column l % 16.
+template <int NF, int MODE, int STAGE>
+__global__ __launch_bounds__(256) void k_leg_syn_mo(const double2* __restrict__ ck,
+                                                    const long long* __restrict__ ckoff,
+                                                    const double2* __restrict__ rc,
+                                                    const double* __restrict__ mu,
+                                                    const double2* __restrict__ cin, double2* __restrict__ out,
+                                                    int N, int nmax_tab, int nmax_use, int Jh, int F, int f0, int S,
+                                                    long long cin_stride, long long out_stride, int gx,
+                                                    long long nspec, double a, int Lmax,
+                                                    const double2* __restrict__ pf,
+                                                    const double* __restrict__ ninv) {
+    static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
+    constexpr int NP = (MODE == 1) ? 1 : MODE;
+    constexpr int U = 8;                                // degrees per batch of LDS reads
+    extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, q = lane >> 4;
+    const int ic = i < 2 * NF ? i : 2 * NF - 1;
+    const LegTile tile = leg_tile(gx, N + 1, 1);
+    const int m = tile.m;
+    const int jw = tile.x * 64 + wv * 16;
+    const int jp = jw + i;
+    const bool active = jp < Jh;
+    const int Kt = nmax_tab - m + 1, Ku = nmax_use - m + 1;
+    const int R = seg_rounds(Kt), L = seg_len(Kt);
+    const int SC = L * NF + 2, SR = L + 2;
+    const double x = mu[active ? jp : 0];
+    const double2* ckm = ck + ckoff[m] + (active ? jp : 0);
+    double2* rsh = csh + 4 * (Lmax * NF + 2);
+    const double* cq = reinterpret_cast<const double*>(csh + q * SC) + ic;
+    const double2* rq = rsh + q * SR;
+    const double2* rcm = rc + ext_idx(N, m, m);
+    const double2* pfm = pf + ext_idx(N, m, m);
+    const double ia = 1.0 / a, a2 = a * a;
+    for (int s = 0; s < S; ++s) {
+        floatx4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = e0, o0 = e0, o1 = e0;
+        for (int r = 0; r < R; ++r) {
+            const int kr0 = 4 * r * L;
+            if (kr0 >= Ku) break;                       // uniform
+            const int g = 4 * r + q;
+            const double2 c0 = ckm[(long long)g * Jh];
+            __syncthreads();
+            for (int kl = threadIdx.x; kl < 4 * L; kl += 256) {
+                const int qs = kl / L, ts = kl - qs * L, kk = kr0 + kl;
+                double2* row = csh + qs * SC + ts * NF;
+                if (kk < Ku) {
+                    if constexpr (STAGE == 1) {
+                        static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
+                        double2 o[4];
+                        swe_prep_row(cin + s * cin_stride, nspec, N, a2, ia, pfm, ninv, m, m + kk, o);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) row[f] = o[f];
+                    } else {
+                        const double2* cg = cin + s * cin_stride + (ext_idx(N, m, m) + kk) * F + f0;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) row[f] = cg[f];
+                    }
+                } else {
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) row[f] = make_double2(0.0, 0.0);
+                }
+                rsh[qs * SR + ts] = (kk < Kt) ? rcm[kk] : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            if (jw >= Jh) continue;
+            double pe = c0.x, po = c0.y;
+            for (int t = 0; t < L; t += U) {
+                double2 rr[U];
+                double bb[U], pv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    rr[u] = rq[t + u];
+                    bb[u] = cq[(t + u) * 2 * NF];
+                }
+#pragma unroll
+                for (int u = 0; u < U; u += 2) {
+                    if (u > 0 || t > 0) {
+                        const double ne = fma(rr[u].x * x, po, -(rr[u].y * pe));
+                        po = fma(rr[u + 1].x * x, ne, -(rr[u + 1].y * po));
+                        pe = ne;
+                    }
+                    pv[u] = pe;
+                    pv[u + 1] = po;
+                    if constexpr (MODE == 1) {
+                        e0 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)pe, (float)bb[u], e0, 0, 0, 0);
+                        o0 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)po, (float)bb[u + 1], o0, 0, 0, 0);
+                    }
+                }
+                if constexpr (MODE != 1) {
+                    const double ve[4] = {pv[0], pv[2], pv[4], pv[6]}, vo[4] = {pv[1], pv[3], pv[5], pv[7]};
+                    const double we[4] = {bb[0], bb[2], bb[4], bb[6]}, wo[4] = {bb[1], bb[3], bb[5], bb[7]};
+                    shortx4 aE[NP], aO[NP], bE[NP], bO[NP];
+                    split4<NP>(ve, aE);
+                    split4<NP>(vo, aO);
+                    split4<NP>(we, bE);
+                    split4<NP>(wo, bO);
+                    mfma_split<MODE>(aE, bE, e0, e1);
+                    mfma_split<MODE>(aO, bO, o0, o1);
+                }
+            }
+        }
+        if (jw < Jh && i < 2 * NF) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int jr = jw + 4 * q + rr;
+                if (jr < Jh) {
+                    double* d = reinterpret_cast<double*>(out + s * out_stride +
+                                                          ((long long)jr * (N + 1) + m) * F + f0) + i;
+                    d[0] = (double)e0[rr] + (double)e1[rr];
+                    d[(long long)Jh * (N + 1) * F * 2] = (double)o0[rr] + (double)o1[rr];
+                }
+            }
+        }
+    }
+}
+
+// Analysis: the organisation of k_leg_an_m (one block per (order m,
+// restart segment g), wavefronts over groups of 64 latitudes, lane =
+// latitude running the recurrence into a wave-private LDS tile of 32
+// degrees per parity; partial sums of the latitude groups added through LDS
+// in wavefront order, in FP64).  MODE 1: v_mfma_f32_16x16x4_f32, A = P of 16
+// degrees x 4 latitudes from the tile, B = the north +/- south Fourier
+// coefficients, both rounded to FP32.  MODE 2, 3: v_mfma_f32_16x16x16_bf16
+// over 16 latitudes, lane (i, q) = degree i and latitudes 4q..4q+3 of the
+// chunk, operands split into bf16 pieces.
+template <int NF, int MODE>
+__global__ __launch_bounds__(256) void k_leg_an_mo(const int* __restrict__ blist,
+                                                   const double2* __restrict__ ck,
+                                                   const long long* __restrict__ ckoff,
+                                                   const double2* __restrict__ rc,
+                                                   const double* __restrict__ mu,
+                                                   const double2* __restrict__ G,
+                                                   double2* __restrict__ cout, int N, int nmax_tab,
+                                                   int nmax_use, int J, int F, int f0, int S,
+                                                   long long G_stride, long long cout_stride, int nw) {
+    static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
+    constexpr int NP = (MODE == 1) ? 1 : MODE;
+    constexpr int TP = 17;                              // padded tile row
+    extern __shared__ double lsh[];                     // [nw][2][64][TP]; then the partial sums
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, q = lane >> 4;
+    const int m = blist[2 * blockIdx.x], g = blist[2 * blockIdx.x + 1];
+    if (m < 0) return;                                  // padding block (uniform)
+    const int Jh = J / 2;
+    const int Kt = nmax_tab - m + 1, Ku = nmax_use - m + 1;
+    const int L = seg_len(Kt);
+    const int k0 = g * L;
+    if (k0 >= Ku) return;                               // uniform
+    const int kend = min(k0 + L, Ku);
+    const int ntp = (kend - k0 + 31) / 32;
+    const int ngrp = (Jh + 63) / 64;
+    double* PE = lsh + wv * (2 * 64 * TP);
+    double* PO = PE + 64 * TP;
+    double* red = lsh;
+    const double2* rcm = rc + ext_idx(N, m, m);
+    const long long rs = (long long)(N + 1) * F * 2;
+    const int jc = i < 2 * NF ? i : 2 * NF - 1;
+    for (int s = 0; s < S; ++s) {
+        floatx4 acc[2][2][2];                           // [tile pair][parity][leading, corrections]
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b][0] = acc[a][b][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const double* gs = reinterpret_cast<const double*>(G + s * G_stride + (long long)m * F + f0) + jc;
+        for (int lg = wv; lg < ngrp; lg += nw) {
+            const int jp = lg * 64 + lane;
+            const bool act = jp < Jh;
+            const double x = mu[act ? jp : 0];
+            const double2 c0 = act ? ck[ckoff[m] + (long long)g * Jh + jp] : make_double2(0.0, 0.0);
+            // B operands: the Fourier data of latitude lg 64 + jl for the lane's column
+            // (MODE 1: jl = 4c + q; MODE 2, 3: jl = 16 c4 + 4q + r)
+            double be[16], bo[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int jl = (MODE == 1) ? 4 * c + q : 16 * (c >> 2) + 4 * q + (c & 3);
+                const int jb = lg * 64 + jl;
+                const bool ab = jb < Jh;
+                const int jr = ab ? jb : 0;
+                const double vn = gs[jr * rs], vs = gs[(J - 1 - jr) * rs];
+                be[c] = ab ? vn + vs : 0.0;
+                bo[c] = ab ? vn - vs : 0.0;
+            }
+            double pe = c0.x, po = c0.y;
+            const double2 rcv = rcm[min(k0 + lane, Kt - 1)];
+            for (int tp = 0; tp < ntp; ++tp) {
+#pragma unroll
+                for (int i2 = 0; i2 < 16; ++i2) {
+                    if (tp > 0 || i2 > 0) {
+                        const int t = 32 * tp + 2 * i2;
+                        const double r0x = bcast_lane(rcv.x, t), r0y = bcast_lane(rcv.y, t);
+                        const double r1x = bcast_lane(rcv.x, t + 1), r1y = bcast_lane(rcv.y, t + 1);
+                        const double ne = fma(r0x * x, po, -(r0y * pe));
+                        po = fma(r1x * x, ne, -(r1y * po));
+                        pe = ne;
+                    }
+                    PE[lane * TP + i2] = pe;
+                    PO[lane * TP + i2] = po;
+                }
+                if constexpr (MODE == 1) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) {
+                        const float ae = (float)PE[(4 * c + q) * TP + i];
+                        const float ao = (float)PO[(4 * c + q) * TP + i];
+                        acc[tp][0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, (float)be[c], acc[tp][0][0], 0, 0, 0);
+                        acc[tp][1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ao, (float)bo[c], acc[tp][1][0], 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int c4 = 0; c4 < 4; ++c4) {
+                        double ve[4], vo[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            ve[r] = PE[(16 * c4 + 4 * q + r) * TP + i];
+                            vo[r] = PO[(16 * c4 + 4 * q + r) * TP + i];
+                        }
+                        shortx4 aE[NP], aO[NP], bE[NP], bO[NP];
+                        split4<NP>(ve, aE);
+                        split4<NP>(vo, aO);
+                        split4<NP>(be + 4 * c4, bE);
+                        split4<NP>(bo + 4 * c4, bO);
+                        mfma_split<MODE>(aE, bE, acc[tp][0][0], acc[tp][0][1]);
+                        mfma_split<MODE>(aO, bO, acc[tp][1][0], acc[tp][1][1]);
+                    }
+                }
+            }
+        }
+        __syncthreads();                                // all tile reads done
+        for (int tp = 0; tp < ntp; ++tp)
+#pragma unroll
+            for (int eo = 0; eo < 2; ++eo)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    red[(((wv * 2 + tp) * 2 + eo) * 4 + rr) * 64 + lane] =
+                        (double)acc[tp][eo][0][rr] + (double)acc[tp][eo][1][rr];
+        __syncthreads();
+        // D layout (16x16, f32): the lane holds rows 4q + rr (degree pairs) of column i
+        for (int u = wv; u < 2 * ntp && i < 2 * NF; u += nw) {
+            const int tp = u >> 1, eo = u & 1;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int k = k0 + 32 * tp + 2 * (4 * q + rr) + eo;
+                if (k < kend) {
+                    double v = 0.0;
+                    for (int w = 0; w < nw; ++w) v += red[(((w * 2 + tp) * 2 + eo) * 4 + rr) * 64 + lane];
+                    reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + k) * F + f0)[i] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NF, int MODE, int STAGE>
+void syn_mo(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S, int nmax_use,
+            long long cin_stride, double a, hipStream_t st) {
+    const int gx = (pl->Jh + 63) / 64;
+    int Lmax = 0;
+    for (int m = 0; m <= pl->N; ++m) Lmax = seg_len(pl->nmax - m + 1) > Lmax ? seg_len(pl->nmax - m + 1) : Lmax;
+    const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2);
+    k_leg_syn_mo<NF, MODE, STAGE><<<gx * (pl->N + 1), 256, lds, st>>>(
+        pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride,
+        (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a, Lmax, pl->pf, pl->ninv);
+}
+
+template <int NF, int MODE>
+void an_mo(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
+           hipStream_t st) {
+    const int ngrp = (pl->Jh + 63) / 64;
+    const int nw = ngrp < 4 ? ngrp : 4;
+    const size_t lds = (size_t)nw * 2 * 64 * 17 * sizeof(double);
+    k_leg_an_mo<NF, MODE><<<pl->an_nblk, 64 * nw, lds, st>>>(pl->anblk, pl->ck, pl->ckoff, pl->rc, pl->mu, G, cout,
+                                                            pl->N, pl->nmax, nmax_use, pl->J, F, f0, S,
+                                                            (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F,
+                                                            nw);
+}
+
+template <int MODE>
+void syn_mo_fields(const shx_plan* pl, const double2* cin, double2* out, int F, int S, int nmax_use,
+                   hipStream_t st) {
+    const long long cs = pl->nspec_e * F;
+    for (int f0 = 0; f0 < F; f0 += 8) {
+        switch (F - f0 < 8 ? F - f0 : 8) {
+            case 1: syn_mo<1, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            case 2: syn_mo<2, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            case 3: syn_mo<3, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            case 4: syn_mo<4, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            case 5: syn_mo<5, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            case 6: syn_mo<6, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            case 7: syn_mo<7, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+            default: syn_mo<8, MODE, 0>(pl, cin, out, F, f0, S, nmax_use, cs, 0.0, st); break;
+        }
+    }
+}
+
+template <int MODE>
+void an_mo_fields(const shx_plan* pl, const double2* G, double2* cout, int F, int S, int nmax_use,
+                  hipStream_t st) {
+    for (int f0 = 0; f0 < F; f0 += 8) {
+        switch (F - f0 < 8 ? F - f0 : 8) {
+            case 1: an_mo<1, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 2: an_mo<2, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 3: an_mo<3, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 4: an_mo<4, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 5: an_mo<5, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 6: an_mo<6, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            case 7: an_mo<7, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            default: an_mo<8, MODE>(pl, G, cout, F, f0, S, nmax_use, st); break;
+        }
+    }
+}
+
 template <int MODE, int NCT>
 void an_mx(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int NF, int S, int nmax_use,
            hipStream_t st) {
@@ -463,6 +811,15 @@ void syn_mode(const shx_plan* pl, const double2* cin, double2* out, int F, int S
 
 hipError_t launch_leg_an_mixed(const shx_plan* pl, const double2* G, double2* cout, int F, int S, int nmax_use,
                                hipStream_t st) {
+    if (pl->tmode == SHX_TABLE_ONTHEFLY) {
+        switch (pl->prec) {
+            case SHX_FP32: an_mo_fields<1>(pl, G, cout, F, S, nmax_use, st); break;
+            case SHX_SPLIT_BF16_2: an_mo_fields<2>(pl, G, cout, F, S, nmax_use, st); break;
+            case SHX_SPLIT_BF16_3: an_mo_fields<3>(pl, G, cout, F, S, nmax_use, st); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (pl->prec) {
         case SHX_FP32: an_mode<1>(pl, G, cout, F, S, nmax_use, st); break;
         case SHX_SPLIT_BF16_2: an_mode<2>(pl, G, cout, F, S, nmax_use, st); break;
@@ -474,6 +831,16 @@ hipError_t launch_leg_an_mixed(const shx_plan* pl, const double2* G, double2* co
 
 hipError_t launch_leg_syn_mixed_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
                                     hipStream_t st) {
+    if (pl->tmode == SHX_TABLE_ONTHEFLY) {
+        const long long cs = 3 * pl->nspec;
+        switch (pl->prec) {
+            case SHX_FP32: syn_mo<4, 1, 1>(pl, state, out, 4, 0, S, pl->nmax, cs, a, st); break;
+            case SHX_SPLIT_BF16_2: syn_mo<4, 2, 1>(pl, state, out, 4, 0, S, pl->nmax, cs, a, st); break;
+            case SHX_SPLIT_BF16_3: syn_mo<4, 3, 1>(pl, state, out, 4, 0, S, pl->nmax, cs, a, st); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (pl->prec) {
         case SHX_FP32: syn_mx<1, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
         case SHX_SPLIT_BF16_2: syn_mx<2, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
@@ -485,6 +852,15 @@ hipError_t launch_leg_syn_mixed_swe(const shx_plan* pl, double a, const double2*
 
 hipError_t launch_leg_syn_mixed(const shx_plan* pl, const double2* cin, double2* out, int F, int S, int nmax_use,
                                 hipStream_t st) {
+    if (pl->tmode == SHX_TABLE_ONTHEFLY) {
+        switch (pl->prec) {
+            case SHX_FP32: syn_mo_fields<1>(pl, cin, out, F, S, nmax_use, st); break;
+            case SHX_SPLIT_BF16_2: syn_mo_fields<2>(pl, cin, out, F, S, nmax_use, st); break;
+            case SHX_SPLIT_BF16_3: syn_mo_fields<3>(pl, cin, out, F, S, nmax_use, st); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (pl->prec) {
         case SHX_FP32: syn_mode<1>(pl, cin, out, F, S, nmax_use, st); break;
         case SHX_SPLIT_BF16_2: syn_mode<2>(pl, cin, out, F, S, nmax_use, st); break;

@@ -10,6 +10,8 @@
 #include <quadmath.h>
 
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "setup_host.h"
@@ -231,4 +233,35 @@ extern "C" void shx_host_twiddles(int L, double* re, double* im) {
         re[t] = (double)cosq(a);
         im[t] = -(double)sinq(a);   // e^{-2 pi i t / L}
     }
+}
+
+// ------------------------------------------------------------------------
+// Value that a Legendre contraction of working precision `prec` uses for the
+// FP64 value x: x (FP64), x rounded to FP32 (SHX_FP32), or the sum of its
+// bf16 pieces (SHX_SPLIT_BF16_2 / _3: each piece the round-to-nearest-even
+// bf16 of the FP32-rounded remainder).
+static unsigned short host_f2bf(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+static float host_bf2f(unsigned short h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+double shx_host_working_value(int prec, double x) {
+    if (prec == 1) return (double)(float)x;
+    if (prec == 2 || prec == 3) {
+        double rem = x, sum = 0.0;
+        for (int q = 0; q < prec; ++q) {
+            const double v = host_bf2f(host_f2bf((float)rem));
+            sum += v;
+            rem -= v;
+        }
+        return sum;
+    }
+    return x;
 }

@@ -12,6 +12,10 @@ int shx_host_sdc(int kind, int nnodes, double* tau, double* Q, double* QE, doubl
 int shx_host_transfer(int kind, int n_src, int n_dst, double* Pi);
 // e^{-2 pi i t / L}, t = 0..L-1.
 void shx_host_twiddles(int L, double* re, double* im);
+
+// The value a Legendre contraction of working precision prec uses for x
+// (FP64: x; FP32: rounded; split bf16: the sum of the pieces).
+double shx_host_working_value(int prec, double x);
 #ifdef __cplusplus
 }
 #endif

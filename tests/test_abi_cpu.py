@@ -36,15 +36,16 @@ def test_header_declarations_exported():
 def test_argument_validation_without_device():
     L = pk.lib()
     h = ctypes.c_void_p()
-    assert L.shx_plan_create(31, 48, 96, 0, None) == -1
-    assert L.shx_plan_create(0, 48, 96, 0, ctypes.byref(h)) == -1
-    assert L.shx_plan_create(31, 47, 96, 0, ctypes.byref(h)) == -2     # odd nlat
-    assert L.shx_plan_create(31, 48, 62, 0, ctypes.byref(h)) == -2     # nlon <= 2N
-    assert L.shx_plan_create(31, 30, 96, 0, ctypes.byref(h)) == -2     # nlat <= N
-    assert L.shx_plan_create(31, 48, 100, 0, ctypes.byref(h)) == -3    # not 2^k or 3*2^k
-    assert L.shx_plan_create(31, 48, 96, 7, ctypes.byref(h)) == -3     # unknown precision
-    assert L.shx_plan_create(7, 12, 24, 0, ctypes.byref(h)) == -3      # 3*2^k below the smallest row (48)
-    assert L.shx_plan_create(3, 4, 8, 0, ctypes.byref(h)) == -3        # 2^k below the smallest row (16)
+    assert L.shx_plan_create(31, 48, 96, 0, 0, None) == -1
+    assert L.shx_plan_create(0, 48, 96, 0, 0, ctypes.byref(h)) == -1
+    assert L.shx_plan_create(31, 47, 96, 0, 0, ctypes.byref(h)) == -2     # odd nlat
+    assert L.shx_plan_create(31, 48, 62, 0, 0, ctypes.byref(h)) == -2     # nlon <= 2N
+    assert L.shx_plan_create(31, 30, 96, 0, 0, ctypes.byref(h)) == -2     # nlat <= N
+    assert L.shx_plan_create(31, 48, 100, 0, 0, ctypes.byref(h)) == -3    # not 2^k or 3*2^k
+    assert L.shx_plan_create(31, 48, 96, 7, 0, ctypes.byref(h)) == -3     # unknown precision
+    assert L.shx_plan_create(7, 12, 24, 0, 0, ctypes.byref(h)) == -3      # 3*2^k below the smallest row (48)
+    assert L.shx_plan_create(3, 4, 8, 0, 0, ctypes.byref(h)) == -3        # 2^k below the smallest row (16)
+    assert L.shx_plan_create(31, 48, 96, 0, 2, ctypes.byref(h)) == -1  # unknown table mode
     assert L.shx_nspec(31) == 32 * 33 // 2
     assert L.shx_strerror(-4).decode().startswith("workspace")
     par = pk.swe_params()

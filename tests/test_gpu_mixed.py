@@ -14,7 +14,11 @@ error of the contractions; a time step adds dt F_E to the state, so its error
 is smaller again.
 
 Each GPU error must also be within 5x of the CPU emulation's (oracle.mixed),
-which predicts the level without sharing the summation order."""
+which predicts the level without sharing the summation order.  Every test
+runs on plans with tables in device memory (SHX_TABLE_HBM: the FP64 tables
+rounded / split once) and on plans without tables (SHX_TABLE_ONTHEFLY: P
+from the FP64 recurrence, rounded / split in registers before the product),
+under the same bounds."""
 import pytest
 import torch
 
@@ -27,6 +31,7 @@ from oracle import swe as OW
 pytestmark = pytest.mark.gpu
 
 MODES = {"fp32": 1, "bf16x2": 2, "bf16x3": 3}
+TMODES = {"hbm": 0, "onthefly": 1}
 BOUND_PAIR = {"fp32": 2e-6, "bf16x2": 2e-5, "bf16x3": 2e-6}
 BOUND_TEND = {"fp32": 1e-4, "bf16x2": 2e-3, "bf16x3": 1e-4}
 BOUND_STEP = {"fp32": 1e-6, "bf16x2": 5e-5, "bf16x3": 1e-6}
@@ -56,17 +61,18 @@ def relerr(a, b):
     return (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
 
 
+@pytest.mark.parametrize("tmode", list(TMODES))
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("N,J,I,F", [(31, 48, 96, 3), (40, 64, 128, 5), (255, 384, 768, 15)])
-def test_pair_mixed(pk, mode, N, J, I, F):
-    print("CASE mixed pair", mode, N, J, I, F, flush=True)
+def test_pair_mixed(pk, mode, N, J, I, F, tmode):
+    print("CASE mixed pair", mode, tmode, N, J, I, F, flush=True)
     g = ogrid(N, J, I)
     if N == 255:
         spec = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1))
     else:
         spec = torch.stack([torch.tensor(workload.raw_spectrum(N, 80 + f, 1)[0]) for f in range(F)])
         spec = spec * torch.tensor([10.0 ** (3 * (f % 3) - 3) for f in range(F)], dtype=torch.float64)[:, None]
-    plan = pk.Plan(N, J, I, MODES[mode])
+    plan = pk.Plan(N, J, I, MODES[mode], TMODES[tmode])
     grid_ref = g.sh_inverse(spec)
     spec_ref = g.sh_forward(grid_ref)
     grid_g = plan.inverse(spec.to("cuda").contiguous())
@@ -80,9 +86,10 @@ def test_pair_mixed(pk, mode, N, J, I, F):
         assert ei < 5 * pi + 1e-12 and ef < 5 * pf + 1e-12, (f, ei, pi, ef, pf)
 
 
+@pytest.mark.parametrize("tmode", list(TMODES))
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("nmax_plus", [0, 1])
-def test_legendre_steps_mixed(pk, mode, nmax_plus):
+def test_legendre_steps_mixed(pk, mode, nmax_plus, tmode):
     """The Legendre-only entry points of a reduced-precision plan, T40 on 64 x
     128 (ragged tiles), 9 fields (two MFMA column tiles), degrees <= N (some
     (m, parity) blocks then have no rows) and <= N + 1, within the pair bound
@@ -91,7 +98,7 @@ def test_legendre_steps_mixed(pk, mode, nmax_plus):
     N, J, I, F = 40, 64, 128, 9
     nmax = N + nmax_plus
     g = ogrid(N, J, I)
-    plan = pk.Plan(N, J, I, MODES[mode])
+    plan = pk.Plan(N, J, I, MODES[mode], TMODES[tmode])
     gen = torch.Generator().manual_seed(21)
     ne = OH.nspec(N, N + 1)
     spec = torch.complex(torch.randn(ne, F, generator=gen, dtype=torch.float64),
@@ -117,10 +124,11 @@ def test_legendre_steps_mixed(pk, mode, nmax_plus):
         assert relerr(out[:, f][keep[:, 0]], ref[keep[:, 0]]) < BOUND_PAIR[mode], ("analysis", f)
 
 
+@pytest.mark.parametrize("tmode", list(TMODES))
 @pytest.mark.parametrize("mode", list(MODES))
-def test_plan_tables_mixed(pk, mode):
+def test_plan_tables_mixed(pk, mode, tmode):
     N, J, I = 63, 96, 192
-    plan = pk.Plan(N, J, I, MODES[mode])
+    plan = pk.Plan(N, J, I, MODES[mode], TMODES[tmode])
     mu, st, _, _ = __import__("oracle.quadrature", fromlist=["x"]).gauss_legendre(J)
     tol = {"fp32": 1e-7, "bf16x2": 2e-5, "bf16x3": 1e-7}[mode]
     for m in (0, 5, 40, 63):
@@ -130,13 +138,14 @@ def test_plan_tables_mixed(pk, mode):
             assert abs(got - P[n - m]).max() <= tol * max(1.0, abs(P[n - m]).max()), (m, n)
 
 
+@pytest.mark.parametrize("tmode", list(TMODES))
 @pytest.mark.parametrize("mode", list(MODES))
-def test_tendency_mixed(pk, mode):
-    print("CASE mixed tendency", mode, flush=True)
+def test_tendency_mixed(pk, mode, tmode):
+    print("CASE mixed tendency", mode, tmode, flush=True)
     N, J, I = 127, 192, 384
     g = ogrid(N, J, I)
     st = torch.tensor(workload.state(127, 1001))
-    plan = pk.Plan(N, J, I, MODES[mode])
+    plan = pk.Plan(N, J, I, MODES[mode], TMODES[tmode])
     fi, fe = pk.tendency(plan, pk.swe_params(), st[None].to("cuda").contiguous())
     ofe = OW.f_explicit(st, g, OW.SWEParams())
     for f in range(3):
@@ -145,14 +154,15 @@ def test_tendency_mixed(pk, mode):
         assert e < BOUND_TEND[mode], (f, e)
 
 
+@pytest.mark.parametrize("tmode", list(TMODES))
 @pytest.mark.parametrize("mode", list(MODES))
-def test_mlsdc_step_mixed(pk, mode):
+def test_mlsdc_step_mixed(pk, mode, tmode):
     """One T127/T63 step (GL 5/3, 2+2 sweeps x 4) with mixed tables on both
     levels; the error vs the FP64 oracle stays at the contraction level."""
-    print("CASE mixed mlsdc", mode, flush=True)
+    print("CASE mixed mlsdc", mode, tmode, flush=True)
     par = pk.swe_params()
-    lf = pk.Level(pk.Plan(127, 192, 384, MODES[mode]), par, pk.SDC_GAUSS_LOBATTO, 5)
-    lc = pk.Level(pk.Plan(63, 96, 192, MODES[mode]), par, pk.SDC_GAUSS_LOBATTO, 3)
+    lf = pk.Level(pk.Plan(127, 192, 384, MODES[mode], TMODES[tmode]), par, pk.SDC_GAUSS_LOBATTO, 5)
+    lc = pk.Level(pk.Plan(63, 96, 192, MODES[mode], TMODES[tmode]), par, pk.SDC_GAUSS_LOBATTO, 3)
     st = torch.tensor(workload.state(127, 1001))
     out = pk.Stepper(lf, lc, niter=4, nsweep_fine=2, nsweep_coarse=2).step(300.0, st.to("cuda"))
     of = OS.Level(OW.SWEProblem.__new__(OW.SWEProblem), "lobatto", 5)
@@ -166,5 +176,5 @@ def test_mlsdc_step_mixed(pk, mode):
                         interp_space=P)
     for f in range(3):
         e = relerr(out[f], ref[f])
-        print("mlsdc", mode, f, e, flush=True)
+        print("mlsdc", mode, tmode, f, e, flush=True)
         assert e < BOUND_STEP[mode], (f, e)
