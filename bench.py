@@ -48,6 +48,8 @@ NITER, NSWEEP = 4, 2
 SEED = 1005
 LARGE_DT = 60.0
 PRECISIONS = (("fp64", 0), ("fp32", 1), ("bf16x2", 2), ("bf16x3", 3))
+# Legendre tables in device memory (suffix "") or regenerated on the fly (no tables)
+TABLE_MODES = (("", 0), ("_onthefly", 1))
 
 
 def kcount(nmax, m, p):
@@ -87,13 +89,13 @@ def measured_traffic():
         return None
 
 
-def make_stepper(pk, fine, coarse, niter, nsweep, residual=False, precision=0):
+def make_stepper(pk, fine, coarse, niter, nsweep, residual=False, precision=0, table_mode=0):
     par = pk.swe_params()
-    pf = pk.Plan(fine["N"], fine["J"], fine["I"], precision)
+    pf = pk.Plan(fine["N"], fine["J"], fine["I"], precision, table_mode)
     lf = pk.Level(pf, par, pk.SDC_GAUSS_LOBATTO, fine["nodes"])
     lc = None
     if coarse:
-        pc = pk.Plan(coarse["N"], coarse["J"], coarse["I"], precision)
+        pc = pk.Plan(coarse["N"], coarse["J"], coarse["I"], precision, table_mode)
         lc = pk.Level(pc, par, pk.SDC_GAUSS_LOBATTO, coarse["nodes"])
     return pk.Stepper(lf, lc, niter=niter, nsweep_fine=nsweep, nsweep_coarse=nsweep, residual_check=residual)
 
@@ -132,24 +134,57 @@ def run_steps(torch, stepper, x0, steps, warmup, graph, dt=DT):
     return time.perf_counter() - t0, a
 
 
-def cpu_baseline(state_np):
-    """The oracle's MLSDC step on the host cores: one step of the same workload."""
+def _median3(fn):
+    """Median of 3 timed runs of fn() after one untimed warm-up run (seconds)."""
+    fn()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), ts
+
+
+def cpu_baseline(state_np, workload):
+    """The oracle (plain FP64 torch-CPU, all host threads) on the host cores,
+    each figure the median of 3 runs after 1 warm-up: one step of the
+    headline T255/T127 workload (the reported value), one T127/T63 step, one
+    15-field T255 transform pair, and one T127/T63 adjoint step (forward
+    recomputation + reverse pass by torch autograd through the oracle)."""
     import torch
     from oracle import sdc as OS
+    from oracle import sht as OH
     from oracle import swe as OW
-    pf = OW.SWEProblem(FINE["N"], FINE["J"], FINE["I"])
-    pc = OW.SWEProblem(COARSE["N"], COARSE["J"], COARSE["I"])
-    lf = OS.Level(pf, "lobatto", FINE["nodes"])
-    lc = OS.Level(pc, "lobatto", COARSE["nodes"])
-    R, P = OS.spectral_transfer(FINE["N"], COARSE["N"])
-    x = torch.tensor(state_np)
-    t0 = time.perf_counter()
-    OS.mlsdc_step(lf, lc, DT, x, niter=NITER, nsweep_fine=NSWEEP, nsweep_coarse=NSWEEP,
-                  restrict_space=R, interp_space=P)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": "1 step of the same T255/T127 (2,2)x4 workload (plain FP64 torch-CPU oracle), "
-                      f"{dt:.1f} s wall"}
+
+    def two_level(fine, coarse):
+        lf = OS.Level(OW.SWEProblem(fine["N"], fine["J"], fine["I"]), "lobatto", fine["nodes"])
+        lc = OS.Level(OW.SWEProblem(coarse["N"], coarse["J"], coarse["I"]), "lobatto", coarse["nodes"])
+        R, P = OS.spectral_transfer(fine["N"], coarse["N"])
+        return lambda x: OS.mlsdc_step(lf, lc, DT, x, niter=NITER, nsweep_fine=NSWEEP, nsweep_coarse=NSWEEP,
+                                       restrict_space=R, interp_space=P)
+
+    step_h = two_level(FINE, COARSE)
+    xh = torch.tensor(state_np)
+    t_h, ts_h = _median3(lambda: step_h(xh))
+    step_c1 = two_level(C1_FINE, C1_COARSE)
+    x1 = torch.tensor(workload.state(127, workload.SEEDS["mlsdc_T127"][0]))
+    t_c1, _ = _median3(lambda: step_c1(x1))
+    g = OH.Grid(FINE["N"], FINE["J"], FINE["I"])
+    spec = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1))
+    t_c2, _ = _median3(lambda: g.sh_forward(g.sh_inverse(spec)))
+    x3 = torch.tensor(workload.state(127, workload.SEEDS["adjoint_T127"][0]))
+    w = torch.where(OH.orders(127) == 0, 1.0, 2.0).to(torch.float64)
+
+    def adjoint_step():
+        x = x3.clone().requires_grad_(True)
+        y = step_c1(x)
+        (0.5 * (w * (y[0].real ** 2 + y[0].imag ** 2)).sum()).backward()
+    t_c3, _ = _median3(adjoint_step)
+    return {"value": 1.0 / t_h, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "median of 3 runs after 1 warm-up of one step of the same T255/T127 (2,2)x4 workload "
+                      f"(plain FP64 torch-CPU oracle; runs {', '.join(f'{t:.1f}' for t in ts_h)} s)",
+            "s_per_step_T255_T127": t_h, "s_per_step_T127_T63": t_c1, "s_per_pair_T255_F15": t_c2,
+            "s_per_adjoint_step_T127_T63": t_c3}
 
 
 def variants_extra(pk, torch, workload, x0, steps, graph):
@@ -203,13 +238,14 @@ def copy_bandwidth(torch, mib=2048):
 
 
 def legendre_extra(pk, torch, workload):
-    """Legendre GFLOP/s, T255, 15 fields (one launch per direction), per precision."""
+    """Legendre GFLOP/s, T255, 15 fields (one launch per direction), per
+    precision, with tables in device memory and without (on the fly)."""
     extra = {}
     spec0 = torch.tensor(workload.states(255, workload.SEEDS["pair_T255"]).reshape(15, -1), device="cuda")
     fl = legendre_flops(255, 384, 15, 255)
     ref_grid = ref_spec = None
-    for pname, prec in PRECISIONS:
-        plan = pk.Plan(255, 384, 768, prec)
+    for (pname, prec), (tname, tmode) in ((p, t) for t in TABLE_MODES for p in PRECISIONS):
+        plan = pk.Plan(255, 384, 768, prec, tmode)
         spec = spec0.clone()
         grid = plan.inverse(spec)
         spec_b = plan.forward(grid)
@@ -237,7 +273,7 @@ def legendre_extra(pk, torch, workload):
                     for f in range(15))
         err_s = max((torch.linalg.vector_norm(spec_b[f] - ref_spec[f]) / torch.linalg.vector_norm(ref_spec[f])).item()
                     for f in range(15))
-        extra[f"legendre_T255_F15_{pname}"] = {
+        extra[f"legendre_T255_F15_{pname}{tname}"] = {
             "synthesis_gflops": fl / (syn_us * 1e-6) / 1e9, "analysis_gflops": fl / (an_us * 1e-6) / 1e9,
             "synthesis_us": syn_us, "analysis_us": an_us, "flop_per_direction": fl,
             "max_rel_err_vs_fp64_inverse": err_g, "max_rel_err_vs_fp64_roundtrip": err_s,
@@ -252,18 +288,19 @@ def rel_errs(torch, x, ref):
 
 
 def mixed_steps_extra(pk, torch, x0, steps, graph):
-    """The benchmark step with reduced-precision Legendre contractions."""
+    """The benchmark step with reduced-precision Legendre contractions, with
+    tables in device memory and without (on the fly)."""
     extra = {}
     ref_state = None
     n = max(5, steps // 2)
-    for pname, prec in PRECISIONS:
-        stp = make_stepper(pk, FINE, COARSE, NITER, NSWEEP, precision=prec)
+    for (pname, prec), (tname, tmode) in ((p, t) for t in TABLE_MODES for p in PRECISIONS):
+        stp = make_stepper(pk, FINE, COARSE, NITER, NSWEEP, precision=prec, table_mode=tmode)
         one = stp.step(DT, x0.clone())
         torch.cuda.synchronize()
         if ref_state is None:
             ref_state = one.clone()
         sp, _ = run_steps(torch, stp, x0, n, 2, graph)
-        extra[f"steps_per_s_T255_T127_{pname}"] = {"value": n / sp,
+        extra[f"steps_per_s_T255_T127_{pname}{tname}"] = {"value": n / sp,
                                                    "one_step_rel_err_vs_fp64": rel_errs(torch, one, ref_state)}
         del stp
     return extra
@@ -300,21 +337,21 @@ def adjoint_extra(pk, torch, workload):
 def large_extra(pk, torch, workload, graph):
     """Fine T1023 (3072 x 1536, 5 Gauss-Radau-right collocation points) over
     coarse T511 (1536 x 768, 3), (2,2) x 4, dt = 60 s, 5 timed steps per
-    precision; Legendre tables held in HBM."""
+    precision; Legendre tables held in HBM, and regenerated on the fly."""
     x = torch.tensor(workload.state(1023, workload.SEEDS["mlsdc_T1023"][0]), device="cuda")
     par = pk.swe_params()
     extra = {}
     ref = None
-    for pname, prec in PRECISIONS:
-        lf = pk.Level(pk.Plan(1023, 1536, 3072, prec), par, pk.SDC_RADAU_RIGHT, 6)
-        lc = pk.Level(pk.Plan(511, 768, 1536, prec), par, pk.SDC_RADAU_RIGHT, 4)
+    for (pname, prec), (tname, tmode) in ((p, t) for t in TABLE_MODES for p in PRECISIONS):
+        lf = pk.Level(pk.Plan(1023, 1536, 3072, prec, tmode), par, pk.SDC_RADAU_RIGHT, 6)
+        lc = pk.Level(pk.Plan(511, 768, 1536, prec, tmode), par, pk.SDC_RADAU_RIGHT, 4)
         st = pk.Stepper(lf, lc, niter=NITER, nsweep_fine=NSWEEP, nsweep_coarse=NSWEEP)
         one = st.step(LARGE_DT, x.clone())
         torch.cuda.synchronize()
         if ref is None:
             ref = one.clone()
         secs, _ = run_steps(torch, st, x, 5, 1, graph, dt=LARGE_DT)
-        extra[f"steps_per_s_T1023_T511_radau_{pname}"] = {"value": 5 / secs,
+        extra[f"steps_per_s_T1023_T511_radau_{pname}{tname}"] = {"value": 5 / secs,
                                                            "one_step_rel_err_vs_fp64": rel_errs(torch, one, ref)}
         del st, lf, lc
     return extra
@@ -557,7 +594,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": n * 8, "bytes_written": n * 8}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(state_np)
+        out["cpu_baseline"] = cpu_baseline(state_np, workload)
     print(json.dumps(out), flush=True)
 
 
