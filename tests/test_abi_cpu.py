@@ -55,14 +55,13 @@ def test_argument_validation_without_device():
     assert L.mlsdc_step_noalloc(None, None, None, 1.0, None, None, None, None) == -1
 
 
-def test_host_gauss_matches_oracle():
-    from oracle.quadrature import gauss_legendre
+def test_host_gauss_matches_oracle(oracle_gauss):
     L = ctypes.CDLL(pk.LIB_PATH)
-    for J in (48, 192, 384):
+    for J in (48, 192, 384, 768, 1536):             # up to the T1023 grid's latitudes
         mu, st, c2, w = (np.empty(J) for _ in range(4))
         assert L.shx_host_gauss(J, mu.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
                                 c2.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p)) == 0
-        omu, ost, oc2, ow = gauss_legendre(J)
+        omu, ost, oc2, ow = oracle_gauss(J)
         # both are correctly rounded from >= 34-digit values: equal to the last bit or one ulp
         assert np.all(np.abs(mu - omu) <= np.spacing(np.abs(omu)) + 1e-300)
         assert np.all(np.abs(st - ost) <= np.spacing(ost))

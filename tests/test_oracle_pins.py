@@ -57,6 +57,28 @@ def test_gauss_exactness_and_library(J):
     assert np.abs(np.sort(w) - np.sort(ww)).max() < 1e-12 * ww.max()
 
 
+@pytest.mark.parametrize("J", [768, 1536])
+def test_gauss_exactness_large(J, oracle_gauss):
+    """The latitude counts of the T511 and T1023 grids: monomials up to degree
+    2J-1 and the orthogonality of the Legendre polynomials P_0..P_{J-1} (Bonnet's
+    recurrence in FP64; every product has degree <= 2J-2) hold to rounding."""
+    mu, st, c2, w = oracle_gauss(J)
+    assert np.all(np.diff(mu) < 0)
+    assert np.allclose(st ** 2 + mu ** 2, 1.0, atol=3e-16, rtol=0)
+    assert np.array_equal(mu, -mu[::-1]) and np.array_equal(w, w[::-1])
+    for k in range(0, 2 * J, 7):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.dot(w, mu ** k) - exact) < 1e-14
+    P = np.zeros((J, J))
+    P[0], P[1] = 1.0, mu
+    for n in range(1, J - 1):
+        P[n + 1] = ((2 * n + 1) * mu * P[n] - n * P[n - 1]) / (n + 1)
+    G = (P * w) @ P.T
+    assert np.abs(G - np.diag(2.0 / (2 * np.arange(J) + 1))).max() < 5e-15
+    x, _ = np.polynomial.legendre.leggauss(J)
+    assert np.abs(np.sort(mu) - x).max() < 1e-15
+
+
 # ---------------------------------------------------------------- Legendre functions
 def test_plm_closed_forms():
     mu, st, _, _ = Qd.gauss_legendre(11)
