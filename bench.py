@@ -358,11 +358,17 @@ def large_extra(pk, torch, workload, graph):
 
 
 # Gaussian-dome temporal refinement (Sec. 5.2): schemes as (name, Gauss-
-# Lobatto nodes per level from the finest, iterations), one sweep per level
-# and iteration (the paper's setting); levels T255 / T127 / T63.
-DOME_SCHEMES = (("SDC(3,4)", (3,), 4), ("MLSDC(3,2,2,1/2)", (3, 2), 2), ("SDC(5,8)", (5,), 8),
-                ("MLSDC(5,3,4,1/2)", (5, 3), 4), ("MLSDC(5,3,7,1/2)", (5, 3), 7),
-                ("3-level MLSDC(5,3,2;4)", (5, 3, 2), 4))
+# Lobatto nodes per level from the finest, iterations, truncation per level),
+# one sweep per level and iteration (the paper's setting).  Besides the
+# paper's schemes: spatial coarsening only (M_f = M_c), temporal coarsening
+# only (both levels T255), and a milder spatial coarsening (T170, ratio 2/3).
+DOME_SCHEMES = (("SDC(3,4)", (3,), 4, (255,)), ("MLSDC(3,2,2,1/2)", (3, 2), 2, (255, 127)),
+                ("SDC(5,8)", (5,), 8, (255,)),
+                ("MLSDC(5,3,4,1/2)", (5, 3), 4, (255, 127)), ("MLSDC(5,3,7,1/2)", (5, 3), 7, (255, 127)),
+                ("3-level MLSDC(5,3,2;4)", (5, 3, 2), 4, (255, 127, 63)),
+                ("MLSDC(3,3,2,1/2)", (3, 3), 2, (255, 127)), ("MLSDC(3,2,2,1)", (3, 2), 2, (255, 255)),
+                ("MLSDC(3,2,2,2/3)", (3, 2), 2, (255, 170)))
+DOME_PLANS = {255: (255, 384, 768), 170: (170, 256, 512), 127: (127, 192, 384), 63: (63, 96, 192)}
 DOME_DTS = (30.0, 60.0, 120.0, 240.0, 480.0, 960.0)
 DOME_REF_DT = 15.0
 
@@ -393,41 +399,61 @@ def advance(torch, stepper, x0, dt, nsteps):
     return a, (time.perf_counter() - t0) / (nsteps - 1)
 
 
-def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
+def degrees(N):
+    """Degree n of each coefficient of the m-major spectral layout."""
+    return np.concatenate([np.arange(m, N + 1) for m in range(N + 1)])
+
+
+def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS, only=None):
     """Temporal refinement on the Gaussian dome over t_end seconds: L_inf
     errors of the geopotential and vorticity on the fine grid (and the
-    area-weighted L2 error of the geopotential) against
-    SDC(5,8) at dt = 60 s, observed orders between successive dt, seconds
-    per step, and the observed speedup of each MLSDC scheme over its
-    single-level counterpart at matched geopotential error (cost of the
-    single-level scheme interpolated log-log in its error)."""
+    area-weighted L2 error of the geopotential) against SDC(5,8) at
+    dt = 15 s, observed orders between successive dt, seconds per step, and
+    the observed speedup of each MLSDC scheme over its single-level
+    counterpart at matched geopotential error (cost of the single-level
+    scheme interpolated log-log in its error).  Also the part of the
+    reference's geopotential that a coarse level of truncation T_c cannot
+    hold (grid maximum of the degrees n > T_c, and the largest coefficient
+    magnitude max_m |Phi_n^m| at n = T_c + 1), at t = 0 and t_end, and per
+    scheme the grid maximum of the error's degrees n > 127."""
     par = pk.swe_params(phibar=workload.dome_phibar())
-    plans = [pk.Plan(c["N"], c["J"], c["I"]) for c in (FINE, COARSE, dict(N=63, J=96, I=192))]
-    pf = plans[0]
+    plans = {N: pk.Plan(*v) for N, v in DOME_PLANS.items()}
+    pf = plans[255]
     mu, _, wq = pf.latitudes()
     wgt = torch.tensor(wq, device="cuda")[:, None] / (2.0 * FINE["I"])   # area weights, sum 1
     grid = torch.tensor(workload.dome_grid(mu, FINE["I"])[None], device="cuda")
     x0 = torch.zeros(3, workload.nspec(FINE["N"]), dtype=torch.complex128, device="cuda")
     x0[0] = pf.forward(grid)[0]
 
-    def stepper(nodes, k):
-        lv = [pk.Level(plans[l], par, pk.SDC_GAUSS_LOBATTO, n) for l, n in enumerate(nodes)]
+    def stepper(nodes, k, trunc):
+        lv = [pk.Level(plans[t], par, pk.SDC_GAUSS_LOBATTO, n) for t, n in zip(trunc, nodes)]
         return pk.MultiStepper(lv, niter=k, nsweeps=1)
 
     def fields(x):
         return pf.inverse(x[0:2].contiguous())
 
-    ref, _ = advance(torch, stepper((5,), 8), x0, DOME_REF_DT, int(round(t_end / DOME_REF_DT)))
+    ref, _ = advance(torch, stepper((5,), 8, (255,)), x0, DOME_REF_DT, int(round(t_end / DOME_REF_DT)))
     rg = fields(ref)
-    out = {"t_end_s": t_end, "reference": f"SDC(5,8), dt = {DOME_REF_DT:g} s", "dt_s": list(DOME_DTS),
-           "alpha": workload.DOME["alpha"], "schemes": {}}
-    out["dt_s"] = list(dts)
-    for name, nodes, k in DOME_SCHEMES:
-        errs, errz, err2, cost = [], [], [], []
-        st = stepper(nodes, k)
+    out = {"t_end_s": t_end, "reference": f"SDC(5,8), dt = {DOME_REF_DT:g} s", "dt_s": list(dts),
+           "alpha": workload.DOME["alpha"], "schemes": {}, "truncated_part_phi": {}}
+    deg = torch.tensor(degrees(FINE["N"]), device="cuda")
+    for tc in (127, 170):
+        tp = {}
+        for tag, x in (("t0", x0), ("t_end", ref)):
+            hi = torch.where(deg > tc, x[0], torch.zeros_like(x[0]))
+            tp["grid_max_" + tag] = pf.inverse(hi[None].contiguous())[0].abs().max().item()
+            tp["max_coef_n%d_" % (tc + 1) + tag] = x[0][deg == tc + 1].abs().max().item()
+        out["truncated_part_phi"]["T%d" % tc] = tp
+    for name, nodes, k, trunc in DOME_SCHEMES:
+        if only and name not in only:
+            continue
+        errs, errz, err2, cost, errhi = [], [], [], [], []
+        st = stepper(nodes, k, trunc)
         for dt in dts:
             x, sps = advance(torch, st, x0, dt, int(round(t_end / dt)))
             d = fields(x) - rg
+            dhi = torch.where(deg > 127, x[0] - ref[0], torch.zeros_like(x[0]))
+            errhi.append(pf.inverse(dhi[None].contiguous())[0].abs().max().item())
             errs.append(d[0].abs().max().item())
             errz.append(d[1].abs().max().item())
             err2.append(math.sqrt((wgt * d[0] * d[0]).sum().item()))
@@ -435,9 +461,13 @@ def dome_extra(pk, torch, workload, t_end=86400.0, dts=DOME_DTS):
         order = [math.log2(errs[i + 1] / errs[i]) if errs[i] > 0 and errs[i + 1] > 0 else float("nan")
                  for i in range(len(errs) - 1)]
         out["schemes"][name] = {"linf_phi": errs, "linf_zeta": errz, "l2_phi": err2, "order_phi": order,
-                                "gpu_seconds": cost}
+                                "gpu_seconds": cost, "linf_phi_degrees_above_127": errhi}
+        del st
+        print(f"# dome {name}: linf_phi {['%.3g' % e for e in errs]}", file=sys.stderr, flush=True)
     for ml, sl in (("MLSDC(3,2,2,1/2)", "SDC(3,4)"), ("MLSDC(5,3,4,1/2)", "SDC(5,8)"),
-                   ("3-level MLSDC(5,3,2;4)", "SDC(5,8)")):
+                   ("3-level MLSDC(5,3,2;4)", "SDC(5,8)"), ("MLSDC(3,2,2,2/3)", "SDC(3,4)")):
+        if ml not in out["schemes"] or sl not in out["schemes"]:
+            continue
         m, s1 = out["schemes"][ml], out["schemes"][sl]
         for key, tag in (("linf_phi", ""), ("l2_phi", "_l2")):
             pts = [(a, b) for a, b in zip(s1[key], s1["gpu_seconds"]) if a > 0 and math.isfinite(a)]
@@ -470,6 +500,8 @@ def main():
                     help="simulated time of the Gaussian-dome refinement study (--only dome)")
     ap.add_argument("--dome-dts", default=",".join(f"{v:g}" for v in DOME_DTS),
                     help="comma-separated time steps (s) of the Gaussian-dome study")
+    ap.add_argument("--dome-schemes", default=None,
+                    help="semicolon-separated subset of the Gaussian-dome schemes (default: all)")
     ap.add_argument("--dome-alpha", type=float, default=None,
                     help="dome width parameter alpha in exp(-alpha (d/a)^2) (default: the workload's)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -499,7 +531,8 @@ def main():
                "adjoint": lambda: adjoint_extra(pk, torch, workload),
                "large": lambda: large_extra(pk, torch, workload, graph),
                "dome": lambda: dome_extra(pk, torch, workload, args.dome_hours * 3600.0,
-                                          tuple(float(v) for v in args.dome_dts.split(",")))}[args.only]
+                                          tuple(float(v) for v in args.dome_dts.split(",")),
+                                          args.dome_schemes.split(";") if args.dome_schemes else None)}[args.only]
         print(json.dumps({"only": args.only, "extra": run()}), flush=True)
         return
 

@@ -223,7 +223,9 @@ size_t mlsdc_workspace_bytes(const sdc_level* fine, const sdc_level* coarse, con
  * initialisation; transfer by spectral truncation / zero padding and
  * Lagrange time interpolation, Sec. 4.3.3), or of single-level SDC when
  * coarse is NULL (step A only, niter sweeps of nsweep_fine).  The coarse plan
- * must have a smaller truncation than the fine plan.  theta_n_dev,
+ * must not have a larger truncation than the fine plan, nor the coarse level
+ * more nodes (equal truncations coarsen in time only, equal node counts in
+ * space only).  theta_n_dev,
  * theta_np1_dev: [3][nspec_fine] complex (may alias).  status_dev: NULL or
  * device double[2]: [0] = FP64 collocation residual of the fine nodes
  * max_m ||r^m||_2 / ||Theta^0||_2 if opts->residual_check, else 0;
@@ -260,8 +262,8 @@ int mlsdc_step_noalloc(const sdc_level* fine, const sdc_level* coarse, const mls
  * (eq. tau_term_level_l+1) and runs nsweep[l] sweeps; going up, the
  * corrections of Theta, F_I and F_E of level l are interpolated into level
  * l-1.  Node 0 of every coarser level is the restricted initial value,
- * evaluated once per step.  Levels: one node kind, strictly decreasing
- * truncation, non-increasing node counts, alias-free grids.  With two levels
+ * evaluated once per step.  Levels: one node kind, non-increasing
+ * truncations and node counts, alias-free grids.  With two levels
  * this launches what mlsdc_step launches (no residual check).
  * theta_n_dev, theta_np1_dev: [3][nspec] of levels[0]'s plan (may alias);
  * ws: device workspace of mlsdc_multi_workspace_bytes bytes (16-byte

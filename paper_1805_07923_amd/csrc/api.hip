@@ -422,7 +422,7 @@ bool valid_levels(const sdc_level* const* lv, int L) {
     if (!lv || L < 1 || L > SHX_MAX_LEVELS) return false;
     for (int l = 0; l < L; ++l) {
         if (!lv[l]) return false;
-        if (l > 0 && (lv[l]->kind != lv[0]->kind || lv[l]->plan->N >= lv[l - 1]->plan->N ||
+        if (l > 0 && (lv[l]->kind != lv[0]->kind || lv[l]->plan->N > lv[l - 1]->plan->N ||
                       lv[l]->nnodes > lv[l - 1]->nnodes))
             return false;
     }
@@ -1042,7 +1042,7 @@ int mlsdc_step_adj(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o
         (cl && o->nsweep_coarse < 1) || !aligned16(theta_n) || !aligned16(lam_np1) || !aligned16(lam_n) ||
         !aligned16(ws) || lam_n == lam_np1 || lam_n == theta_n)
         return SHX_EINVAL;
-    if (cl && (cl->kind != fl->kind || cl->plan->N >= fl->plan->N || cl->nnodes > fl->nnodes))
+    if (cl && (cl->kind != fl->kind || cl->plan->N > fl->plan->N || cl->nnodes > fl->nnodes))
         return SHX_EINVAL;
     if (!alias_free(fl->plan) || (cl && !alias_free(cl->plan))) return SHX_ESHAPE;
     if (!adjoint_length_supported(fl->plan->I) || (cl && !adjoint_length_supported(cl->plan->I)) ||
@@ -1303,7 +1303,7 @@ int mlsdc_step(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, do
         (cl && o->nsweep_coarse < 1) || !aligned16(theta_n) || !aligned16(theta_np1) || !aligned16(ws) ||
         !aligned16(status))
         return SHX_EINVAL;
-    if (cl && (cl->kind != fl->kind || cl->plan->N >= fl->plan->N || cl->nnodes > fl->nnodes))
+    if (cl && (cl->kind != fl->kind || cl->plan->N > fl->plan->N || cl->nnodes > fl->nnodes))
         return SHX_EINVAL;
     if (!alias_free(fl->plan) || (cl && !alias_free(cl->plan))) return SHX_ESHAPE;
     if (!ws || wsb < mlsdc_workspace_bytes(fl, cl, o)) return SHX_EWORKSPACE;

@@ -6,7 +6,9 @@ tolerance as the other parity tests (1e-12 normwise per field):
     3 * 2^k longitude count (12 x 48), T10 on 16 x 32;
   * two-node (trapezoidal) Gauss-Lobatto SDC, the smallest node set;
   * a coarse level with as many nodes as the fine one (coarsening in space
-    only: the time transfers are identities);
+    only: the time transfers are identities), and one with the fine level's
+    truncation (coarsening in time only: the spectral transfers are
+    identities), through mlsdc_step and the multi-level entry point;
   * zero iterations (the step returns the spread initial value);
   * empty inputs (no fields, no states) rejected with SHX_EINVAL before any
     launch, and the adjoints' refusal of reduced-precision plans."""
@@ -112,6 +114,25 @@ def test_mlsdc_equal_node_counts(pk):
     of = OS.Level(oracle_problem(31, 48, 96), "lobatto", 3)
     oc = OS.Level(oracle_problem(15, 24, 48), "lobatto", 3)
     R, P = OS.spectral_transfer(31, 15)
+    ref = OS.mlsdc_step(of, oc, 600.0, st, niter=2, restrict_space=R, interp_space=P)
+    for f in range(3):
+        assert relerr(out[f], ref[f]) < TOL, f
+
+
+def test_mlsdc_equal_truncation(pk):
+    """Two T31 levels with three and two Gauss-Lobatto nodes: only the time
+    is coarsened, restriction and interpolation in space are the identity."""
+    print("CASE mlsdc equal truncation", flush=True)
+    par = pk.swe_params()
+    lf = pk.Level(pk.Plan(31, 48, 96), par, pk.SDC_GAUSS_LOBATTO, 3)
+    lc = pk.Level(pk.Plan(31, 48, 96), par, pk.SDC_GAUSS_LOBATTO, 2)
+    st = torch.tensor(workload.state(31, 1000))
+    out = pk.Stepper(lf, lc, niter=2, nsweep_fine=1, nsweep_coarse=1).step(600.0, st.to("cuda"))
+    multi = pk.MultiStepper([lf, lc], niter=2, nsweeps=1).step(600.0, st.to("cuda"))
+    assert torch.equal(out, multi)
+    of = OS.Level(oracle_problem(31, 48, 96), "lobatto", 3)
+    oc = OS.Level(oracle_problem(31, 48, 96), "lobatto", 2)
+    R, P = OS.spectral_transfer(31, 31)
     ref = OS.mlsdc_step(of, oc, 600.0, st, niter=2, restrict_space=R, interp_space=P)
     for f in range(3):
         assert relerr(out[f], ref[f]) < TOL, f
