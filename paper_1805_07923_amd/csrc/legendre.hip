@@ -186,8 +186,11 @@ __global__ void k_plm_one(const double* __restrict__ mu, const double* __restric
 // read from the table: out[s][p][jp][m][f0+f] = sum_{n = m+p mod 2} P^m_n(mu_jp) cin[s][ext(m, n)][f0+f].
 // gx (N+1) blocks (gx = ceil(Jh/64), all blocks of an order on one XCD),
 // 256 threads, one wavefront per 16 latitudes.  Per order the sum over n is
-// a (16 latitudes) x (n) x (2 NF real columns) product, done by
-// v_mfma_f64_16x16x4f64 with the 4-deep inner dimension taken by four
+// a (16 latitudes) x (n) x (2 NF real columns) product, done by the
+// four-block v_mfma_f64_4x4x4f64 (block b: latitudes 4b..4b+3, one group of
+// four real columns; ceil(NF/2) instructions per degree, so that a product
+// of fewer than 8 fields keeps no idle columns, as a 16-column tile would)
+// with the 4-deep inner dimension taken by four
 // degree segments: lane (i, q) = (lane % 16, lane / 16) owns latitude i and
 // segment q of the current round, starts from the stored exact pair
 // (P_{m+gL}, P_{m+gL+1}) and advances two degrees per step with the
@@ -195,7 +198,7 @@ __global__ void k_plm_one(const double* __restrict__ mu, const double* __restric
 // P_n = (mu P_{n-1} - eps_{n-1} P_{n-2}) / eps_n, in FP64.  Each step feeds
 // one even-degree and one odd-degree product (E and O accumulators, the two
 // hemisphere halves); the B operand is the lane's coefficient row of that
-// degree, column lane % 16.  STAGE = 0: cin holds coefficients in the ext
+// degree, column 4 g + lane % 4 for column group g.  STAGE = 0: cin holds coefficients in the ext
 // layout, F per entry; STAGE = 1: cin holds states [S][3][nspec] and the
 // staged rows are the tendency's grid fields (swe_prep_row; NF = F = 4);
 // STAGE = 2: cin holds F_E cotangents [S][3][nspec] and the staged rows are
@@ -222,10 +225,10 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
                                                    const double* __restrict__ nn1) {
     static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
     constexpr int U = 8;                                // degrees per batch of LDS reads
+    constexpr int NG = (2 * NF + 3) / 4;                // groups of 4 real columns
     extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, q = lane >> 4;
-    const int ic = i < 2 * NF ? i : 2 * NF - 1;         // B column (clamped; columns >= 2 NF unused)
     const LegTile tile = leg_tile(gx, N + 1, 1);
     const int m = tile.m;
     const int jw = tile.x * 64 + wv * 16;               // first latitude of this wavefront
@@ -237,13 +240,18 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
     const double x = mu[active ? jp : 0];
     const double2* ckm = ck + ckoff[m] + (active ? jp : 0);
     double2* rsh = csh + 4 * (Lmax * NF + 2);
-    const double* cq = reinterpret_cast<const double*>(csh + q * SC) + ic;   // segment q, column ic
+    const double* cq = reinterpret_cast<const double*>(csh + q * SC);        // segment q
+    int cg[NG];                                         // B columns 4 g + lane % 4 (clamped; >= 2 NF unused)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) cg[g] = min(4 * g + (lane & 3), 2 * NF - 1);
     const double2* rq = rsh + q * SR;
     const double2* rcm = rc + ext_idx(N, m, m);
     const double2* pfm = pf + ext_idx(N, m, m);
     const double ia = 1.0 / a, a2 = a * a, ia2 = ia * ia;
     for (int s = 0; s < S; ++s) {
-        v4d accE = {0.0, 0.0, 0.0, 0.0}, accO = {0.0, 0.0, 0.0, 0.0};
+        double accE[NG], accO[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) accE[g] = accO[g] = 0.0;
         for (int r = 0; r < R; ++r) {
             const int kr0 = 4 * r * L;
             if (kr0 >= Ku) break;                       // uniform
@@ -282,11 +290,12 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
             double pe = c0.x, po = c0.y;                // P_{m+gL}, P_{m+gL+1}
             for (int t = 0; t < L; t += U) {
                 double2 rr[U];
-                double bb[U];
+                double bb[U][NG];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     rr[u] = rq[t + u];
-                    bb[u] = cq[(t + u) * 2 * NF];
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) bb[u][g] = cq[(t + u) * 2 * NF + cg[g]];
                 }
 #pragma unroll
                 for (int u = 0; u < U; u += 2) {
@@ -295,21 +304,25 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
                         po = fma(rr[u + 1].x * x, ne, -(rr[u + 1].y * po));
                         pe = ne;
                     }
-                    accE = __builtin_amdgcn_mfma_f64_16x16x4f64(pe, bb[u], accE, 0, 0, 0);
-                    accO = __builtin_amdgcn_mfma_f64_16x16x4f64(po, bb[u + 1], accO, 0, 0, 0);
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        accE[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(pe, bb[u][g], accE[g], 0, 0, 0);
+                        accO[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(po, bb[u + 1][g], accO[g], 0, 0, 0);
+                    }
                 }
             }
         }
-        // D layout (f64 16x16x4): the lane holds rows q + 4 rr (latitudes) of column i
-        if (jw < Jh && i < 2 * NF) {
+        // D layout (f64 4x4x4, 4 blocks): lane 4 b + j + 16 r holds row r of
+        // block b (latitude 4 b + r) and column j of the group
+        const int jr = jw + 4 * (i >> 2) + q;
+        if (jw < Jh && jr < Jh) {
+            double* o0 = reinterpret_cast<double*>(out + s * out_stride + ((long long)jr * (N + 1) + m) * F + f0);
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int jr = jw + q + 4 * rr;
-                if (jr < Jh) {
-                    double* o0 = reinterpret_cast<double*>(out + s * out_stride +
-                                                           ((long long)jr * (N + 1) + m) * F + f0) + i;
-                    o0[0] = accE[rr];
-                    o0[(long long)Jh * (N + 1) * F * 2] = accO[rr];
+            for (int g = 0; g < NG; ++g) {
+                const int c = 4 * g + (lane & 3);
+                if (c < 2 * NF) {
+                    o0[c] = accE[g];
+                    o0[c + (long long)Jh * (N + 1) * F * 2] = accO[g];
                 }
             }
         }
