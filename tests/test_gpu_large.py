@@ -8,12 +8,18 @@ by tests/golden/make_large_T1023.py (oracle only) and stored as the full
 2-norm of every field plus the values at 512 seeded positions per field.
 Each GPU result is checked
   * normwise, with the error norm estimated from the samples
-    (sqrt(n / n_samples * sum |d_i|^2) / ||ref||), against 1e-12 in FP64, or,
-    for the tendency and the step, against ten times the oracle's own
-    sensitivity to the order of its latitude sums when that is larger (at
-    T1023 the Laplacian's n(n+1) ~ 1e6 lifts the rounding noise of the
-    kinetic-energy analysis in the divergence tendency to a few 1e-12: the
-    oracle itself moves that much when its latitude sums run south to north);
+    (sqrt(n / n_samples * sum |d_i|^2) / ||ref||), against 1e-12 in FP64;
+    for the tendency, against the oracle's own sensitivity where that is
+    larger: at T1023 the Laplacian's n(n+1) ~ 1e6 lifts the rounding noise
+    of the kinetic-energy analysis at high degrees, so the oracle's
+    divergence tendency moves by 5e-12 .. 4e-11 when only the rounding of
+    its sums or of its Legendre functions changes
+    (tests/golden/make_large_sensitivity_T1023.py: latitude order,
+    synthesis degree order, complex FFTs, functions moved within their last
+    bit, all of these at once, and the functions from the FP64 three-term
+    recurrence as an on-the-fly transform generates them); the bound is
+    1.25 times the largest of these per field.  The step is checked against
+    ten times its latitude-order sensitivity (below 1e-12 here);
   * by its own full 2-norm against the stored one (a check over every entry);
 and by properties that hold at any size (round trip of the pair, mass
 conservation of the step)."""
@@ -31,16 +37,19 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLD = os.path.join(HERE, "golden", "large_T1023.json")
+SENS = os.path.join(HERE, "golden", "large_T1023_sensitivity.json")
 TOL = 1e-12
-# Stated errors of the reduced precisions against the FP64 oracle (largest
-# field).  The divergence tendency is the worst conditioned result at T1023:
-# the Laplacian's n(n+1) ~ 1e6 multiplies the contraction error of the
-# kinetic-energy analysis at high degrees, where the tendency itself is small
-# (measured 1.4e-2 FP32, 8.1e-2 split-BF16 x2, 1.3e-3 x3); a 60 s step adds
-# dt F to the state and stays near the contraction level (1.3e-6, 8.0e-5,
-# 9.3e-7).
+MIXED = os.path.join(HERE, "golden", "large_T1023_mixed.json")
+# Reduced precisions: the tendency's error against the FP64 oracle is bounded
+# by five times the error that the CPU emulation of the same contractions
+# (oracle.mixed, stored by tests/golden/make_large_mixed_T1023.py) makes on
+# the full T1023 tendency, per field.  The divergence tendency is the worst
+# conditioned result: the Laplacian's n(n+1) ~ 1e6 multiplies the
+# contraction error of the kinetic-energy analysis at high degrees, where the
+# tendency itself is small.  A 60 s step adds dt F to the state and stays
+# near the contraction level.
 BOUND_STEP = {1: 5e-6, 2: 3e-4, 3: 5e-6}
-BOUND_TEND = {1: 5e-2, 2: 3e-1, 3: 5e-3}
+MODE_NAMES = {1: "fp32", 2: "bf16x2", 3: "bf16x3"}
 
 
 @pytest.fixture(scope="module")
@@ -78,18 +87,27 @@ def sampled_error(x, rec):
     return est, full
 
 
-def check(x, recs, tol, what, sens=None):
+def tendency_sensitivity(gold):
+    """Per field, the largest stored change of the oracle's F_E under a change
+    of rounding only."""
+    with open(SENS) as fh:
+        sens = json.load(fh)
+    rows = [gold["f_explicit_order_sensitivity"]] + [v for k, v in sens.items() if k != "config"]
+    return [max(r[f] for r in rows) for f in range(3)]
+
+
+def check(x, recs, tol, what, sens=None, factor=10.0):
     for f, rec in enumerate(recs):
-        t = max(tol, 10.0 * sens[f]) if sens else tol
+        t = max(tol, factor * sens[f]) if sens else tol
         est, full = sampled_error(x[f], rec)
         print(what, f, est, full, "bound", t, flush=True)
         assert est < t and full < t, (what, f, est, full, t)
 
 
-def levels(pk, prec):
+def levels(pk, prec, tmode=0):
     par = pk.swe_params()
-    lf = pk.Level(pk.Plan(1023, 1536, 3072, prec), par, pk.SDC_RADAU_RIGHT, 6)
-    lc = pk.Level(pk.Plan(511, 768, 1536, prec), par, pk.SDC_RADAU_RIGHT, 4)
+    lf = pk.Level(pk.Plan(1023, 1536, 3072, prec, tmode), par, pk.SDC_RADAU_RIGHT, 6)
+    lc = pk.Level(pk.Plan(511, 768, 1536, prec, tmode), par, pk.SDC_RADAU_RIGHT, 4)
     return lf, lc
 
 
@@ -125,7 +143,7 @@ def test_large_tendency_fp64(pk, gold, state):
     print("CASE large tendency T1023 fp64", flush=True)
     plan = pk.Plan(1023, 1536, 3072)
     _, fe = pk.tendency(plan, pk.swe_params(), state[None].contiguous())
-    check(fe[0], gold["f_explicit"], TOL, "f_explicit", gold["f_explicit_order_sensitivity"])
+    check(fe[0], gold["f_explicit"], TOL, "f_explicit", tendency_sensitivity(gold), 1.25)
 
 
 def test_large_step_fp64(pk, gold, state):
@@ -140,22 +158,26 @@ def test_large_step_fp64(pk, gold, state):
     assert abs(y[0, 0] - state[0, 0]).item() <= 1e-12 * torch.linalg.vector_norm(state[0]).item()
 
 
+@pytest.mark.parametrize("tmode", [0, 1])
 @pytest.mark.parametrize("prec", [1, 2, 3])
-def test_large_mixed(pk, gold, state, prec):
-    """Reduced-precision Legendre contractions at T1023/T511: tendency and one
-    step within the stated errors of the FP64 oracle."""
-    print("CASE large mixed", prec, flush=True)
+def test_large_mixed(pk, gold, state, prec, tmode):
+    """Reduced-precision Legendre contractions at T1023/T511, with the tables
+    in device memory and without: tendency within five times the emulated
+    error, one step within the stated error of the FP64 oracle."""
+    print("CASE large mixed", prec, "table mode", tmode, flush=True)
+    with open(MIXED) as fh:
+        emu = json.load(fh)["f_explicit_rel_err"][MODE_NAMES[prec]]
     c = gold["config"]
-    lf, lc = levels(pk, prec)
+    lf, lc = levels(pk, prec, tmode)
     _, fe = pk.tendency(lf.plan, pk.swe_params(), state[None].contiguous())
     for f, rec in enumerate(gold["f_explicit"]):
         est, _ = sampled_error(fe[0, f], rec)
-        print("mixed tendency", prec, f, est, flush=True)
-        assert est < BOUND_TEND[prec], (f, est)
+        print("mixed tendency", prec, tmode, f, est, "emulated", emu[f], flush=True)
+        assert est < 5.0 * emu[f], (f, est, emu[f])
     st = pk.Stepper(lf, lc, niter=c["niter"], nsweep_fine=c["nsweep_fine"], nsweep_coarse=c["nsweep_coarse"])
     y = st.step(c["dt"], state)
     for f, rec in enumerate(gold["step"]):
         est, _ = sampled_error(y[f], rec)
-        print("mixed step", prec, f, est, flush=True)
+        print("mixed step", prec, tmode, f, est, flush=True)
         assert est < BOUND_STEP[prec], (f, est)
     assert np.isfinite(torch.view_as_real(y).cpu().numpy()).all()

@@ -684,3 +684,60 @@ def test_adjoint_jvp_golden_matches_oracle_reverse_mode():
     got = torch.stack([(g.real * d.real + g.imag * d.imag).sum() for d in dirs]).numpy()
     ref = np.array(c["dL"])
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- reduced-precision emulation
+def test_mixed_accumulation_is_recursive_fp32():
+    """FP32 accumulation one term at a time: 1 + 2^-25 added 64 times stays 1
+    (each addition rounds the increment away, to nearest even), while any
+    summation that first adds the small terms together (pairwise or blocked)
+    returns 1 + 2^-19 exactly."""
+    from oracle import mixed as OM
+    K = 65
+    A = torch.ones(1, K, dtype=torch.float64)
+    B = torch.full((K, 1), 2.0 ** -25, dtype=torch.float64)
+    B[0, 0] = 1.0
+    assert OM.mixed_matmul(A, B, "fp32").item() == 1.0
+    assert (A @ B).item() == 1.0 + 64 * 2.0 ** -25
+    # exact small-integer contractions come out exact in every mode
+    gen = torch.Generator().manual_seed(3)
+    Ai = torch.randint(-8, 9, (5, 7), generator=gen).to(torch.float64)
+    Bi = torch.randint(-8, 9, (7, 4), generator=gen).to(torch.float64)
+    for mode in ("fp32", "bf16x2", "bf16x3"):
+        assert torch.equal(OM.mixed_matmul(Ai, Bi, mode), Ai @ Bi), mode
+
+
+def test_mixed_split_pieces():
+    """bf16 pieces: hi has 8 significant bits, two pieces hold a value to
+    about 2^-16 relative and three to about 2^-24."""
+    from oracle import mixed as OM
+    gen = torch.Generator().manual_seed(4)
+    x = torch.randn(4000, generator=gen, dtype=torch.float64) * torch.exp(torch.randn(4000, generator=gen, dtype=torch.float64) * 5)
+    p = OM.split(x, 3)
+    hi_bits = p[0].view(torch.int32) & 0xFFFF
+    assert int(hi_bits.abs().max()) == 0                      # bf16: the low 16 bits of the FP32 pattern are zero
+    r2 = ((p[0].double() + p[1].double() - x).abs() / x.abs()).max().item()
+    r3 = ((p[0].double() + p[1].double() + p[2].double() - x).abs() / x.abs()).max().item()
+    assert 2.0 ** -19 < r2 <= 2.0 ** -16 and r3 <= 2.0 ** -24
+
+
+@pytest.mark.parametrize("mode,u", [("fp32", 2.0 ** -24), ("bf16x2", 2.0 ** -16), ("bf16x3", 2.0 ** -24)])
+def test_mixed_error_within_recursive_summation_bound(mode, u):
+    """Error of the emulated contraction against the exact one within the
+    standard bound for rounded operands and recursive summation,
+    |err| <= (2 u_in + gamma_K) sum_k |a_k b_k|, gamma_K = K u / (1 - K u),
+    u = 2^-24 for the FP32 sums and u_in the operand precision; and not far
+    below it on random data (the chain does round: above 1e-5 of the bound,
+    where an FP64 contraction would sit near 1e-9)."""
+    from oracle import mixed as OM
+    gen = torch.Generator().manual_seed(5)
+    K = 1536
+    A = torch.randn(64, K, generator=gen, dtype=torch.float64)
+    B = torch.randn(K, 3, generator=gen, dtype=torch.float64) + 0.3
+    got = OM.mixed_matmul(A, B, mode)
+    exact = A @ B
+    s = A.abs() @ B.abs()
+    uacc = 2.0 ** -24
+    gam = K * uacc / (1 - K * uacc)
+    ratio = ((got - exact).abs() / ((2 * u + gam) * s)).max().item()
+    assert 1e-5 < ratio <= 1.0, ratio
