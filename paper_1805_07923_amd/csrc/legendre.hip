@@ -23,6 +23,10 @@
 namespace {
 
 constexpr int UNR = 8;   // table loads in flight per lane
+// matrix-core synthesis with LS sets of 16 latitudes per wavefront: 4
+// wavefronts per block for one set, 3 for two (96 latitudes per block)
+__host__ __device__ constexpr int syn_wb(int LS) { return LS == 1 ? 4 : 3; }
+__host__ __device__ constexpr int syn_lat(int LS) { return 16 * LS * syn_wb(LS); }
 constexpr int AN_JC = 256;   // latitude pairs up to which the table analysis is used
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -210,8 +214,8 @@ __global__ void k_plm_one(const double* __restrict__ mu, const double* __restric
 // coefficients past the table as zeros (P then continues as 0), so every
 // lane reads its next eight degrees at fixed offsets from one address, with
 // no clamping and no per-degree selection.
-template <int NF, int STAGE = 0>
-__global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ ck,
+template <int NF, int STAGE = 0, int SYN_LS = 1>
+__global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2* __restrict__ ck,
                                                    const long long* __restrict__ ckoff,
                                                    const double2* __restrict__ rc,
                                                    const double* __restrict__ mu,
@@ -231,14 +235,19 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
     const int i = lane & 15, q = lane >> 4;
     const LegTile tile = leg_tile(gx, N + 1, 1);
     const int m = tile.m;
-    const int jw = tile.x * 64 + wv * 16;               // first latitude of this wavefront
-    const int jp = jw + i;
-    const bool active = jp < Jh;
+    const int jw = tile.x * syn_lat(SYN_LS) + wv * 16 * SYN_LS;  // first latitude of this wavefront
     const int Kt = nmax_tab - m + 1, Ku = nmax_use - m + 1;
     const int R = seg_rounds(Kt), L = seg_len(Kt);
     const int SC = L * NF + 2, SR = L + 2;              // padded segment strides (double2)
-    const double x = mu[active ? jp : 0];
-    const double2* ckm = ck + ckoff[m] + (active ? jp : 0);
+    double x[SYN_LS];                                   // latitude set ls: jw + 16 ls + i
+    const double2* ckm[SYN_LS];
+#pragma unroll
+    for (int ls = 0; ls < SYN_LS; ++ls) {
+        const int jp = jw + 16 * ls + i;
+        const bool active = jp < Jh;
+        x[ls] = mu[active ? jp : 0];
+        ckm[ls] = ck + ckoff[m] + (active ? jp : 0);
+    }
     double2* rsh = csh + 4 * (Lmax * NF + 2);
     const double* cq = reinterpret_cast<const double*>(csh + q * SC);        // segment q
     int cg[NG];                                         // B columns 4 g + lane % 4 (clamped; >= 2 NF unused)
@@ -249,16 +258,20 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
     const double2* pfm = pf + ext_idx(N, m, m);
     const double ia = 1.0 / a, a2 = a * a, ia2 = ia * ia;
     for (int s = 0; s < S; ++s) {
-        double accE[NG], accO[NG];
+        double accE[SYN_LS][NG], accO[SYN_LS][NG];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) accE[g] = accO[g] = 0.0;
+        for (int ls = 0; ls < SYN_LS; ++ls)
+#pragma unroll
+            for (int g = 0; g < NG; ++g) accE[ls][g] = accO[ls][g] = 0.0;
         for (int r = 0; r < R; ++r) {
             const int kr0 = 4 * r * L;
             if (kr0 >= Ku) break;                       // uniform
             const int g = 4 * r + q;
-            const double2 c0 = ckm[(long long)g * Jh];  // in flight during the staging
+            double2 c0[SYN_LS];                         // in flight during the staging
+#pragma unroll
+            for (int ls = 0; ls < SYN_LS; ++ls) c0[ls] = ckm[ls][(long long)g * Jh];
             __syncthreads();                            // previous readers of the rows are done
-            for (int kl = threadIdx.x; kl < 4 * L; kl += 256) {
+            for (int kl = threadIdx.x; kl < 4 * L; kl += 64 * syn_wb(SYN_LS)) {
                 const int qs = kl / L, ts = kl - qs * L, kk = kr0 + kl;
                 double2* row = csh + qs * SC + ts * NF;
                 if (kk < Ku) {
@@ -287,7 +300,12 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
             }
             __syncthreads();
             if (jw >= Jh) continue;                     // uniform: no latitudes for this wavefront
-            double pe = c0.x, po = c0.y;                // P_{m+gL}, P_{m+gL+1}
+            double pe[SYN_LS], po[SYN_LS];              // P_{m+gL}, P_{m+gL+1}
+#pragma unroll
+            for (int ls = 0; ls < SYN_LS; ++ls) {
+                pe[ls] = c0[ls].x;
+                po[ls] = c0[ls].y;
+            }
             for (int t = 0; t < L; t += U) {
                 double2 rr[U];
                 double bb[U][NG];
@@ -299,30 +317,36 @@ __global__ __launch_bounds__(256) void k_leg_syn_m(const double2* __restrict__ c
                 }
 #pragma unroll
                 for (int u = 0; u < U; u += 2) {
-                    if (u > 0 || t > 0) {
-                        const double ne = fma(rr[u].x * x, po, -(rr[u].y * pe));
-                        po = fma(rr[u + 1].x * x, ne, -(rr[u + 1].y * po));
-                        pe = ne;
-                    }
 #pragma unroll
-                    for (int g = 0; g < NG; ++g) {
-                        accE[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(pe, bb[u][g], accE[g], 0, 0, 0);
-                        accO[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(po, bb[u + 1][g], accO[g], 0, 0, 0);
+                    for (int ls = 0; ls < SYN_LS; ++ls) {
+                        if (u > 0 || t > 0) {
+                            const double ne = fma(rr[u].x * x[ls], po[ls], -(rr[u].y * pe[ls]));
+                            po[ls] = fma(rr[u + 1].x * x[ls], ne, -(rr[u + 1].y * po[ls]));
+                            pe[ls] = ne;
+                        }
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            accE[ls][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(pe[ls], bb[u][g], accE[ls][g], 0, 0, 0);
+                            accO[ls][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(po[ls], bb[u + 1][g], accO[ls][g], 0, 0, 0);
+                        }
                     }
                 }
             }
         }
         // D layout (f64 4x4x4, 4 blocks): lane 4 b + j + 16 r holds row r of
         // block b (latitude 4 b + r) and column j of the group
-        const int jr = jw + 4 * (i >> 2) + q;
-        if (jw < Jh && jr < Jh) {
-            double* o0 = reinterpret_cast<double*>(out + s * out_stride + ((long long)jr * (N + 1) + m) * F + f0);
 #pragma unroll
-            for (int g = 0; g < NG; ++g) {
-                const int c = 4 * g + (lane & 3);
-                if (c < 2 * NF) {
-                    o0[c] = accE[g];
-                    o0[c + (long long)Jh * (N + 1) * F * 2] = accO[g];
+        for (int ls = 0; ls < SYN_LS; ++ls) {
+            const int jr = jw + 16 * ls + 4 * (i >> 2) + q;
+            if (jw < Jh && jr < Jh) {
+                double* o0 = reinterpret_cast<double*>(out + s * out_stride + ((long long)jr * (N + 1) + m) * F + f0);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const int c = 4 * g + (lane & 3);
+                    if (c < 2 * NF) {
+                        o0[c] = accE[ls][g];
+                        o0[c + (long long)Jh * (N + 1) * F * 2] = accO[ls][g];
+                    }
                 }
             }
         }
@@ -563,14 +587,23 @@ __global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, co
 template <int NF, int STAGE = 0>
 void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S, int nmax_use,
            long long cin_stride, double a, hipStream_t st) {
-    const int gx = (pl->Jh + 63) / 64;
     int Lmax = 0;                                       // longest segment over the orders
     for (int m = 0; m <= pl->N; ++m) Lmax = seg_len(pl->nmax - m + 1) > Lmax ? seg_len(pl->nmax - m + 1) : Lmax;
     const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2);
-    k_leg_syn_m<NF, STAGE><<<gx * (pl->N + 1), 256, lds, st>>>(pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N,
-                                                              pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride,
-                                                              (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a,
-                                                              Lmax, pl->pf, pl->ninv, pl->nn1);
+    const long long os = (long long)pl->J * (pl->N + 1) * F;
+    // two latitude sets per wavefront from 384 latitude pairs up (fewer
+    // wavefronts; measured faster at T1023, slower at T255 and below)
+    if (pl->Jh >= 384) {
+        const int gx = (pl->Jh + syn_lat(2) - 1) / syn_lat(2);
+        k_leg_syn_m<NF, STAGE, 2><<<gx * (pl->N + 1), 64 * syn_wb(2), lds, st>>>(
+            pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride, os,
+            gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1);
+    } else {
+        const int gx = (pl->Jh + syn_lat(1) - 1) / syn_lat(1);
+        k_leg_syn_m<NF, STAGE, 1><<<gx * (pl->N + 1), 64 * syn_wb(1), lds, st>>>(
+            pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride, os,
+            gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1);
+    }
 }
 
 template <int NF>
