@@ -73,17 +73,26 @@ def legendre_flops(N, J, F, nmax):
     return 4.0 * rows * Jh * F
 
 
+def kernel_source_sha256(path, signature):
+    """SHA-256 of one kernel's source text: from its signature line to the
+    closing brace of the function (a line holding only '}')."""
+    import hashlib
+    with open(path) as f:
+        src = f.read()
+    a = src.index(signature)
+    b = src.index("\n}\n", a)
+    return hashlib.sha256(src[a:b + 3].encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed counter
-    record, or None when the kernel source changed since it was taken."""
-    import hashlib
+    record, or None when that kernel's source changed since it was taken."""
     rec = os.path.join(ROOT, "profiles", "k_leg_an_T255_traffic.json")
     try:
         with open(rec) as f:
             d = json.load(f)
-        with open(os.path.join(ROOT, d["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != d["source_sha256"]:
-                return None
+        if kernel_source_sha256(os.path.join(ROOT, d["source"]), d["kernel_signature"]) != d["kernel_sha256"]:
+            return None
         return d["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
