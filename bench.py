@@ -609,7 +609,7 @@ def main():
             "evaluations_per_step": {"fine": evals_fine, "coarse": evals_coarse},
         },
         "roofline": {
-            "kernel": "k_leg_an (Legendre analysis, fine level, 5 fields)",
+            "kernel": "k_leg_an (Legendre analysis from the table on the matrix cores, fine level, 5 fields)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "avg_launch_us": an_us, "algorithmic_bytes_per_launch": abytes,

@@ -30,6 +30,8 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->tw);
     (void)hipFree(p->psyn);
     (void)hipFree(p->pan);
+    (void)hipFree(p->pan4);
+    (void)hipFree(p->off4);
     (void)hipFree(p->psyn32);
     (void)hipFree(p->pan32);
     (void)hipFree(p->an16);
@@ -864,6 +866,25 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
     ok = ok && hipMemcpy(p->ord_e, orde.data(), orde.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->deg_e, dege.data(), dege.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && launch_plm_table(p, 0) == hipSuccess;
+    if (ok && prec == SHX_FP64 && table_mode == SHX_TABLE_HBM && p->Jh <= AN_TAB_JH) {
+        // the analysis table in the layout of the matrix-core table analysis
+        const int ngrp = (p->Jh + 3) / 4;
+        std::vector<long long> off4(2 * (N + 1));
+        long long tot = 0, mx = 0;
+        for (int mp = 0; mp < 2 * (N + 1); ++mp) {
+            const long long sz = (long long)((kcount(p->nmax, mp >> 1, mp & 1) + 15) / 16) * ngrp * 64;
+            off4[mp] = tot;
+            tot += sz;
+            mx = sz > mx ? sz : mx;
+        }
+        ok = dalloc(&p->pan4, tot) == hipSuccess && dalloc(&p->off4, off4.size()) == hipSuccess &&
+             hipMemcpy(p->off4, off4.data(), off4.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+             launch_an_tab4(p, mx, 0) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+        if (ok) {                                       // the [m][p][jp][k] layout has no other reader here
+            (void)hipFree(p->pan);
+            p->pan = nullptr;
+        }
+    }
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (ok && prec != SHX_FP64 && table_mode == SHX_TABLE_HBM) ok = convert_tables(p);
     if (!ok) {

@@ -21,6 +21,10 @@ __host__ __device__ inline long long nspec_of(int N) { return (long long)(N + 1)
 __host__ __device__ inline long long nspec_ext_of(int N) { return (long long)(N + 1) * (N + 4) / 2; }
 
 // Rows of the parity block p (n - m = p mod 2) of order m for degrees <= nmax.
+// latitude pairs up to which the FP64 analysis of up to 6 fields streams
+// its table (beyond: the matrix-core kernel that generates P^m_n)
+constexpr int AN_TAB_JH = 256;
+
 __host__ __device__ inline int kcount(int nmax, int m, int p) {
     return (nmax - m - p >= 0) ? (nmax - m - p) / 2 + 1 : 0;
 }
@@ -179,7 +183,8 @@ struct shx_plan {
     double* w = nullptr;            // device [J]
     double2* tw = nullptr;          // device [I], e^{-2 pi i t / I}
     double* psyn = nullptr;         // FP64 table, [m][p][k][jp] (FP64 plans)
-    double* pan = nullptr;          // FP64 table, [m][p][jp][k] (FP64 plans)
+    double* pan = nullptr;          // FP64 table, [m][p][jp][k]: the source of pan4 and of the
+                                    // reduced-precision analysis tables, freed once they are built
     float* psyn32 = nullptr;        // FP32 tables (SHX_FP32 plans), same layouts
     float* pan32 = nullptr;
     unsigned short* an16 = nullptr;   // bf16 split planes for the analysis, [q][m][p][k][jp pad 16]
@@ -188,6 +193,14 @@ struct shx_plan {
     long long* off_an16 = nullptr;    // device [(N+1)*2] offsets into a bf16 plane
     long long* off_syn16 = nullptr;
     long long* off = nullptr;       // device [(N+1)*2] table offsets (elements)
+    // FP64 analysis table laid out for the matrix-core table analysis
+    // (FP64 plans with tables and at most 256 latitude pairs):
+    // pan4[off4[2m+p] + ((kt * ngrp + c) * 4 + kq) * 16 + i] = P^m_{m+p+2k}(mu_jp),
+    // k = 16 kt + i, jp = 4 c + kq, ngrp = ceil(Jh / 4); zero past the rows and
+    // latitude pairs, so that one operand of 16 degrees x 4 latitude pairs is
+    // 64 consecutive values.
+    double* pan4 = nullptr;
+    long long* off4 = nullptr;
     // Recurrence data of the FP64 kernels that generate P^m_n in registers:
     // ck[ckoff[m] + g * Jh + jp] = (P^m_{m+g*L}, P^m_{m+g*L+1}) at mu_jp for the
     // 4 R segments g of the order (L = seg_len, R = seg_rounds of its
@@ -238,6 +251,7 @@ struct Mat9x9 {
 // ----------------------------------------------------- launch wrappers
 // legendre.hip
 hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st);
+hipError_t launch_an_tab4(const shx_plan* pl, long long max_block, hipStream_t st);
 // P^m_n at the northern latitudes by the double-double recurrence, rounded to
 // FP64, into out[Jh] (device): the table export of plans without tables.
 hipError_t launch_plm_one(const shx_plan* pl, int m, int n, double* out, hipStream_t st);

@@ -27,7 +27,6 @@ constexpr int UNR = 8;   // table loads in flight per lane
 // wavefronts per block for one set, 3 for two (96 latitudes per block)
 __host__ __device__ constexpr int syn_wb(int LS) { return LS == 1 ? 4 : 3; }
 __host__ __device__ constexpr int syn_lat(int LS) { return 16 * LS * syn_wb(LS); }
-constexpr int AN_JC = 256;   // latitude pairs up to which the table analysis is used
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Value of lane src (wave-uniform) of a per-lane double, for every lane.
@@ -485,100 +484,115 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
     }
 }
 
-// Analysis from the table (up to AN_JC latitude pairs and 6 fields, where
-// streaming the FP64 table measured faster than k_leg_an_m):
+// pan4 from pan (layout in shx_plan): one thread per destination element of
+// order-parity block blockIdx.y = 2 m + p.
+__global__ void k_an_tab4(const double* __restrict__ pan, const long long* __restrict__ off,
+                          const long long* __restrict__ off4, double* __restrict__ pan4, int nmax, int Jh) {
+    const int mp = blockIdx.y, m = mp >> 1, p = mp & 1;
+    const int K = kcount(nmax, m, p);
+    const int ngrp = (Jh + 3) / 4;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (K <= 0 || e >= (long long)((K + 15) / 16) * ngrp * 64) return;
+    const long long blk = e / 64;
+    const int l = (int)(e - blk * 64);
+    const int kt = (int)(blk / ngrp), c = (int)(blk - (long long)kt * ngrp);
+    const int k = 16 * kt + (l & 15), jp = 4 * c + (l >> 4);
+    pan4[off4[mp] + e] = (k < K && jp < Jh) ? pan[off[mp] + (long long)jp * K + k] : 0.0;
+}
+
+// Analysis from the table on the matrix cores (up to AN_TAB_JH latitude
+// pairs and 6 fields; beyond, k_leg_an_m generates P^m_n instead):
 // cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
-// one block per (m, p, 64-degree tile holding rows) from the plan's list
-// (the blocks of an order on one XCD), 256 threads: lane = degree row k, the four
-// wavefronts split the latitude sum into quarters.  The combined Fourier
-// data g_jp = G_north +/- G_south of this (m, p) is staged in LDS per state
-// (dynamic LDS: Jh * NF double2) and read by broadcast; the partial sums of
-// waves 1..3 are added by wave 0 through LDS.
+// One block per (m, p, 64-degree tile holding rows) from the plan's list
+// (the blocks of an order on one XCD), one wavefront per 16 degrees summing
+// over all latitude pairs, so no partial sums cross wavefronts.  Per group
+// of 4 latitude pairs the four-block v_mfma_f64_4x4x4f64 takes A = 16
+// degrees x 4 latitude pairs of the table, 64 consecutive values of pan4 (one
+// 8-byte load per lane), and B = the north +/- south Fourier data of the
+// same latitude pairs staged in LDS (column 4 g + lane % 4): one instruction
+// per pair of fields; D lane 4 b + j + 16 i holds degree row 4 b + i,
+// column 4 g + j.  With an odd field count the last field's two columns are
+// summed on the VALU by each lane over its latitude slot (lane / 16) and the
+// four slots added by lane exchange, instead of a third, half-empty matrix
+// product per group.
 template <int NF>
-__global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, const double* __restrict__ pan,
-                                                const long long* __restrict__ off,
-                                                const double2* __restrict__ G,
-                                                double2* __restrict__ cout, int N, int nmax_tab,
-                                                int nmax_use, int J, int F, int f0, int S,
-                                                long long G_stride, long long cout_stride) {
+__global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, const double* __restrict__ pan4,
+                                                  const long long* __restrict__ off4,
+                                                  const double2* __restrict__ G,
+                                                  double2* __restrict__ cout, int N, int nmax_tab,
+                                                  int nmax_use, int J, int F, int f0, int S,
+                                                  long long G_stride, long long cout_stride) {
+    constexpr int NG = NF / 2;                          // groups of 4 real columns (two fields) on MFMA
+    constexpr bool ODD = NF % 2 == 1;                   // last field: its two columns on the VALU
     extern __shared__ double2 gsh[];                    // [Jh][NF]
-    __shared__ double red[3][2 * NF][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int mp = tblk[2 * blockIdx.x], tx = tblk[2 * blockIdx.x + 1];
     if (mp < 0) return;                                 // padding block (uniform)
     const int m = mp >> 1, p = mp & 1;
-    const int k = tx * 64 + lane;
     const int K = kcount(nmax_use, m, p);
     if (tx * 64 >= K) return;                           // whole block idle (uniform)
-    const bool active = k < K;
-    const int Ktab = kcount(nmax_tab, m, p);
-    {
-        const int Jh = J / 2;
-        const int jq = (Jh + 3) / 4;
-        const int j0 = wv * jq, j1 = min(Jh, j0 + jq);
-        const double* P = pan + off[2 * m + p] + (active ? k : 0);
-        const double sg = p ? -1.0 : 1.0;
-        const long long rowstride = (long long)(N + 1) * F;
-        for (int s = 0; s < S; ++s) {
-            const double2* g = G + s * G_stride + (long long)m * F + f0;
-            __syncthreads();                                // previous state's readers are done
-            for (int i = threadIdx.x; i < Jh * NF; i += 256) {
-                const int jp = i / NF, f = i - jp * NF;
-                const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
-                gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+    const int Jh = J / 2;
+    const int k0 = tx * 64 + 16 * wv;                   // this wavefront's first degree row
+    const int kq = lane >> 4;                           // latitude slot of the operands
+    const int ngrp = (Jh + 3) / 4;                      // groups of 4 latitude pairs
+    // A operands of this wavefront's 16 degrees: 64 consecutive values per group
+    const double* P = pan4 + off4[2 * m + p] + (long long)(k0 >> 4) * ngrp * 64 + lane;
+    const double sg = p ? -1.0 : 1.0;
+    const long long rowstride = (long long)(N + 1) * F;
+    const double* gs = reinterpret_cast<const double*>(gsh);
+    const int cb = lane & 3;                            // B column within a group
+    for (int s = 0; s < S; ++s) {
+        const double2* g = G + s * G_stride + (long long)m * F + f0;
+        __syncthreads();                                // previous state's readers are done
+        for (int i = threadIdx.x; i < Jh * NF; i += 256) {
+            const int jp = i / NF, f = i - jp * NF;
+            const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+            gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+        }
+        __syncthreads();
+        if (k0 >= K) continue;                          // no rows for this wavefront (uniform)
+        double acc[NG > 0 ? NG : 1];
+#pragma unroll
+        for (int g2 = 0; g2 < NG; ++g2) acc[g2] = 0.0;
+        double vr = 0.0, vi = 0.0;                      // odd field: this lane's latitude slot
+        auto step = [&](double a, int jp) {
+            const bool in = jp < Jh;
+#pragma unroll
+            for (int g2 = 0; g2 < NG; ++g2) {
+                const double b = in ? gs[jp * 2 * NF + 4 * g2 + cb] : 0.0;
+                acc[g2] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[g2], 0, 0, 0);
             }
-            __syncthreads();
-            double ar[NF], ai[NF];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) ar[f] = ai[f] = 0.0;
-            int jp = j0;
-            for (; jp + UNR <= j1; jp += UNR) {
-                double pv[UNR];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(jp + u) * Ktab];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const double2* gg = gsh + (jp + u) * NF;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const double2 x = gg[f];
-                        ar[f] = fma(pv[u], x.x, ar[f]);
-                        ai[f] = fma(pv[u], x.y, ai[f]);
-                    }
-                }
+            if constexpr (ODD) {
+                const double2 z = in ? gsh[jp * NF + NF - 1] : make_double2(0.0, 0.0);
+                vr = fma(a, z.x, vr);
+                vi = fma(a, z.y, vi);
             }
-            for (; jp < j1; ++jp) {
-                const double pv = P[(long long)jp * Ktab];
-                const double2* gg = gsh + jp * NF;
+        };
+        int c = 0;
+        for (; c + UNR <= ngrp; c += UNR) {
+            double pv[UNR];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const double2 x = gg[f];
-                    ar[f] = fma(pv, x.x, ar[f]);
-                    ai[f] = fma(pv, x.y, ai[f]);
-                }
-            }
-            if (wv > 0) {
+            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(c + u) * 64];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    red[wv - 1][2 * f][lane] = ar[f];
-                    red[wv - 1][2 * f + 1][lane] = ai[f];
-                }
-            }
-            __syncthreads();
-            if (wv == 0 && active) {
-                double2* o = cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0;
+            for (int u = 0; u < UNR; ++u) step(pv[u], 4 * (c + u) + kq);
+        }
+        for (; c < ngrp; ++c) step(P[(long long)c * 64], 4 * c + kq);
+        // MFMA D: lane 4 b + j + 16 i holds degree row 4 b + i, column 4 g + j
+        const int k = k0 + 4 * ((lane & 15) >> 2) + (lane >> 4);
+        if (k < K) {
+            double* o = reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F + f0);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    // fixed summation order: wave 0, 1, 2, 3
-                    double xr = ar[f], xi = ai[f];
-#pragma unroll
-                    for (int w = 0; w < 3; ++w) {
-                        xr += red[w][2 * f][lane];
-                        xi += red[w][2 * f + 1][lane];
-                    }
-                    o[f] = make_double2(xr, xi);
-                }
-            }
+            for (int g2 = 0; g2 < NG; ++g2) o[4 * g2 + cb] = acc[g2];
+        }
+        if constexpr (ODD) {
+            // sum of the four latitude slots (lanes l, l ^ 16, l ^ 32, l ^ 48), fixed order
+            vr += __shfl_xor(vr, 16);
+            vi += __shfl_xor(vi, 16);
+            vr += __shfl_xor(vr, 32);
+            vi += __shfl_xor(vi, 32);
+            const int kv = k0 + (lane & 15);
+            if (kq == 0 && kv < K)
+                cout[s * cout_stride + ext_idx(N, m, m + p + 2 * kv) * F + f0 + NF - 1] = make_double2(vr, vi);
         }
     }
 }
@@ -615,9 +629,9 @@ void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int 
 template <int NF>
 void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
               hipStream_t st) {
-    if (NF <= 6 && pl->Jh <= AN_JC && pl->pan) {
+    if (NF <= 6 && pl->pan4) {                         // FP64 plans with tables, Jh <= AN_TAB_JH
         const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
-        k_leg_an<NF><<<pl->tb_nblk, 256, lds, st>>>(pl->tblk, pl->pan, pl->off, G, cout, pl->N, pl->nmax, nmax_use,
+        k_leg_an<NF><<<pl->tb_nblk, 256, lds, st>>>(pl->tblk, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax, nmax_use,
                                                    pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
                                                    pl->nspec_e * F);
         return;
@@ -636,6 +650,12 @@ hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
     dim3 grid((pl->Jh + 63) / 64, pl->N + 1);
     k_plm_table<<<grid, 64, 0, st>>>(pl->mu, pl->sint, pl->off, pl->psyn, pl->pan, pl->ck, pl->ckoff, pl->rc,
                                      pl->N, pl->nmax, pl->Jh);
+    return hipGetLastError();
+}
+
+hipError_t launch_an_tab4(const shx_plan* pl, long long max_block, hipStream_t st) {
+    dim3 grid((unsigned)((max_block + 255) / 256), 2 * (pl->N + 1));
+    k_an_tab4<<<grid, 256, 0, st>>>(pl->pan, pl->off, pl->off4, pl->pan4, pl->nmax, pl->Jh);
     return hipGetLastError();
 }
 
