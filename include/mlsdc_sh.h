@@ -280,8 +280,8 @@ int mlsdc_step_multi(const sdc_level* const* levels, int nlevels, int niter, con
  * spectral arrays <x, y> = sum over the stored coefficients of
  * Re x Re y + Im x Im y; grids sum_ij x_ij y_ij.  So a cotangent returned for
  * a spectral input is the gradient with respect to its real and imaginary
- * parts.  Transforms with nlon = 2048 or 3072 and plans of a reduced
- * working precision are not supported here (SHX_EUNSUPPORTED). */
+ * parts.  Plans of a reduced working precision are not supported here
+ * (SHX_EUNSUPPORTED). */
 
 /* spec_cot = S^T grid_cot for the synthesis S of sh_inverse:
  *   spec_cot^m_n = c_m sum_j P^m_n(mu_j) sum_i grid_cot_ij e^{-i m lambda_i}, c_0 = 1, c_m = 2.
@@ -294,6 +294,9 @@ int sh_inverse_adj(const shx_plan* plan, int nfield, const double* grid_cot_dev,
 int sh_forward_adj(const shx_plan* plan, int nfield, const double* spec_cot_dev, double* grid_cot_dev,
                    void* ws_dev, size_t ws_bytes, shx_stream_t stream);
 
+/* Workspace of swe_tendency_adj for nstate states.  For nlon = 2048 and 3072
+ * it includes 9 nlat nlon doubles per state: those rows are too long for the
+ * transposed grid products to stay in LDS, so they go through HBM. */
 size_t swe_adj_workspace_bytes(const shx_plan* plan, int nstate);
 
 /* lam_state += (dF_I/dTheta)^T lam_fi + (dF_E/dTheta)^T lam_fe, linearised at

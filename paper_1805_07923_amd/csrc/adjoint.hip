@@ -347,9 +347,31 @@ hipError_t grid_adj_t(const shx_plan* pl, const double2* FIs, const double2* FIl
 
 #define SHX_ADJ_LENGTHS(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(48) X(96) X(192) X(384) X(768) X(1536)
 
-}  // namespace
+// The same transposed products for rows too long for the nine rows of the
+// kernel above to fit in LDS (2048, 3072 points), on grids in HBM:
+// g[9][J][L] holds the inverse transforms of (zeta, Phi', U, V) and of the
+// cotangents of (A, B, C, D, E); the grid cotangents of (zeta, Phi', U, V)
+// are written over rows 4..7.  One thread per grid point.
+__global__ void k_swe_adj_prod(double* __restrict__ g, const double* __restrict__ mu,
+                               const double* __restrict__ cos2, const double* __restrict__ w, int J, int L,
+                               double two_omega) {
+    const long long n = (long long)J * L;
+    const long long e = (long long)blockIdx.x * TB + threadIdx.x;
+    if (e >= n) return;
+    const int j = (int)(e / L);
+    const double fc = two_omega * mu[j];
+    const double ic2 = 1.0 / cos2[j];
+    const double wv = w[j] / (L * cos2[j]), we = w[j] / L;
+    const double z = g[e], ph = g[n + e], U = g[2 * n + e], V = g[3 * n + e];
+    const double lA = g[4 * n + e], lB = g[5 * n + e], lC = g[6 * n + e], lD = g[7 * n + e], lE = g[8 * n + e];
+    const double eta = z + fc;
+    g[4 * n + e] = wv * (lA * U + lB * V);
+    g[5 * n + e] = wv * (lC * U + lD * V);
+    g[6 * n + e] = wv * (lA * eta + lC * ph) + we * lE * U * ic2;
+    g[7 * n + e] = wv * (lB * eta + lD * ph) + we * lE * V * ic2;
+}
 
-bool adjoint_length_supported(int L) {
+bool lds_adj_length(int L) {
     switch (L) {
 #define CASE(n) case n:
         SHX_ADJ_LENGTHS(CASE)
@@ -357,6 +379,14 @@ bool adjoint_length_supported(int L) {
         return true;
         default: return false;
     }
+}
+
+}  // namespace
+
+bool adjoint_length_supported(int L) { return lds_adj_length(L) || fft_length_supported(L); }
+
+size_t adj_grid_doubles(const shx_plan* pl, int S) {
+    return lds_adj_length(pl->I) ? 0 : (size_t)S * 9 * pl->J * pl->I;
 }
 
 hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double2* lam4, const double2* lfi,
@@ -367,13 +397,29 @@ hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double
 }
 
 hipError_t launch_swe_grid_adj(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S,
-                               double omega, hipStream_t st) {
+                               double omega, double* grid, hipStream_t st) {
     switch (pl->I) {
 #define CASE(n) case n: return grid_adj_t<n>(pl, FIs, FIl, Ga, S, omega, st);
         SHX_ADJ_LENGTHS(CASE)
 #undef CASE
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    // longer rows: inverse transforms into HBM, pointwise products, forward
+    // transforms with the factor c_m (1 for m = 0, else 2)
+    if (!grid) return hipErrorInvalidValue;
+    const long long fj = (long long)pl->J * (pl->N + 1), n = (long long)pl->J * pl->I;
+    for (int s = 0; s < S; ++s) {
+        double* g = grid + (long long)s * 9 * n;
+        hipError_t e = launch_fft_inv(pl, FIs + s * fj * 4, g, 4, 0, st);
+        if (e == hipSuccess) e = launch_fft_inv(pl, FIl + s * fj * 5, g + 4 * n, 5, 0, st);
+        if (e != hipSuccess) return e;
+        k_swe_adj_prod<<<(unsigned)((n + TB - 1) / TB), TB, 0, st>>>(g, pl->mu, pl->cos2, pl->w, pl->J, pl->I,
+                                                                    2.0 * omega);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_fft_fwd(pl, g + 4 * n, Ga + s * fj * 4, 4, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_imex_solve_adj(const shx_plan* pl, const swe_params& p, double h, const double2* lx,

@@ -530,6 +530,7 @@ namespace {
 // Workspace of the tendency adjoint for S states.
 struct TendAdjWS {
     double2 *FIs, *FIl, *Ga, *lam4;
+    double* grid;                   // grid rows in HBM for row lengths beyond the LDS kernel
 };
 TendAdjWS carve_tadj(Carve& c, const shx_plan* pl, int S) {
     TendAdjWS t;
@@ -538,6 +539,8 @@ TendAdjWS carve_tadj(Carve& c, const shx_plan* pl, int S) {
     t.FIl = c.take<double2>(fj * 5);
     t.Ga = c.take<double2>(fj * 4);
     t.lam4 = c.take<double2>((size_t)S * pl->nspec_e * 4);
+    const size_t gd = adj_grid_doubles(pl, S);
+    t.grid = gd ? c.take<double>(gd) : nullptr;
     return t;
 }
 
@@ -547,7 +550,7 @@ int tendency_adj_impl(const shx_plan* pl, const swe_params& p, int S, const doub
     if (lfe) {
         HIPCHK(launch_leg_syn_swe(pl, p.a, state, t.FIs, S, st));
         HIPCHK(launch_leg_syn_swe_adj(pl, p.a, lfe, t.FIl, S, st));
-        HIPCHK(launch_swe_grid_adj(pl, t.FIs, t.FIl, t.Ga, S, p.omega, st));
+        HIPCHK(launch_swe_grid_adj(pl, t.FIs, t.FIl, t.Ga, S, p.omega, t.grid, st));
         HIPCHK(launch_leg_an(pl, t.Ga, t.lam4, 4, S, pl->nmax, st));
     }
     HIPCHK(launch_prep_adj(pl, p, t.lam4, lfi, lstate, S, lfe != nullptr, st));

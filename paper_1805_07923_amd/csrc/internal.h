@@ -336,10 +336,13 @@ hipError_t launch_status(const shx_plan* pl, const double* partial, int nblk, in
 int residual_blocks(const shx_plan* pl);
 // adjoint.hip
 bool adjoint_length_supported(int L);
+// doubles of HBM grid workspace the tendency adjoint needs for S states (0
+// when its rows fit in LDS)
+size_t adj_grid_doubles(const shx_plan* pl, int S);
 hipError_t launch_prep_adj(const shx_plan* pl, const swe_params& p, const double2* lam4, const double2* lfi,
                            double2* lstate, int S, int has_fe, hipStream_t st);
 hipError_t launch_swe_grid_adj(const shx_plan* pl, const double2* FIs, const double2* FIl, double2* Ga, int S,
-                               double omega, hipStream_t st);
+                               double omega, double* grid, hipStream_t st);
 hipError_t launch_imex_solve_adj(const shx_plan* pl, const swe_params& p, double h, const double2* lx,
                                  double2* lb, int S, hipStream_t st);
 hipError_t launch_sdc_node_adj(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wt,

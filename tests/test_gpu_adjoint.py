@@ -3,7 +3,9 @@ the whole MLSDC step, checked by dot-product identities, against torch
 autograd through the FP64 CPU oracle (the reference gradient), against the
 oracle's forward-mode directional derivatives (whole-step dot products
 <J d, w> = <d, J^T w>, stored values), and against central finite differences
-on the 20-step T127/T63 integration."""
+on the 20-step T127/T63 integration; the tendency and one step of the
+T1023/T511 configuration by dot products with central differences of the
+GPU's own forward maps."""
 import json
 import math
 import os
@@ -101,6 +103,73 @@ def test_tendency_adjoint_vs_autograd(pk, N, J, I, S):
         loss.backward()
         for f in range(3):
             assert relerr(got[s, f], x.grad[f]) < 1e-12, (s, f, relerr(got[s, f], x.grad[f]))
+
+
+@pytest.mark.parametrize("N,J,I", [(1023, 1536, 3072), (127, 192, 384)])
+def test_tendency_adjoint_dot_central_difference(pk, N, J, I):
+    """<J d, w> = <d, J^T w> for the tendency on the GPU, with J d from central
+    differences of the GPU tendency.  F_I is linear and F_E quadratic in the
+    state (products of linear functions of it), so the central difference
+    (F(x + d) - F(x - d)) / 2 is exactly J(x) d up to rounding, for a
+    direction as large as the state.  At T1023 (3072-point rows) the
+    transposed grid products run through the HBM workspace instead of LDS;
+    T127 checks the LDS kernel the same way."""
+    print("CASE tendency adjoint dot", N, flush=True)
+    seed = {1023: 1004, 127: 1001}[N]
+    x = torch.tensor(workload.state(N, seed), device="cuda")
+    gen = torch.Generator().manual_seed(17)
+    deg = torch.tensor(np.concatenate([np.arange(m, N + 1) for m in range(N + 1)]))
+    m0 = torch.tensor(np.concatenate([np.full(N + 1 - m, m) for m in range(N + 1)]) == 0)
+    d = crandn(x.shape, gen) * (deg + 1.0) ** -1.5
+    d[:, m0] = d[:, m0].real.to(torch.complex128)
+    d[:, deg == 0] = 0
+    for f in range(3):                              # the size of the state, field by field
+        d[f] *= torch.linalg.vector_norm(x[f].cpu()) / torch.linalg.vector_norm(d[f])
+    d = d.to("cuda")
+    w_fi, w_fe = crandn(x.shape, gen).to("cuda"), crandn(x.shape, gen).to("cuda")
+    plan = pk.Plan(N, J, I)
+    par = pk.swe_params()
+    fip, fep = pk.tendency(plan, par, (x + d)[None].contiguous())
+    fim, fem = pk.tendency(plan, par, (x - d)[None].contiguous())
+    lhs = rdot((fip[0] - fim[0]) / 2, w_fi) + rdot((fep[0] - fem[0]) / 2, w_fe)
+    lam = pk.tendency_adj(plan, par, x[None].contiguous(), w_fi[None].contiguous(), w_fe[None].contiguous())
+    rhs = rdot(d, lam[0])
+    scale = abs(rdot((fep[0] - fem[0]) / 2, w_fe)) + abs(rdot((fip[0] - fim[0]) / 2, w_fi))
+    print("dot", lhs, rhs, abs(lhs - rhs) / scale, flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * scale
+
+
+def test_step_adjoint_T1023_dot_central_difference(pk):
+    """<J d, w> = <d, J^T w> for one step of the large configuration (T1023 /
+    T511, Gauss-Radau 6 / 4 points, 2 + 2 sweeps x 4, dt = 60 s), J d from
+    central differences of the GPU step with a direction of 1e-4 of the
+    state: the step is a polynomial of high degree in the state, so the
+    difference carries an O(eps^2) error, well under the bound."""
+    print("CASE step adjoint T1023 dot", flush=True)
+    par = pk.swe_params()
+    lf = pk.Level(pk.Plan(1023, 1536, 3072), par, pk.SDC_RADAU_RIGHT, 6)
+    lc = pk.Level(pk.Plan(511, 768, 1536), par, pk.SDC_RADAU_RIGHT, 4)
+    st = pk.Stepper(lf, lc, niter=4, nsweep_fine=2, nsweep_coarse=2)
+    N = 1023
+    x = torch.tensor(workload.state(N, 1004), device="cuda")
+    gen = torch.Generator().manual_seed(23)
+    deg = torch.tensor(np.concatenate([np.arange(m, N + 1) for m in range(N + 1)]))
+    m0 = torch.tensor(np.concatenate([np.full(N + 1 - m, m) for m in range(N + 1)]) == 0)
+    d = crandn(x.shape, gen) * (deg + 1.0) ** -1.5
+    d[:, m0] = d[:, m0].real.to(torch.complex128)
+    d[:, deg == 0] = 0
+    for f in range(3):
+        d[f] *= 1e-4 * torch.linalg.vector_norm(x[f].cpu()) / torch.linalg.vector_norm(d[f])
+    d = d.to("cuda")
+    w = crandn(x.shape, gen)
+    for f in range(3):                              # weights of the size of each field's inverse
+        w[f] /= torch.linalg.vector_norm(x[f].cpu())
+    w = w.to("cuda")
+    yp, ym = st.step(60.0, x + d), st.step(60.0, x - d)
+    lhs = rdot((yp - ym) / 2, w)
+    rhs = rdot(d, st.step_adj(60.0, x, w))
+    print("dot", lhs, rhs, abs(lhs - rhs) / abs(lhs), flush=True)
+    assert abs(lhs - rhs) <= 1e-7 * abs(lhs)
 
 
 @pytest.mark.parametrize("which", ["fi", "fe"])
