@@ -42,6 +42,8 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->ck);
     (void)hipFree(p->ckoff);
     (void)hipFree(p->rc);
+    (void)hipFree(p->rq);
+    (void)hipFree(p->cs);
     (void)hipFree(p->pf);
     (void)hipFree(p->ninv);
     (void)hipFree(p->nn1);
@@ -848,6 +850,7 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
               dalloc(&p->ord_e, p->nspec_e) == hipSuccess && dalloc(&p->deg_e, p->nspec_e) == hipSuccess &&
               dalloc(&p->ck, ck_elems) == hipSuccess && dalloc(&p->ckoff, N + 1) == hipSuccess &&
               dalloc(&p->rc, p->nspec_e) == hipSuccess && dalloc(&p->anblk, anblk.size()) == hipSuccess &&
+              dalloc(&p->rq, p->nspec_e) == hipSuccess && dalloc(&p->cs, p->nspec_e) == hipSuccess &&
               dalloc(&p->pf, p->nspec_e) == hipSuccess && dalloc(&p->ninv, N + 3) == hipSuccess &&
               dalloc(&p->nn1, N + 3) == hipSuccess;
     ok = ok && hipMemcpy(p->pf, pf.data(), pf.size() * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;

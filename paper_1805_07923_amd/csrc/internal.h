@@ -209,6 +209,8 @@ struct shx_plan {
     double2* ck = nullptr;
     long long* ckoff = nullptr;     // device [N+1]
     double2* rc = nullptr;          // device [nspec_e]
+    double* rq = nullptr;           // device [nspec_e], (eps^m_{n-1})^2 for n >= m + 2, else 0
+    double* cs = nullptr;           // device [nspec_e], C_n of the restart segments (P = C Q)
     double2* pf = nullptr;          // device [nspec_e], degree factors of swe_prep_row
     double* ninv = nullptr;         // device [N+3], -1/(n(n+1)), 0 at n = 0
     double* nn1 = nullptr;          // device [N+3], n(n+1)

@@ -103,11 +103,15 @@ __device__ __forceinline__ dd dd_eps(int n, int m) {
 // generate P^m_n themselves (at the start of every seg_len segment, so that
 // their plain FP64 recurrence never runs more than 64 steps from an exact
 // value) and
-// the recurrence coefficients 1/eps^m_n and eps^m_{n-1}/eps^m_n.
+// the recurrence coefficients 1/eps^m_n and eps^m_{n-1}/eps^m_n; and, for the
+// analysis' form of the recurrence, Q_n = mu Q_{n-1} - (eps^m_{n-1})^2 Q_{n-2}
+// with P^m_n = C_n Q_n, the coefficients (eps^m_{n-1})^2 and the factors C_n
+// of each restart segment (C = 1 at its first degree, C_n = C_{n-1} / eps^m_n).
 __global__ void k_plm_table(const double* __restrict__ mu, const double* __restrict__ sint,
                             const long long* __restrict__ off, double* __restrict__ psyn,
                             double* __restrict__ pan, double2* __restrict__ ck,
-                            const long long* __restrict__ ckoff, double2* __restrict__ rc, int N, int nmax,
+                            const long long* __restrict__ ckoff, double2* __restrict__ rc,
+                            double* __restrict__ rq, double* __restrict__ cs, int N, int nmax,
                             int Jh) {
     const int jp = blockIdx.x * blockDim.x + threadIdx.x;
     const int m = blockIdx.y;
@@ -126,9 +130,13 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
     double2* ckm = ck + ckoff[m] + jp;
     const int L = seg_len(nmax - m + 1);
     double2* rcm = rc + ext_idx(N, m, m);
+    double* rqm = rq + ext_idx(N, m, m);
+    double* csm = cs + ext_idx(N, m, m);
+    dd cn{1.0, 0.0};                                    // C_n of the current segment
     for (int n = m; n <= nmax; ++n) {
         dd pn;
         double2 r = make_double2(0.0, 0.0);
+        double b = 0.0;
         if (n == m) {
             pn = pmm;
         } else if (n == m + 1) {
@@ -136,11 +144,18 @@ __global__ void k_plm_table(const double* __restrict__ mu, const double* __restr
         } else {
             const dd en = dd_eps(n, m);
             pn = dd_div(dd_sub(dd_mul_d(p1, x), dd_mul(e_prev, p2)), en);
-            const dd ra = dd_div(dd{1.0, 0.0}, en), rb = dd_div(e_prev, en);
+            const dd ra = dd_div(dd{1.0, 0.0}, en), rb = dd_div(e_prev, en), e2 = dd_mul(e_prev, e_prev);
             r = make_double2(ra.h + ra.l, rb.h + rb.l);
+            b = e2.h + e2.l;
             e_prev = en;
         }
-        if (jp == 0) rcm[n - m] = r;
+        if ((n - m) % L == 0) cn = dd{1.0, 0.0};
+        else cn = dd_div(cn, dd_eps(n, m));
+        if (jp == 0) {
+            rcm[n - m] = r;
+            rqm[n - m] = b;
+            csm[n - m] = cn.h + cn.l;
+        }
         if (n > m) { p2 = p1; p1 = pn; }
         const double v = pn.h + pn.l;
         const int g = (n - m) / L, gr = (n - m) - g * L;
@@ -376,7 +391,8 @@ template <int NF>
 __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
                                                   const double2* __restrict__ ck,
                                                   const long long* __restrict__ ckoff,
-                                                  const double2* __restrict__ rc,
+                                                  const double* __restrict__ rq,
+                                                  const double* __restrict__ cs,
                                                   const double* __restrict__ mu,
                                                   const double2* __restrict__ G,
                                                   double2* __restrict__ cout, int N, int nmax_tab,
@@ -400,8 +416,11 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
     double* PE = lsh + wv * (2 * 64 * TP);
     double* PO = PE + 64 * TP;
     double* red = lsh;                                  // [nw][2 tile pairs][2 parities][4][64] afterwards
-    const double2* rcm = rc + ext_idx(N, m, m);
+    const double* rqm = rq + ext_idx(N, m, m);
+    const double* csm = cs + ext_idx(N, m, m);
     const long long rs = (long long)(N + 1) * F * 2;    // latitude row stride of G in doubles
+    // Q_{k0+1} = P_{k0+1} / C_{k0+1} (the segment's second restart value)
+    const double qs = (k0 + 1 < Kt) ? 1.0 / csm[k0 + 1] : 0.0;
     const int jc = i < 2 * NF ? i : 2 * NF - 1;         // B column (clamped; columns >= 2 NF unused)
     for (int s = 0; s < S; ++s) {
         v4d acc[2][2];
@@ -423,18 +442,17 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
                 be[c] = ab ? vn + vs : 0.0;
                 bo[c] = ab ? vn - vs : 0.0;
             }
-            double pe = c0.x, po = c0.y;                // P_{m+k0}, P_{m+k0+1}
+            double pe = c0.x, po = c0.y * qs;           // Q_{m+k0} = P_{m+k0}, Q_{m+k0+1}
             // recurrence coefficients of the 64 degrees: lane t holds degree k0 + t
-            const double2 rcv = rcm[min(k0 + lane, Kt - 1)];
+            const double rbv = rqm[min(k0 + lane, Kt - 1)];
             for (int tp = 0; tp < ntp; ++tp) {
 #pragma unroll
                 for (int i2 = 0; i2 < 16; ++i2) {
                     if (tp > 0 || i2 > 0) {
                         const int t = 32 * tp + 2 * i2;     // wave-uniform lane of the degree
-                        const double r0x = lane_bcast(rcv.x, t), r0y = lane_bcast(rcv.y, t);
-                        const double r1x = lane_bcast(rcv.x, t + 1), r1y = lane_bcast(rcv.y, t + 1);
-                        const double ne = fma(r0x * x, po, -(r0y * pe));
-                        po = fma(r1x * x, ne, -(r1y * po));
+                        const double b0 = lane_bcast(rbv, t), b1 = lane_bcast(rbv, t + 1);
+                        const double ne = fma(x, po, -(b0 * pe));
+                        po = fma(x, ne, -(b1 * po));
                         pe = ne;
                     }
                     PE[lane * TP + i2] = pe;
@@ -476,7 +494,8 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
                 if (k < kend) {
                     double v = 0.0;
                     for (int w = 0; w < nw; ++w) v += red[(((w * 2 + tp) * 2 + eo) * 4 + rr) * 64 + lane];
-                    reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + k) * F + f0)[i] = v;
+                    reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + k) * F + f0)[i] =
+                        csm[k] * v;
                 }
             }
         }
@@ -639,7 +658,8 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
     const int ngrp = (pl->Jh + 63) / 64;
     const int nw = ngrp < 4 ? ngrp : 4;
     const size_t lds = (size_t)nw * 2 * 64 * 17 * sizeof(double);
-    k_leg_an_m<NF><<<pl->an_nblk, 64 * nw, lds, st>>>(pl->anblk, pl->ck, pl->ckoff, pl->rc, pl->mu, G, cout, pl->N,
+    k_leg_an_m<NF><<<pl->an_nblk, 64 * nw, lds, st>>>(pl->anblk, pl->ck, pl->ckoff, pl->rq, pl->cs, pl->mu, G, cout,
+                                                     pl->N,
                                                      pl->nmax, nmax_use, pl->J, F, f0, S,
                                                      (long long)pl->J * (pl->N + 1) * F, pl->nspec_e * F, nw);
 }
@@ -649,6 +669,7 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
 hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
     dim3 grid((pl->Jh + 63) / 64, pl->N + 1);
     k_plm_table<<<grid, 64, 0, st>>>(pl->mu, pl->sint, pl->off, pl->psyn, pl->pan, pl->ck, pl->ckoff, pl->rc,
+                                     pl->rq, pl->cs,
                                      pl->N, pl->nmax, pl->Jh);
     return hipGetLastError();
 }
