@@ -231,7 +231,8 @@ __global__ void k_plm_one(const double* __restrict__ mu, const double* __restric
 template <int NF, int STAGE = 0, int SYN_LS = 1>
 __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2* __restrict__ ck,
                                                    const long long* __restrict__ ckoff,
-                                                   const double2* __restrict__ rc,
+                                                   const double* __restrict__ rq,
+                                                   const double* __restrict__ cs,
                                                    const double* __restrict__ mu,
                                                    const double2* __restrict__ cin,
                                                    double2* __restrict__ out, int N, int nmax_tab,
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
     static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
     constexpr int U = 8;                                // degrees per batch of LDS reads
     constexpr int NG = (2 * NF + 3) / 4;                // groups of 4 real columns
-    extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc
+    extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] coefficients
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, q = lane >> 4;
     const LegTile tile = leg_tile(gx, N + 1, 1);
@@ -262,13 +263,14 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
         x[ls] = mu[active ? jp : 0];
         ckm[ls] = ck + ckoff[m] + (active ? jp : 0);
     }
-    double2* rsh = csh + 4 * (Lmax * NF + 2);
+    double* rsh = reinterpret_cast<double*>(csh + 4 * (Lmax * NF + 2));
     const double* cq = reinterpret_cast<const double*>(csh + q * SC);        // segment q
     int cg[NG];                                         // B columns 4 g + lane % 4 (clamped; >= 2 NF unused)
 #pragma unroll
     for (int g = 0; g < NG; ++g) cg[g] = min(4 * g + (lane & 3), 2 * NF - 1);
-    const double2* rq = rsh + q * SR;
-    const double2* rcm = rc + ext_idx(N, m, m);
+    const double* rqs = rsh + q * SR;
+    const double* rqm = rq + ext_idx(N, m, m);
+    const double* csm = cs + ext_idx(N, m, m);
     const double2* pfm = pf + ext_idx(N, m, m);
     const double ia = 1.0 / a, a2 = a * a, ia2 = ia * ia;
     for (int s = 0; s < S; ++s) {
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
             double2 c0[SYN_LS];                         // in flight during the staging
 #pragma unroll
             for (int ls = 0; ls < SYN_LS; ++ls) c0[ls] = ckm[ls][(long long)g * Jh];
+            const double qinv = (g * L + 1 < Kt) ? 1.0 / csm[g * L + 1] : 0.0;   // Q_{gL+1} = P_{gL+1} / C
             __syncthreads();                            // previous readers of the rows are done
             for (int kl = threadIdx.x; kl < 4 * L; kl += 64 * syn_wb(SYN_LS)) {
                 const int qs = kl / L, ts = kl - qs * L, kk = kr0 + kl;
@@ -293,24 +296,27 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
                         static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
                         double2 o[4];
                         swe_prep_row(cin + s * cin_stride, nspec, N, a2, ia, pfm, ninv, m, m + kk, o);
+                        const double c = csm[kk];
 #pragma unroll
-                        for (int f = 0; f < 4; ++f) row[f] = o[f];
+                        for (int f = 0; f < 4; ++f) row[f] = make_double2(c * o[f].x, c * o[f].y);
                     } else if constexpr (STAGE == 2) {
                         static_assert(STAGE != 2 || NF == 5, "the tendency adjoint synthesises five fields");
                         double2 o[5];
                         swe_combine_adj_row(cin + s * cin_stride, nspec, N, ia, ia2, pfm, nn1, m, m + kk, o);
+                        const double c = csm[kk];
 #pragma unroll
-                        for (int f = 0; f < 5; ++f) row[f] = o[f];
+                        for (int f = 0; f < 5; ++f) row[f] = make_double2(c * o[f].x, c * o[f].y);
                     } else {
                         const double2* cg = cin + s * cin_stride + (ext_idx(N, m, m) + kk) * F + f0;
+                        const double c = csm[kk];
 #pragma unroll
-                        for (int f = 0; f < NF; ++f) row[f] = cg[f];
+                        for (int f = 0; f < NF; ++f) row[f] = make_double2(c * cg[f].x, c * cg[f].y);
                     }
                 } else {
 #pragma unroll
                     for (int f = 0; f < NF; ++f) row[f] = make_double2(0.0, 0.0);
                 }
-                rsh[qs * SR + ts] = (kk < Kt) ? rcm[kk] : make_double2(0.0, 0.0);
+                rsh[qs * SR + ts] = (kk < Kt) ? rqm[kk] : 0.0;
             }
             __syncthreads();
             if (jw >= Jh) continue;                     // uniform: no latitudes for this wavefront
@@ -318,14 +324,14 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
 #pragma unroll
             for (int ls = 0; ls < SYN_LS; ++ls) {
                 pe[ls] = c0[ls].x;
-                po[ls] = c0[ls].y;
+                po[ls] = c0[ls].y * qinv;
             }
             for (int t = 0; t < L; t += U) {
-                double2 rr[U];
+                double rr[U];
                 double bb[U][NG];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    rr[u] = rq[t + u];
+                    rr[u] = rqs[t + u];
 #pragma unroll
                     for (int g = 0; g < NG; ++g) bb[u][g] = cq[(t + u) * 2 * NF + cg[g]];
                 }
@@ -334,8 +340,8 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
 #pragma unroll
                     for (int ls = 0; ls < SYN_LS; ++ls) {
                         if (u > 0 || t > 0) {
-                            const double ne = fma(rr[u].x * x[ls], po[ls], -(rr[u].y * pe[ls]));
-                            po[ls] = fma(rr[u + 1].x * x[ls], ne, -(rr[u + 1].y * po[ls]));
+                            const double ne = fma(x[ls], po[ls], -(rr[u] * pe[ls]));
+                            po[ls] = fma(x[ls], ne, -(rr[u + 1] * po[ls]));
                             pe[ls] = ne;
                         }
 #pragma unroll
@@ -629,12 +635,14 @@ void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, 
     if (pl->Jh >= 384) {
         const int gx = (pl->Jh + syn_lat(2) - 1) / syn_lat(2);
         k_leg_syn_m<NF, STAGE, 2><<<gx * (pl->N + 1), 64 * syn_wb(2), lds, st>>>(
-            pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride, os,
+            pl->ck, pl->ckoff, pl->rq, pl->cs, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S,
+            cin_stride, os,
             gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1);
     } else {
         const int gx = (pl->Jh + syn_lat(1) - 1) / syn_lat(1);
         k_leg_syn_m<NF, STAGE, 1><<<gx * (pl->N + 1), 64 * syn_wb(1), lds, st>>>(
-            pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride, os,
+            pl->ck, pl->ckoff, pl->rq, pl->cs, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S,
+            cin_stride, os,
             gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1);
     }
 }
