@@ -171,13 +171,13 @@ def test_large_mixed(pk, gold, state, prec, tmode):
     lf, lc = levels(pk, prec, tmode)
     _, fe = pk.tendency(lf.plan, pk.swe_params(), state[None].contiguous())
     for f, rec in enumerate(gold["f_explicit"]):
-        est, _ = sampled_error(fe[0, f], rec)
-        print("mixed tendency", prec, tmode, f, est, "emulated", emu[f], flush=True)
-        assert est < 5.0 * emu[f], (f, est, emu[f])
+        est, full = sampled_error(fe[0, f], rec)
+        print("mixed tendency", prec, tmode, f, est, full, "emulated", emu[f], flush=True)
+        assert est < 5.0 * emu[f] and full < 5.0 * emu[f], (f, est, full, emu[f])
     st = pk.Stepper(lf, lc, niter=c["niter"], nsweep_fine=c["nsweep_fine"], nsweep_coarse=c["nsweep_coarse"])
     y = st.step(c["dt"], state)
     for f, rec in enumerate(gold["step"]):
-        est, _ = sampled_error(y[f], rec)
-        print("mixed step", prec, tmode, f, est, flush=True)
-        assert est < BOUND_STEP[prec], (f, est)
+        est, full = sampled_error(y[f], rec)
+        print("mixed step", prec, tmode, f, est, full, flush=True)
+        assert est < BOUND_STEP[prec] and full < BOUND_STEP[prec], (f, est, full)
     assert np.isfinite(torch.view_as_real(y).cpu().numpy()).all()
