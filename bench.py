@@ -56,15 +56,15 @@ def kcount(nmax, m, p):
     return (nmax - m - p) // 2 + 1 if nmax - m - p >= 0 else 0
 
 
-def legendre_bytes(N, J, F, nmax):
-    """Algorithmic HBM bytes of one Legendre launch with the FP64 tables:
-    the table rows for degrees <= nmax (read once), the F-field input and
-    the F-field output (each touched once)."""
-    Jh = J // 2
-    table = sum(kcount(nmax, m, p) for m in range(N + 1) for p in (0, 1)) * Jh * 8
+def legendre_bytes(N, F, terms, fourier_pairs):
+    """Algorithmic HBM bytes of one Legendre analysis launch with the FP64
+    tables: the table values it sums (`terms`, per latitude pair, after the
+    polar truncation; read once), the north and south Fourier rows of the
+    `fourier_pairs` (m, latitude pair) it reads and the F-field output (each
+    touched once).  Both counts come from the plan (shx_plan_analysis_terms)."""
+    table = terms * 8
     ext = (N + 1) * (N + 4) // 2
-    fourier = J * (N + 1) * F * 16
-    return table + fourier + ext * F * 16, table
+    return table + 2 * fourier_pairs * F * 16 + ext * F * 16, table
 
 
 def legendre_flops(N, J, F, nmax):
@@ -583,7 +583,8 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     an_us = e0.elapsed_time(e1) * 1e3 / reps
-    abytes, table_bytes = legendre_bytes(FINE["N"], FINE["J"], 5, FINE["N"] + 1)
+    terms, fpairs = pf.analysis_terms(FINE["N"] + 1)
+    abytes, table_bytes = legendre_bytes(FINE["N"], 5, terms, fpairs)
     achieved = abytes / (an_us * 1e-6) / 1e9
 
     out = {

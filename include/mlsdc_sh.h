@@ -125,6 +125,27 @@ int shx_plan_latitudes(const shx_plan* plan, double* mu, double* sin_theta, doub
  * round or split it as their contractions do).  Synchronous. */
 int shx_plan_legendre(const shx_plan* plan, int m, int n, double* out);
 
+/* Number of table products P^m_n(mu_j) x (north +/- south Fourier data)
+ * that the Legendre analysis (eq. legendre_transform; sh_forward,
+ * sh_legendre_analysis, swe_tendency) forms per field for degrees
+ * n <= nmax (nmax = ntrunc or ntrunc + 1, else SHX_EINVAL), counted per
+ * latitude pair.  Plans that generate P^m_n sum every latitude pair: the
+ * count is sum over (m, n) of nlat/2.  FP64 plans with tables on at most
+ * 512 latitudes apply the polar truncation of the transform library the
+ * method builds on (Sec. 3, Schaeffer 2013) to chunks of up to 6 fields
+ * (fields go in chunks of 8; chunks of 7 or 8 fields sum every pair), and
+ * the count is that of such a chunk.  Per order m, parity of n - m and
+ * tile of 16 such degrees, the latitude pairs are taken in groups of 4 from
+ * the pole (ngrp = ceil(nlat/8) groups); c0 is the first group holding a
+ * |P^m_n| >= 1e-20 for a degree of the tile (ngrp if none); the sum runs
+ * over the groups from max(0, ngrp - B ceil((ngrp - c0) / B)) on, B = 8
+ * from 320 latitudes up and 4 below (whole batches of table loads).  A
+ * coefficient then changes by at most 1e-20 times the sum of
+ * |w_j xi_m(mu_j)| over the omitted latitudes.  *terms receives the count;
+ * *fourier_pairs (if not NULL) the number of (m, latitude pair) whose
+ * Fourier data the analysis reads.  Synchronous. */
+int shx_plan_analysis_terms(const shx_plan* plan, int nmax, long long* terms, long long* fourier_pairs);
+
 /* ------------------------------------------------------- the SH pair */
 
 /* Device workspace bytes for sh_inverse / sh_forward with nfield fields. */

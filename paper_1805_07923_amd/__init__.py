@@ -37,6 +37,7 @@ _SIGS = {
     "shx_plan_destroy": (None, [_P]),
     "shx_plan_latitudes": (_I, [_P, _P, _P, _P]),
     "shx_plan_legendre": (_I, [_P, _I, _I, _P]),
+    "shx_plan_analysis_terms": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
     "shx_workspace_bytes": (_SZ, [_P, _I]),
     "sh_inverse": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
     "sh_forward": (_I, [_P, _I, _P, _P, _P, _SZ, _P]),
@@ -176,6 +177,15 @@ class Plan:
         out = np.empty(self.nlat // 2)
         _check(lib().shx_plan_legendre(self.h, m, n, out.ctypes.data), "shx_plan_legendre")
         return out
+
+    def analysis_terms(self, nmax=None):
+        """(table products per field, (m, latitude pair) Fourier rows read)
+        of the Legendre analysis for degrees <= nmax (default N + 1), after
+        the polar truncation of plans with tables."""
+        t, fp = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib().shx_plan_analysis_terms(self.h, self.N + 1 if nmax is None else nmax, ctypes.byref(t),
+                                             ctypes.byref(fp)), "shx_plan_analysis_terms")
+        return t.value, fp.value
 
     def inverse(self, spec, grid=None):
         """spec complex128 [F, nspec] -> grid float64 [F, nlat, nlon]."""

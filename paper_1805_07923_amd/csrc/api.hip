@@ -32,6 +32,7 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->pan);
     (void)hipFree(p->pan4);
     (void)hipFree(p->off4);
+    (void)hipFree(p->an_c0);
     (void)hipFree(p->psyn32);
     (void)hipFree(p->pan32);
     (void)hipFree(p->an16);
@@ -857,8 +858,6 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
     ok = ok && hipMemcpy(p->ninv, ninv.data(), (N + 3) * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->nn1, nn1.data(), (N + 3) * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->anblk, anblk.data(), anblk.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && dalloc(&p->tblk, tblk.size()) == hipSuccess &&
-         hipMemcpy(p->tblk, tblk.data(), tblk.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->ckoff, ckoff.data(), (N + 1) * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(p->ck, 0, ck_elems * sizeof(double2)) == hipSuccess;
     ok = ok && hipMemcpy(p->mu, p->h_mu.data(), J * 8, hipMemcpyHostToDevice) == hipSuccess;
@@ -883,9 +882,44 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
             tot += sz;
             mx = sz > mx ? sz : mx;
         }
+        p->an_kt = (kcount(p->nmax, 0, 0) + 15) / 16;   // tiles of the largest block (m = 0, p = 0)
         ok = dalloc(&p->pan4, tot) == hipSuccess && dalloc(&p->off4, off4.size()) == hipSuccess &&
+             dalloc(&p->an_c0, (size_t)2 * (N + 1) * p->an_kt) == hipSuccess &&
              hipMemcpy(p->off4, off4.data(), off4.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-             launch_an_tab4(p, mx, 0) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+             launch_an_tab4(p, mx, 0) == hipSuccess && launch_an_polar(p, 0) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+        // block list with the first summed latitude group of each of the
+        // block's four tiles (a byte each) and their minimum
+        p->h_an_c0.assign((size_t)2 * (N + 1) * p->an_kt, 0);
+        ok = ok && hipMemcpy(p->h_an_c0.data(), p->an_c0, p->h_an_c0.size() * sizeof(int),
+                             hipMemcpyDeviceToHost) == hipSuccess;
+        const int B = an_batch(p->Jh);
+        for (int& c : p->h_an_c0) {                     // whole batches of loads from the first summed group
+            const int run = B * ((ngrp - c + B - 1) / B);
+            c = ngrp - run > 0 ? ngrp - run : 0;
+        }
+        (void)hipFree(p->an_c0);
+        p->an_c0 = nullptr;
+        std::vector<int> tb4(4 * (size_t)p->tb_nblk, -1);
+        for (int b = 0; ok && b < p->tb_nblk; ++b) {
+            const int mp = tblk[2 * b], tx = tblk[2 * b + 1];
+            if (mp < 0) continue;
+            const int K = kcount(p->nmax, mp >> 1, mp & 1);
+            unsigned packed = 0;
+            int cmin = ngrp;
+            for (int w = 0; w < 4; ++w) {
+                const int kt = 4 * tx + w;
+                const int c = (16 * kt < K) ? p->h_an_c0[(size_t)mp * p->an_kt + kt] : ngrp;
+                packed |= (unsigned)c << (8 * w);
+                cmin = c < cmin ? c : cmin;
+            }
+            tb4[4 * b] = mp;
+            tb4[4 * b + 1] = tx;
+            tb4[4 * b + 2] = (int)packed;
+            tb4[4 * b + 3] = cmin;
+        }
+        ok = ok && dalloc(&p->tblk, tb4.size()) == hipSuccess &&
+             hipMemcpy(p->tblk, tb4.data(), tb4.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
         if (ok) {                                       // the [m][p][jp][k] layout has no other reader here
             (void)hipFree(p->pan);
             p->pan = nullptr;
@@ -910,6 +944,29 @@ int shx_plan_latitudes(const shx_plan* pl, double* mu, double* st, double* w) {
         if (st) st[j] = pl->h_sint[j];
         if (w) w[j] = pl->h_w[j];
     }
+    return SHX_OK;
+}
+
+int shx_plan_analysis_terms(const shx_plan* pl, int nmax, long long* terms, long long* fourier_pairs) {
+    if (!pl || !terms || (nmax != pl->N && nmax != pl->N + 1)) return SHX_EINVAL;
+    const std::vector<int>& c0 = pl->h_an_c0;
+    long long t = 0, fp = 0;
+    for (int m = 0; m <= pl->N; ++m) {
+        int first = pl->Jh;                             // first latitude pair read for this order
+        for (int p = 0; p < 2; ++p) {
+            const int mp = 2 * m + p, K = kcount(nmax, m, p);
+            for (int kt = 0; 16 * kt < K; ++kt) {
+                const int rows = K - 16 * kt < 16 ? K - 16 * kt : 16;
+                int j0 = pl->pan4 ? 4 * c0[(size_t)mp * pl->an_kt + kt] : 0;
+                j0 = j0 < pl->Jh ? j0 : pl->Jh;
+                t += (long long)rows * (pl->Jh - j0);
+                first = j0 < first ? j0 : first;
+            }
+        }
+        fp += pl->Jh - first;
+    }
+    *terms = t;
+    if (fourier_pairs) *fourier_pairs = fp;
     return SHX_OK;
 }
 

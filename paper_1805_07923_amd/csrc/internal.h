@@ -20,11 +20,26 @@ __host__ __device__ inline long long ext_idx(int N, int m, int n) {
 __host__ __device__ inline long long nspec_of(int N) { return (long long)(N + 1) * (N + 2) / 2; }
 __host__ __device__ inline long long nspec_ext_of(int N) { return (long long)(N + 1) * (N + 4) / 2; }
 
-// Rows of the parity block p (n - m = p mod 2) of order m for degrees <= nmax.
 // latitude pairs up to which the FP64 analysis of up to 6 fields streams
 // its table (beyond: the matrix-core kernel that generates P^m_n)
 constexpr int AN_TAB_JH = 256;
 
+// Polar truncation of the table analysis (the near-pole omission of the
+// transform library of Sec. 3, Schaeffer 2013): a group of 4 latitude pairs
+// is left out of the sum for a 16-degree tile when it and every group nearer
+// the pole hold only |P^m_n| < AN_POLAR_TAU.  A coefficient then changes by
+// at most AN_POLAR_TAU times the sum of |weighted Fourier data| over the
+// omitted latitudes, 10^4 below the FP64 unit roundoff relative to the data.
+constexpr double AN_POLAR_TAU = 1e-20;
+// Table loads in flight per lane in the table analysis: batches of 8 groups
+// of 4 latitude pairs from 160 pairs up, of 4 below (measured: T255 17.4
+// against 17.7 us with 4, T127 9.0 against 9.3 with 8).  The summed run of
+// a tile starts where it holds whole batches (a ragged run would wait for
+// its last loads one at a time): at max(0, ngrp - B ceil((ngrp - c0) / B))
+// for the first group c0 with |P^m_n| >= AN_POLAR_TAU and ngrp groups.
+constexpr int an_batch(int Jh) { return Jh >= 160 ? 8 : 4; }
+
+// Rows of the parity block p (n - m = p mod 2) of order m for degrees <= nmax.
 __host__ __device__ inline int kcount(int nmax, int m, int p) {
     return (nmax - m - p >= 0) ? (nmax - m - p) / 2 + 1 : 0;
 }
@@ -201,6 +216,12 @@ struct shx_plan {
     // 64 consecutive values.
     double* pan4 = nullptr;
     long long* off4 = nullptr;
+    // an_c0[(2m+p) * an_kt + kt]: first latitude group c of tile kt of pan4
+    // that holds a value of magnitude >= AN_POLAR_TAU (ngrp if none); an_kt =
+    // tiles of the largest order-parity block.  Set-up only: h_an_c0 keeps
+    // the first summed groups (moved back to whole load batches).
+    int* an_c0 = nullptr;
+    int an_kt = 0;
     // Recurrence data of the FP64 kernels that generate P^m_n in registers:
     // ck[ckoff[m] + g * Jh + jp] = (P^m_{m+g*L}, P^m_{m+g*L+1}) at mu_jp for the
     // 4 R segments g of the order (L = seg_len, R = seg_rounds of its
@@ -219,9 +240,11 @@ struct shx_plan {
     // for padding.
     int* anblk = nullptr;
     int an_nblk = 0;
-    // Blocks of the table analysis, (2 m + p, degree tile) pairs [2 tb_nblk]
-    // for the tiles of 64 degrees that hold rows (n <= N+1), listed XCD by XCD
-    // as anblk, (-1, -1) for padding.
+    // Blocks of the table analysis [4 tb_nblk]: (2 m + p, tile of 64 degrees,
+    // first summed latitude group of each of its four 16-degree tiles (byte
+    // w for tile w; ngrp past the rows), the smallest of these) for the tiles
+    // that hold rows (n <= N+1), listed XCD by XCD as anblk, -1 for padding.
+    // Only plans with pan4 have it.
     int* tblk = nullptr;
     int tb_nblk = 0;
     int* ord = nullptr;             // device [nspec] zonal order of each entry
@@ -231,6 +254,7 @@ struct shx_plan {
     long long table_elems = 0;
     std::vector<double> h_mu, h_sint, h_cos2, h_w;
     std::vector<long long> h_off;
+    std::vector<int> h_an_c0;       // first summed group per tile, an_c0's layout (plans with pan4)
 };
 
 struct sdc_level {
@@ -254,6 +278,7 @@ struct Mat9x9 {
 // legendre.hip
 hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st);
 hipError_t launch_an_tab4(const shx_plan* pl, long long max_block, hipStream_t st);
+hipError_t launch_an_polar(const shx_plan* pl, hipStream_t st);
 // P^m_n at the northern latitudes by the double-double recurrence, rounded to
 // FP64, into out[Jh] (device): the table export of plans without tables.
 hipError_t launch_plm_one(const shx_plan* pl, int m, int n, double* out, hipStream_t st);

@@ -22,7 +22,6 @@
 
 namespace {
 
-constexpr int UNR = 8;   // table loads in flight per lane
 // matrix-core synthesis with LS sets of 16 latitudes per wavefront: 4
 // wavefronts per block for one set, 3 for two (96 latitudes per block)
 __host__ __device__ constexpr int syn_wb(int LS) { return LS == 1 ? 4 : 3; }
@@ -525,6 +524,24 @@ __global__ void k_an_tab4(const double* __restrict__ pan, const long long* __res
     pan4[off4[mp] + e] = (k < K && jp < Jh) ? pan[off[mp] + (long long)jp * K + k] : 0.0;
 }
 
+// First summed latitude group of each 16-degree tile of pan4 (an_c0 in
+// shx_plan): one wavefront per (tile kt, order-parity block blockIdx.y)
+// scans the groups from the pole and stops at the first with a value of
+// magnitude >= tau.
+__global__ __launch_bounds__(64) void k_an_polar(const double* __restrict__ pan4,
+                                                 const long long* __restrict__ off4, int* __restrict__ c0,
+                                                 int nmax, int Jh, int kt_all, double tau) {
+    const int mp = blockIdx.y, kt = blockIdx.x, lane = threadIdx.x;
+    const int ngrp = (Jh + 3) / 4;
+    int c = ngrp;
+    if (16 * kt < kcount(nmax, mp >> 1, mp & 1)) {
+        const double* t = pan4 + off4[mp] + (long long)kt * ngrp * 64 + lane;
+        for (c = 0; c < ngrp; ++c)
+            if (__ballot(fabs(t[(long long)c * 64]) >= tau) != 0) break;
+    }
+    if (lane == 0) c0[mp * kt_all + kt] = c;
+}
+
 // Analysis from the table on the matrix cores (up to AN_TAB_JH latitude
 // pairs and 6 fields; beyond, k_leg_an_m generates P^m_n instead):
 // cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
@@ -539,9 +556,12 @@ __global__ void k_an_tab4(const double* __restrict__ pan, const long long* __res
 // column 4 g + j.  With an odd field count the last field's two columns are
 // summed on the VALU by each lane over its latitude slot (lane / 16) and the
 // four slots added by lane exchange, instead of a third, half-empty matrix
-// product per group.
-template <int NF>
-__global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, const double* __restrict__ pan4,
+// product per group.  Each wavefront starts at its tile's first summed group
+// (polar truncation, AN_POLAR_TAU; the run is whole batches of UNR =
+// an_batch(Jh) loads), and the block stages the Fourier data from the
+// smallest first group of its tiles on.
+template <int NF, int UNR>
+__global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, const double* __restrict__ pan4,
                                                   const long long* __restrict__ off4,
                                                   const double2* __restrict__ G,
                                                   double2* __restrict__ cout, int N, int nmax_tab,
@@ -551,7 +571,8 @@ __global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, co
     constexpr bool ODD = NF % 2 == 1;                   // last field: its two columns on the VALU
     extern __shared__ double2 gsh[];                    // [Jh][NF]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int mp = tblk[2 * blockIdx.x], tx = tblk[2 * blockIdx.x + 1];
+    const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
+    const int mp = tb.x, tx = tb.y;
     if (mp < 0) return;                                 // padding block (uniform)
     const int m = mp >> 1, p = mp & 1;
     const int K = kcount(nmax_use, m, p);
@@ -562,6 +583,10 @@ __global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, co
     const int ngrp = (Jh + 3) / 4;                      // groups of 4 latitude pairs
     // A operands of this wavefront's 16 degrees: 64 consecutive values per group
     const double* P = pan4 + off4[2 * m + p] + (long long)(k0 >> 4) * ngrp * 64 + lane;
+    const int cb0 = tb.w;                               // first staged latitude group
+    // this wavefront's first group (wave-uniform: kept in a scalar register
+    // so that the group loop and its addresses stay scalar)
+    const int cw0 = __builtin_amdgcn_readfirstlane((k0 < K) ? (tb.z >> (8 * wv)) & 255 : ngrp);
     const double sg = p ? -1.0 : 1.0;
     const long long rowstride = (long long)(N + 1) * F;
     const double* gs = reinterpret_cast<const double*>(gsh);
@@ -569,7 +594,7 @@ __global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, co
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();                                // previous state's readers are done
-        for (int i = threadIdx.x; i < Jh * NF; i += 256) {
+        for (int i = 4 * cb0 * NF + threadIdx.x; i < Jh * NF; i += 256) {
             const int jp = i / NF, f = i - jp * NF;
             const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
             gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
@@ -593,15 +618,18 @@ __global__ __launch_bounds__(256) void k_leg_an(const int* __restrict__ tblk, co
                 vi = fma(a, z.y, vi);
             }
         };
+        // groups cw0 + c, c = 0 .. nrun-1 (nrun a multiple of UNR where ngrp allows)
+        const double* Pw = P + (long long)cw0 * 64;
+        const int nrun = ngrp - cw0, jw = 4 * cw0 + kq;
         int c = 0;
-        for (; c + UNR <= ngrp; c += UNR) {
+        for (; c + UNR <= nrun; c += UNR) {
             double pv[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) pv[u] = P[(long long)(c + u) * 64];
+            for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * 64];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) step(pv[u], 4 * (c + u) + kq);
+            for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
         }
-        for (; c < ngrp; ++c) step(P[(long long)c * 64], 4 * c + kq);
+        for (; c < nrun; ++c) step(Pw[c * 64], jw + 4 * c);
         // MFMA D: lane 4 b + j + 16 i holds degree row 4 b + i, column 4 g + j
         const int k = k0 + 4 * ((lane & 15) >> 2) + (lane >> 4);
         if (k < K) {
@@ -658,9 +686,14 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
               hipStream_t st) {
     if (NF <= 6 && pl->pan4) {                         // FP64 plans with tables, Jh <= AN_TAB_JH
         const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
-        k_leg_an<NF><<<pl->tb_nblk, 256, lds, st>>>(pl->tblk, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax, nmax_use,
-                                                   pl->J, F, f0, S, (long long)pl->J * (pl->N + 1) * F,
-                                                   pl->nspec_e * F);
+        const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
+        const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
+        if (an_batch(pl->Jh) == 8)
+            k_leg_an<NF, 8><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
+                                                          nmax_use, pl->J, F, f0, S, gst, cst);
+        else
+            k_leg_an<NF, 4><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
+                                                          nmax_use, pl->J, F, f0, S, gst, cst);
         return;
     }
     const int ngrp = (pl->Jh + 63) / 64;
@@ -685,6 +718,12 @@ hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
 hipError_t launch_an_tab4(const shx_plan* pl, long long max_block, hipStream_t st) {
     dim3 grid((unsigned)((max_block + 255) / 256), 2 * (pl->N + 1));
     k_an_tab4<<<grid, 256, 0, st>>>(pl->pan, pl->off, pl->off4, pl->pan4, pl->nmax, pl->Jh);
+    return hipGetLastError();
+}
+
+hipError_t launch_an_polar(const shx_plan* pl, hipStream_t st) {
+    dim3 grid(pl->an_kt, 2 * (pl->N + 1));
+    k_an_polar<<<grid, 64, 0, st>>>(pl->pan4, pl->off4, pl->an_c0, pl->nmax, pl->Jh, pl->an_kt, AN_POLAR_TAU);
     return hipGetLastError();
 }
 

@@ -87,6 +87,8 @@ int main() {
     CHECK(sdc_level_create(nullptr, &par, 0, 3, &lv) == SHX_EINVAL);
     CHECK(sh_inverse(nullptr, 1, nullptr, nullptr, nullptr, 0, nullptr) == SHX_EINVAL);
     CHECK(sh_forward(nullptr, 1, nullptr, nullptr, nullptr, 0, nullptr) == SHX_EINVAL);
+    long long terms = 0;
+    CHECK(shx_plan_analysis_terms(nullptr, 31, &terms, nullptr) == SHX_EINVAL);
     CHECK(swe_tendency(nullptr, &par, 1, nullptr, nullptr, nullptr, nullptr, 0, nullptr) == SHX_EINVAL);
     CHECK(mlsdc_step(nullptr, nullptr, nullptr, 1.0, nullptr, nullptr, nullptr, nullptr, 0, nullptr) == SHX_EINVAL);
     CHECK(mlsdc_step_noalloc(nullptr, nullptr, nullptr, 1.0, nullptr, nullptr, nullptr, nullptr) == SHX_EINVAL);

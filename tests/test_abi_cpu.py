@@ -51,6 +51,7 @@ def test_argument_validation_without_device():
     par = pk.swe_params()
     assert L.sdc_level_create(None, ctypes.byref(par), 0, 3, ctypes.byref(h)) == -1
     assert L.sh_inverse(None, 1, None, None, None, 0, None) == -1
+    assert L.shx_plan_analysis_terms(None, 31, None, None) == -1
     assert L.mlsdc_step(None, None, None, 1.0, None, None, None, None, 0, None) == -1
     assert L.mlsdc_step_noalloc(None, None, None, 1.0, None, None, None, None) == -1
 
