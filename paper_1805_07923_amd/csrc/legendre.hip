@@ -570,7 +570,7 @@ __global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, c
     constexpr int NG = NF / 2;                          // groups of 4 real columns (two fields) on MFMA
     constexpr bool ODD = NF % 2 == 1;                   // last field: its two columns on the VALU
     extern __shared__ double2 gsh[];                    // [Jh][NF]
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
     const int mp = tb.x, tx = tb.y;
     if (mp < 0) return;                                 // padding block (uniform)
@@ -591,6 +591,18 @@ __global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, c
     const long long rowstride = (long long)(N + 1) * F;
     const double* gs = reinterpret_cast<const double*>(gsh);
     const int cb = lane & 3;                            // B column within a group
+    // groups cw0 + c, c = 0 .. nrun-1 (nrun a multiple of UNR where ngrp allows)
+    const double* Pw = P + (long long)cw0 * 64;
+    const int nrun = ngrp - cw0, jw = 4 * cw0 + kq;
+    // the first batch of table values is loaded before the Fourier data are
+    // staged, so that the two memory round trips overlap; the table is the
+    // same for every state
+    const bool pre = k0 < K && nrun >= UNR;             // wave-uniform
+    double pv0[UNR];
+    if (pre) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * 64];
+    }
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();                                // previous state's readers are done
@@ -618,10 +630,12 @@ __global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, c
                 vi = fma(a, z.y, vi);
             }
         };
-        // groups cw0 + c, c = 0 .. nrun-1 (nrun a multiple of UNR where ngrp allows)
-        const double* Pw = P + (long long)cw0 * 64;
-        const int nrun = ngrp - cw0, jw = 4 * cw0 + kq;
         int c = 0;
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) step(pv0[u], jw + 4 * u);
+            c = UNR;
+        }
         for (; c + UNR <= nrun; c += UNR) {
             double pv[UNR];
 #pragma unroll
