@@ -137,19 +137,29 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
     const shx_plan* pl = lv->plan;
     const int M = lv->nnodes - 1, n1 = lv->nnodes;
     const size_t ns3 = 3 * (size_t)pl->nspec;
+    NodeRows rows{};
+    for (int m = 0; m < M; ++m) {
+        for (int j = 0; j < n1; ++j) {
+            rows.q[m][j] = dt * lv->Q[(m + 1) * n1 + j];
+            rows.qe[m][j] = dt * lv->QE[(m + 1) * n1 + j];
+            rows.qd[m][j] = dt * lv->QD[(m + 1) * n1 + j];
+        }
+        rows.h[m] = dt * lv->QD[(m + 1) * n1 + (m + 1)];
+    }
     for (int m = 0; m < M; ++m) {
         NodeWeights wt;
         for (int j = 0; j < 9; ++j) {
-            const bool in = j < n1;
-            wt.q[j] = in ? dt * lv->Q[(m + 1) * n1 + j] : 0.0;
-            wt.qe[j] = in ? dt * lv->QE[(m + 1) * n1 + j] : 0.0;
-            wt.qd[j] = in ? dt * lv->QD[(m + 1) * n1 + j] : 0.0;
+            wt.q[j] = j < n1 ? rows.q[m][j] : 0.0;
+            wt.qe[j] = j < n1 ? rows.qe[m][j] : 0.0;
+            wt.qd[j] = j < n1 ? rows.qd[m][j] : 0.0;
         }
-        const double h = dt * lv->QD[(m + 1) * n1 + (m + 1)];
-        // the F of node m (m >= 1) is formed inside this node update from t.cout
+        double2* r = rec ? rec + (size_t)m * ns3 : nullptr;
+        // the first update forms the old-F part of every node's right-hand
+        // side (held in fe_new at nodes 2..M until those are written); the
+        // F of node m (m >= 1) is formed inside node m's update from t.cout
         HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
-            return launch_sdc_node(pl, lv->p, m, M, wt, h, th, th, fi_new, fe_new, fi_old, fe_old, tau,
-                                   m > 0 ? t.cout : nullptr, rec ? rec + (size_t)m * ns3 : nullptr, st);
+            return m == 0 ? launch_sdc_node_first(pl, lv->p, M, rows, th, fi_old, fe_old, tau, fe_new, r, st)
+                          : launch_sdc_node(pl, lv->p, m, M, wt, rows.h[m], th, fi_new, fe_new, t.cout, r, st);
         }));
         const size_t o = (size_t)(m + 1) * ns3;
         int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st, false);

@@ -273,6 +273,13 @@ struct NodeWeights {
 struct Mat9x9 {
     double a[81];
 };
+// The weights of every node update of a sweep (row m = node m+1, M <= 8).
+struct NodeRows {
+    double q[8][9];   // dt * Q[m+1][j]
+    double qe[8][9];  // dt * QE[m+1][j]
+    double qd[8][9];  // dt * QD[m+1][j]
+    double h[8];      // dt * QD[m+1][m+1]
+};
 
 // ----------------------------------------------------- launch wrappers
 // legendre.hip
@@ -326,10 +333,12 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
 // cout_m != nullptr (m >= 1): the new F at node m is formed from these
 // analyses of node m's tendency inside the node update (and stored).
 // rec != nullptr: Theta^{m+1} is also stored there (the adjoint's tape).
+hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
+                                 double2* theta, const double2* fi_old, const double2* fe_old, const double2* tau,
+                                 double2* sq, double2* rec, hipStream_t st);
 hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
-                           double h, const double2* theta0, double2* theta, double2* fi, double2* fe,
-                           const double2* fi_old, const double2* fe_old, const double2* tau,
-                           const double2* cout_m, double2* rec, hipStream_t st);
+                           double h, double2* theta, double2* fi, double2* fe, const double2* cout_m,
+                           double2* rec, hipStream_t st);
 hipError_t launch_restrict(const shx_plan* fine, const shx_plan* coarse, const Mat9x9& Pi, int nsrc,
                            int i0, int i1, const double2* src, double2* dst, double2* dst2, hipStream_t st);
 // Copies of node 0 of up to 6 node arrays to node ranges of (other) node arrays.

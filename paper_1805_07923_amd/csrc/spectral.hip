@@ -177,27 +177,95 @@ __global__ void k_imex_solve(const int* __restrict__ deg, const double2* rhs, do
     x[2 * nspec + i] = xd;
 }
 
-// Node update of the sweep for node m+1 (m = 0..M-1):
-//   b = Theta^0 + sum_j dtQ[m+1][j] (F_I + F_E)^{j,old}
-//       + sum_{j=1}^{m} [dtQE[m+1][j] dF_E^j + dtQD[m+1][j] dF_I^j]
-//       - h F_I^{m+1,old} + tau^{m+1},   Theta^{m+1} = solve(b, h).
-// With cout != nullptr (m >= 1) the new F at node m is not yet formed: it is
-// combined here from the analyses of node m's tendency (cout) and Theta^m,
-// stored to (fi, fe) node m and used directly.  Blocks of NODE_CO
-// coefficients x 3 fields: thread group c accumulates field c; the 2 x 2
-// solve of (Phi', delta) meets the three right-hand sides in LDS.  32
-// coefficients per block (96 threads, a quarter of the second wave idle)
-// measured faster than 64 (8.8 vs 10.1 us at T255): twice the blocks spread
-// the memory-bound loop over more CUs.
+// Node updates of a sweep, nodes m+1 = 1..M (eq. update_equation_sdcq_discrete_form
+// and eq. modified_update_equation_sdcq_discrete_form with the IMEX split):
+//   b_m = Theta^0 + sum_j dtQ[m+1][j] (F_I + F_E)^{j,old}
+//         + sum_{j=1}^{m} [dtQE[m+1][j] dF_E^j + dtQD[m+1][j] dF_I^j]
+//         - h_m F_I^{m+1,old} + tau^{m+1},   Theta^{m+1} = solve(b_m, h_m),
+// with dF^j = F^{j,new} - F^{j,old}.  The part of b_m that holds no new F,
+//   S_m = Theta^0 + sum_j dtQ[m+1][j] (F_I + F_E)^{j,old}
+//         - sum_{j=1}^{m} [dtQE[m+1][j] F_E^{j,old} + dtQD[m+1][j] F_I^{j,old}]
+//         - h_m F_I^{m+1,old} + tau^{m+1},
+// is formed for every m by the first update (k_sdc_node_first), which reads
+// the old F once: it solves with S_0 and stores S_m, m >= 1, in the slot of
+// the new F_E of node m+1, which the sweep fills only later (node m+1's
+// update, or the closing combine for node M).  k_sdc_node (m >= 1) reads
+// S_m, forms the new F at node m from the analyses of node m's tendency
+// (cout) and Theta^m, stores it to (fi, fe) node m, and adds
+// sum_{j=1}^{m} [dtQE[m+1][j] F_E^{j,new} + dtQD[m+1][j] F_I^{j,new}].
+// Blocks of NODE_CO coefficients x 3 fields: thread group c accumulates
+// field c; the 2 x 2 solve of (Phi', delta) meets the three right-hand
+// sides in LDS.  32 coefficients per block (96 threads, a quarter of the
+// second wave idle) measured faster than 64 (8.8 vs 10.1 us at T255): twice
+// the blocks spread the memory-bound loop over more CUs.
 constexpr int NODE_CO = 32;
+
+__device__ __forceinline__ void node_solve(const int* __restrict__ deg, const swe_params& p, double h, int c,
+                                           int loc, long long i, bool on, double2 acc, double2 (*bsh)[NODE_CO],
+                                           double2* __restrict__ out, double2* __restrict__ rec, long long o) {
+    bsh[c][loc] = acc;
+    __syncthreads();
+    if (!on) return;
+    const int n = deg[i];
+    const double L = n * (n + 1.0) / (p.a * p.a);
+    double2 xp, xz, xd;
+    solve_one(L, h, p, bsh[0][loc], bsh[1][loc], bsh[2][loc], xp, xz, xd);
+    const double2 v = (c == 0) ? xp : ((c == 1) ? xz : xd);
+    out[o] = v;
+    if (rec) rec[o] = v;
+}
+
+__global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node_first(const int* __restrict__ deg, long long nspec,
+                                                              swe_params p, int M, NodeRows R,
+                                                              double2* __restrict__ theta,
+                                                              const double2* __restrict__ fi_old,
+                                                              const double2* __restrict__ fe_old,
+                                                              const double2* __restrict__ tau,
+                                                              double2* __restrict__ sq,
+                                                              double2* __restrict__ rec) {
+    __shared__ double2 bsh[3][NODE_CO];
+    const int c = threadIdx.x / NODE_CO, loc = threadIdx.x - c * NODE_CO;
+    const long long i = (long long)blockIdx.x * NODE_CO + loc;
+    const bool on = i < nspec;
+    const long long ns3 = 3 * nspec, o = c * nspec + i;
+    double2 acc0 = make_double2(0.0, 0.0);
+    if (on) {
+        double2 fi[9], fe[9];                           // the old F at nodes 0..M (M <= 8)
+#pragma unroll
+        for (int j = 0; j < 9; ++j)
+            if (j <= M) {
+                fi[j] = fi_old[j * ns3 + o];
+                fe[j] = fe_old[j * ns3 + o];
+            }
+        const double2 t0 = theta[o];
+        for (int m = 0; m < M; ++m) {
+            double2 acc = t0;
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+                if (j <= M) acc = caxpy(R.q[m][j], cadd(fi[j], fe[j]), acc);
+#pragma unroll
+            for (int j = 1; j < 9; ++j)
+                if (j <= m) {
+                    acc = caxpy(-R.qe[m][j], fe[j], acc);
+                    acc = caxpy(-R.qd[m][j], fi[j], acc);
+                }
+#pragma unroll
+            for (int j = 1; j < 9; ++j)
+                if (j == m + 1) acc = caxpy(-R.h[m], fi[j], acc);
+            if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + o]);
+            if (m == 0)
+                acc0 = acc;
+            else
+                sq[(m + 1) * ns3 + o] = acc;
+        }
+    }
+    node_solve(deg, p, R.h[0], c, loc, i, on, acc0, bsh, theta + ns3, rec, o);
+}
+
 __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ deg,
-                                                        int N, long long nspec, swe_params p, int m, int M,
-                                                        NodeWeights wt, double h, const double2* __restrict__ th0,
-                                                        double2* __restrict__ theta, double2* __restrict__ fi,
-                                                        double2* __restrict__ fe,
-                                                        const double2* __restrict__ fi_old,
-                                                        const double2* __restrict__ fe_old,
-                                                        const double2* __restrict__ tau,
+                                                        int N, long long nspec, swe_params p, int m,
+                                                        NodeWeights wt, double h, double2* __restrict__ theta,
+                                                        double2* __restrict__ fi, double2* __restrict__ fe,
                                                         const double2* __restrict__ cout,
                                                         double2* __restrict__ rec) {
     __shared__ double2 bsh[3][NODE_CO];
@@ -207,39 +275,19 @@ __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict_
     const long long ns3 = 3 * nspec, o = c * nspec + i;
     double2 acc = make_double2(0.0, 0.0);
     if (on) {
-        double2 fem = acc, fim = acc;
-        if (cout) {
-            combine_field(cout, theta + m * ns3, N, nspec, p, i, ord[i], deg[i], c, fem, fim);
-            fe[m * ns3 + o] = fem;
-            fi[m * ns3 + o] = fim;
+        double2 fem, fim;
+        combine_field(cout, theta + m * ns3, N, nspec, p, i, ord[i], deg[i], c, fem, fim);
+        acc = fe[(m + 1) * ns3 + o];                    // S_m from the sweep's first update
+        fe[m * ns3 + o] = fem;
+        fi[m * ns3 + o] = fim;
+        for (int j = 1; j < m; ++j) {
+            acc = caxpy(wt.qe[j], fe[j * ns3 + o], acc);
+            acc = caxpy(wt.qd[j], fi[j * ns3 + o], acc);
         }
-        acc = th0[o];
-        for (int j = 0; j <= M; ++j) {
-            const double2 f = cadd(fi_old[j * ns3 + o], fe_old[j * ns3 + o]);
-            acc = caxpy(wt.q[j], f, acc);
-        }
-        const int jm = cout ? m - 1 : m;               // nodes read back from memory
-        for (int j = 1; j <= jm; ++j) {
-            acc = caxpy(wt.qe[j], csub(fe[j * ns3 + o], fe_old[j * ns3 + o]), acc);
-            acc = caxpy(wt.qd[j], csub(fi[j * ns3 + o], fi_old[j * ns3 + o]), acc);
-        }
-        if (cout) {
-            acc = caxpy(wt.qe[m], csub(fem, fe_old[m * ns3 + o]), acc);
-            acc = caxpy(wt.qd[m], csub(fim, fi_old[m * ns3 + o]), acc);
-        }
-        acc = caxpy(-h, fi_old[(m + 1) * ns3 + o], acc);
-        if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + o]);
+        acc = caxpy(wt.qe[m], fem, acc);
+        acc = caxpy(wt.qd[m], fim, acc);
     }
-    bsh[c][loc] = acc;
-    __syncthreads();
-    if (!on) return;
-    const int n = deg[i];
-    const double L = n * (n + 1.0) / (p.a * p.a);
-    double2 xp, xz, xd;
-    solve_one(L, h, p, bsh[0][loc], bsh[1][loc], bsh[2][loc], xp, xz, xd);
-    const double2 v = (c == 0) ? xp : ((c == 1) ? xz : xd);
-    theta[(m + 1) * ns3 + o] = v;
-    if (rec) rec[o] = v;
+    node_solve(deg, p, h, c, loc, i, on, acc, bsh, theta + (m + 1) * ns3, rec, o);
 }
 
 // dst[i][c] = sum_j Pi[i][j] src[j][map(c)], i in [i0, i1); c runs over the
@@ -422,14 +470,22 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
     return hipGetLastError();
 }
 
-hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
-                           double h, const double2* theta0, double2* theta, double2* fi, double2* fe,
-                           const double2* fi_old, const double2* fe_old, const double2* tau,
-                           const double2* cout_m, double2* rec, hipStream_t st) {
-    if (cout_m && m < 1) return hipErrorInvalidValue;
+hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
+                                 double2* theta, const double2* fi_old, const double2* fe_old, const double2* tau,
+                                 double2* sq, double2* rec, hipStream_t st) {
+    if (M < 1 || M > 8) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((pl->nspec + NODE_CO - 1) / NODE_CO);
-    k_sdc_node<<<nb, 3 * NODE_CO, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, m, M, wts, h, theta0, theta, fi,
-                                          fe, fi_old, fe_old, tau, cout_m, rec);
+    k_sdc_node_first<<<nb, 3 * NODE_CO, 0, st>>>(pl->deg, pl->nspec, p, M, rows, theta, fi_old, fe_old, tau, sq, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
+                           double h, double2* theta, double2* fi, double2* fe, const double2* cout_m,
+                           double2* rec, hipStream_t st) {
+    if (!cout_m || m < 1 || m >= M) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((pl->nspec + NODE_CO - 1) / NODE_CO);
+    k_sdc_node<<<nb, 3 * NODE_CO, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, m, wts, h, theta, fi, fe,
+                                          cout_m, rec);
     return hipGetLastError();
 }
 
