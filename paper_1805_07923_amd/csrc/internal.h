@@ -33,7 +33,8 @@ constexpr int AN_TAB_JH = 256;
 constexpr double AN_POLAR_TAU = 1e-20;
 // Table loads in flight per lane in the table analysis: batches of 8 groups
 // of 4 latitude pairs from 160 pairs up, of 4 below (measured: T255 17.4
-// against 17.7 us with 4, T127 9.0 against 9.3 with 8).  The summed run of
+// against 17.7 us with 4; T127, where two wavefronts share each tile's
+// latitude sum, 8.1 against 8.5 with 8).  The summed run of
 // a tile starts where it holds whole batches (a ragged run would wait for
 // its last loads one at a time): at max(0, ngrp - B ceil((ngrp - c0) / B))
 // for the first group c0 with |P^m_n| >= AN_POLAR_TAU and ngrp groups.

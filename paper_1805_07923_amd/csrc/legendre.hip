@@ -559,18 +559,25 @@ __global__ __launch_bounds__(64) void k_an_polar(const double* __restrict__ pan4
 // product per group.  Each wavefront starts at its tile's first summed group
 // (polar truncation, AN_POLAR_TAU; the run is whole batches of UNR =
 // an_batch(Jh) loads), and the block stages the Fourier data from the
-// smallest first group of its tiles on.
-template <int NF, int UNR>
-__global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, const double* __restrict__ pan4,
-                                                  const long long* __restrict__ off4,
-                                                  const double2* __restrict__ G,
-                                                  double2* __restrict__ cout, int N, int nmax_tab,
-                                                  int nmax_use, int J, int F, int f0, int S,
-                                                  long long G_stride, long long cout_stride) {
+// smallest first group of its tiles on.  SPLIT = 2 (below 160 latitude
+// pairs, where one wavefront per tile leaves about one wavefront per SIMD)
+// gives each tile two wavefronts of 512-thread blocks, each summing half of
+// the tile's batches; the second hands its partial sums to the first through
+// LDS (measured at T127: 8.1-8.4 against 9.3 us; at T255 19.7 against 17.3).
+template <int NF, int UNR, int SPLIT>
+__global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__ tblk, const double* __restrict__ pan4,
+                                                          const long long* __restrict__ off4,
+                                                          const double2* __restrict__ G,
+                                                          double2* __restrict__ cout, int N, int nmax_tab,
+                                                          int nmax_use, int J, int F, int f0, int S,
+                                                          long long G_stride, long long cout_stride) {
+    static_assert(SPLIT == 1 || SPLIT == 2, "one or two wavefronts per tile");
     constexpr int NG = NF / 2;                          // groups of 4 real columns (two fields) on MFMA
     constexpr bool ODD = NF % 2 == 1;                   // last field: its two columns on the VALU
-    extern __shared__ double2 gsh[];                    // [Jh][NF]
+    constexpr int NR = NG + (ODD ? 2 : 0);              // partial sums per lane handed between halves
+    extern __shared__ double2 gsh[];                    // [Jh][NF], then (SPLIT 2) [4][NR][64] doubles
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tw = wv & 3, half = wv >> 2;              // tile of the block, latitude half (SPLIT 2)
     const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
     const int mp = tb.x, tx = tb.y;
     if (mp < 0) return;                                 // padding block (uniform)
@@ -578,41 +585,50 @@ __global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, c
     const int K = kcount(nmax_use, m, p);
     if (tx * 64 >= K) return;                           // whole block idle (uniform)
     const int Jh = J / 2;
-    const int k0 = tx * 64 + 16 * wv;                   // this wavefront's first degree row
+    const int k0 = tx * 64 + 16 * tw;                   // this wavefront's first degree row
+    const bool rows = k0 < K;                           // wave-uniform
     const int kq = lane >> 4;                           // latitude slot of the operands
     const int ngrp = (Jh + 3) / 4;                      // groups of 4 latitude pairs
     // A operands of this wavefront's 16 degrees: 64 consecutive values per group
     const double* P = pan4 + off4[2 * m + p] + (long long)(k0 >> 4) * ngrp * 64 + lane;
     const int cb0 = tb.w;                               // first staged latitude group
-    // this wavefront's first group (wave-uniform: kept in a scalar register
+    // the tile's first summed group (wave-uniform: kept in a scalar register
     // so that the group loop and its addresses stay scalar)
-    const int cw0 = __builtin_amdgcn_readfirstlane((k0 < K) ? (tb.z >> (8 * wv)) & 255 : ngrp);
+    const int cw0 = __builtin_amdgcn_readfirstlane(rows ? (tb.z >> (8 * tw)) & 255 : ngrp);
     const double sg = p ? -1.0 : 1.0;
     const long long rowstride = (long long)(N + 1) * F;
     const double* gs = reinterpret_cast<const double*>(gsh);
     const int cb = lane & 3;                            // B column within a group
-    // groups cw0 + c, c = 0 .. nrun-1 (nrun a multiple of UNR where ngrp allows)
-    const double* Pw = P + (long long)cw0 * 64;
-    const int nrun = ngrp - cw0, jw = 4 * cw0 + kq;
+    // the tile sums groups cw0 .. ngrp-1 (a multiple of UNR where ngrp
+    // allows); with SPLIT 2 the first half of its batches goes to the
+    // wavefront of half 0, the rest to half 1
+    const int nrun = ngrp - cw0;
+    int cbeg = 0, cend = nrun;
+    if constexpr (SPLIT == 2) {
+        const int b0 = (nrun / UNR + 1) / 2;
+        if (half == 0) cend = b0 * UNR; else cbeg = b0 * UNR;
+    }
+    const double* Pw = P + (long long)(cw0 + cbeg) * 64;
+    const int nmine = cend - cbeg, jw = 4 * (cw0 + cbeg) + kq;
     // the first batch of table values is loaded before the Fourier data are
     // staged, so that the two memory round trips overlap; the table is the
     // same for every state
-    const bool pre = k0 < K && nrun >= UNR;             // wave-uniform
+    const bool pre = rows && nmine >= UNR;              // wave-uniform
     double pv0[UNR];
     if (pre) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * 64];
     }
+    double* red = reinterpret_cast<double*>(gsh + (size_t)Jh * NF) + (size_t)tw * NR * 64 + lane;
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();                                // previous state's readers are done
-        for (int i = 4 * cb0 * NF + threadIdx.x; i < Jh * NF; i += 256) {
+        for (int i = 4 * cb0 * NF + threadIdx.x; i < Jh * NF; i += 256 * SPLIT) {
             const int jp = i / NF, f = i - jp * NF;
             const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
             gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
         }
         __syncthreads();
-        if (k0 >= K) continue;                          // no rows for this wavefront (uniform)
         double acc[NG > 0 ? NG : 1];
 #pragma unroll
         for (int g2 = 0; g2 < NG; ++g2) acc[g2] = 0.0;
@@ -630,20 +646,44 @@ __global__ __launch_bounds__(256) void k_leg_an(const int4* __restrict__ tblk, c
                 vi = fma(a, z.y, vi);
             }
         };
-        int c = 0;
-        if (pre) {
+        if (rows) {
+            int c = 0;
+            if (pre) {
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) step(pv0[u], jw + 4 * u);
-            c = UNR;
+                for (int u = 0; u < UNR; ++u) step(pv0[u], jw + 4 * u);
+                c = UNR;
+            }
+            for (; c + UNR <= nmine; c += UNR) {
+                double pv[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * 64];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
+            }
+            for (; c < nmine; ++c) step(Pw[c * 64], jw + 4 * c);
         }
-        for (; c + UNR <= nrun; c += UNR) {
-            double pv[UNR];
+        if constexpr (SPLIT == 2) {
+            // half 1 hands its partial sums to half 0 (same lane, same tile),
+            // which adds them after its own
+            if (half == 1 && rows) {
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * 64];
+                for (int g2 = 0; g2 < NG; ++g2) red[g2 * 64] = acc[g2];
+                if constexpr (ODD) {
+                    red[NG * 64] = vr;
+                    red[(NG + 1) * 64] = vi;
+                }
+            }
+            __syncthreads();
+            if (half == 0 && rows) {
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
+                for (int g2 = 0; g2 < NG; ++g2) acc[g2] += red[g2 * 64];
+                if constexpr (ODD) {
+                    vr += red[NG * 64];
+                    vi += red[(NG + 1) * 64];
+                }
+            }
         }
-        for (; c < nrun; ++c) step(Pw[c * 64], jw + 4 * c);
+        if (half != 0 || !rows) continue;               // uniform
         // MFMA D: lane 4 b + j + 16 i holds degree row 4 b + i, column 4 g + j
         const int k = k0 + 4 * ((lane & 15) >> 2) + (lane >> 4);
         if (k < K) {
@@ -702,12 +742,14 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
         const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
         const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
         const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
+        constexpr int NR = NF / 2 + (NF % 2 ? 2 : 0);
+        const size_t lds2 = lds + (size_t)4 * NR * 64 * sizeof(double);
         if (an_batch(pl->Jh) == 8)
-            k_leg_an<NF, 8><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
-                                                          nmax_use, pl->J, F, f0, S, gst, cst);
+            k_leg_an<NF, 8, 1><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
+                                                             nmax_use, pl->J, F, f0, S, gst, cst);
         else
-            k_leg_an<NF, 4><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
-                                                          nmax_use, pl->J, F, f0, S, gst, cst);
+            k_leg_an<NF, 4, 2><<<pl->tb_nblk, 512, lds2, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
+                                                              nmax_use, pl->J, F, f0, S, gst, cst);
         return;
     }
     const int ngrp = (pl->Jh + 63) / 64;
