@@ -31,6 +31,7 @@ void plan_free(shx_plan* p) {
     (void)hipFree(p->psyn);
     (void)hipFree(p->pan);
     (void)hipFree(p->pan4);
+    (void)hipFree(p->pan4f);
     (void)hipFree(p->off4);
     (void)hipFree(p->an_c0);
     (void)hipFree(p->psyn32);
@@ -881,8 +882,9 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
     ok = ok && hipMemcpy(p->ord_e, orde.data(), orde.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->deg_e, dege.data(), dege.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && launch_plm_table(p, 0) == hipSuccess;
-    if (ok && prec == SHX_FP64 && table_mode == SHX_TABLE_HBM && p->Jh <= AN_TAB_JH) {
+    if (ok && (prec == SHX_FP64 || prec == SHX_FP32) && table_mode == SHX_TABLE_HBM && p->Jh <= AN_TAB_JH) {
         // the analysis table in the layout of the matrix-core table analysis
+        // (FP64, or rounded to FP32 for SHX_FP32 plans)
         const int ngrp = (p->Jh + 3) / 4;
         std::vector<long long> off4(2 * (N + 1));
         long long tot = 0, mx = 0;
@@ -893,7 +895,8 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
             mx = sz > mx ? sz : mx;
         }
         p->an_kt = (kcount(p->nmax, 0, 0) + 15) / 16;   // tiles of the largest block (m = 0, p = 0)
-        ok = dalloc(&p->pan4, tot) == hipSuccess && dalloc(&p->off4, off4.size()) == hipSuccess &&
+        ok = (prec == SHX_FP64 ? dalloc(&p->pan4, tot) : dalloc(&p->pan4f, tot)) == hipSuccess &&
+             dalloc(&p->off4, off4.size()) == hipSuccess &&
              dalloc(&p->an_c0, (size_t)2 * (N + 1) * p->an_kt) == hipSuccess &&
              hipMemcpy(p->off4, off4.data(), off4.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
              launch_an_tab4(p, mx, 0) == hipSuccess && launch_an_polar(p, 0) == hipSuccess &&
@@ -930,7 +933,7 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
         }
         ok = ok && dalloc(&p->tblk, tb4.size()) == hipSuccess &&
              hipMemcpy(p->tblk, tb4.data(), tb4.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
-        if (ok) {                                       // the [m][p][jp][k] layout has no other reader here
+        if (ok && prec == SHX_FP64) {                   // the [m][p][jp][k] layout has no other reader here
             (void)hipFree(p->pan);
             p->pan = nullptr;
         }
@@ -967,7 +970,7 @@ int shx_plan_analysis_terms(const shx_plan* pl, int nmax, long long* terms, long
             const int mp = 2 * m + p, K = kcount(nmax, m, p);
             for (int kt = 0; 16 * kt < K; ++kt) {
                 const int rows = K - 16 * kt < 16 ? K - 16 * kt : 16;
-                int j0 = pl->pan4 ? 4 * c0[(size_t)mp * pl->an_kt + kt] : 0;
+                int j0 = (pl->pan4 || pl->pan4f) ? 4 * c0[(size_t)mp * pl->an_kt + kt] : 0;
                 j0 = j0 < pl->Jh ? j0 : pl->Jh;
                 t += (long long)rows * (pl->Jh - j0);
                 first = j0 < first ? j0 : first;

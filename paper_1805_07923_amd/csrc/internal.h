@@ -209,13 +209,14 @@ struct shx_plan {
     long long* off_an16 = nullptr;    // device [(N+1)*2] offsets into a bf16 plane
     long long* off_syn16 = nullptr;
     long long* off = nullptr;       // device [(N+1)*2] table offsets (elements)
-    // FP64 analysis table laid out for the matrix-core table analysis
-    // (FP64 plans with tables and at most 256 latitude pairs):
+    // Analysis table laid out for the matrix-core table analyses (FP64
+    // plans with tables and at most 256 latitude pairs; pan4f for FP32):
     // pan4[off4[2m+p] + ((kt * ngrp + c) * 4 + kq) * 16 + i] = P^m_{m+p+2k}(mu_jp),
     // k = 16 kt + i, jp = 4 c + kq, ngrp = ceil(Jh / 4); zero past the rows and
     // latitude pairs, so that one operand of 16 degrees x 4 latitude pairs is
     // 64 consecutive values.
     double* pan4 = nullptr;
+    float* pan4f = nullptr;         // the same layout rounded to FP32 (SHX_FP32 plans, Jh <= AN_TAB_JH)
     long long* off4 = nullptr;
     // an_c0[(2m+p) * an_kt + kt]: first latitude group c of tile kt of pan4
     // that holds a value of magnitude >= AN_POLAR_TAU (ngrp if none); an_kt =

@@ -508,10 +508,11 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
     }
 }
 
-// pan4 from pan (layout in shx_plan): one thread per destination element of
-// order-parity block blockIdx.y = 2 m + p.
+// pan4 (FP64) or pan4f (FP32, rounded) from pan (layout in shx_plan): one
+// thread per destination element of order-parity block blockIdx.y = 2 m + p.
+template <class T>
 __global__ void k_an_tab4(const double* __restrict__ pan, const long long* __restrict__ off,
-                          const long long* __restrict__ off4, double* __restrict__ pan4, int nmax, int Jh) {
+                          const long long* __restrict__ off4, T* __restrict__ pan4, int nmax, int Jh) {
     const int mp = blockIdx.y, m = mp >> 1, p = mp & 1;
     const int K = kcount(nmax, m, p);
     const int ngrp = (Jh + 3) / 4;
@@ -521,23 +522,24 @@ __global__ void k_an_tab4(const double* __restrict__ pan, const long long* __res
     const int l = (int)(e - blk * 64);
     const int kt = (int)(blk / ngrp), c = (int)(blk - (long long)kt * ngrp);
     const int k = 16 * kt + (l & 15), jp = 4 * c + (l >> 4);
-    pan4[off4[mp] + e] = (k < K && jp < Jh) ? pan[off[mp] + (long long)jp * K + k] : 0.0;
+    pan4[off4[mp] + e] = (T)((k < K && jp < Jh) ? pan[off[mp] + (long long)jp * K + k] : 0.0);
 }
 
 // First summed latitude group of each 16-degree tile of pan4 (an_c0 in
 // shx_plan): one wavefront per (tile kt, order-parity block blockIdx.y)
 // scans the groups from the pole and stops at the first with a value of
 // magnitude >= tau.
-__global__ __launch_bounds__(64) void k_an_polar(const double* __restrict__ pan4,
+template <class T>
+__global__ __launch_bounds__(64) void k_an_polar(const T* __restrict__ pan4,
                                                  const long long* __restrict__ off4, int* __restrict__ c0,
                                                  int nmax, int Jh, int kt_all, double tau) {
     const int mp = blockIdx.y, kt = blockIdx.x, lane = threadIdx.x;
     const int ngrp = (Jh + 3) / 4;
     int c = ngrp;
     if (16 * kt < kcount(nmax, mp >> 1, mp & 1)) {
-        const double* t = pan4 + off4[mp] + (long long)kt * ngrp * 64 + lane;
+        const T* t = pan4 + off4[mp] + (long long)kt * ngrp * 64 + lane;
         for (c = 0; c < ngrp; ++c)
-            if (__ballot(fabs(t[(long long)c * 64]) >= tau) != 0) break;
+            if (__ballot(fabs((double)t[(long long)c * 64]) >= tau) != 0) break;
     }
     if (lane == 0) c0[mp * kt_all + kt] = c;
 }
@@ -773,13 +775,21 @@ hipError_t launch_plm_table(const shx_plan* pl, hipStream_t st) {
 
 hipError_t launch_an_tab4(const shx_plan* pl, long long max_block, hipStream_t st) {
     dim3 grid((unsigned)((max_block + 255) / 256), 2 * (pl->N + 1));
-    k_an_tab4<<<grid, 256, 0, st>>>(pl->pan, pl->off, pl->off4, pl->pan4, pl->nmax, pl->Jh);
+    if (pl->pan4f)
+        k_an_tab4<float><<<grid, 256, 0, st>>>(pl->pan, pl->off, pl->off4, pl->pan4f, pl->nmax, pl->Jh);
+    else
+        k_an_tab4<double><<<grid, 256, 0, st>>>(pl->pan, pl->off, pl->off4, pl->pan4, pl->nmax, pl->Jh);
     return hipGetLastError();
 }
 
 hipError_t launch_an_polar(const shx_plan* pl, hipStream_t st) {
     dim3 grid(pl->an_kt, 2 * (pl->N + 1));
-    k_an_polar<<<grid, 64, 0, st>>>(pl->pan4, pl->off4, pl->an_c0, pl->nmax, pl->Jh, pl->an_kt, AN_POLAR_TAU);
+    if (pl->pan4f)
+        k_an_polar<float><<<grid, 64, 0, st>>>(pl->pan4f, pl->off4, pl->an_c0, pl->nmax, pl->Jh, pl->an_kt,
+                                               AN_POLAR_TAU);
+    else
+        k_an_polar<double><<<grid, 64, 0, st>>>(pl->pan4, pl->off4, pl->an_c0, pl->nmax, pl->Jh, pl->an_kt,
+                                                AN_POLAR_TAU);
     return hipGetLastError();
 }
 

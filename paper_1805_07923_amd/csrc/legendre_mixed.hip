@@ -251,6 +251,100 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
     }
 }
 
+// FP32 analysis from the tiled FP32 table pan4f (SHX_FP32 plans with tables
+// and at most AN_TAB_JH latitude pairs), the counterpart of the FP64 table
+// analysis: one block per (m, parity, 64 degrees) from the plan's block list,
+// one wavefront per 16 degrees summing the latitude groups of 4 pairs from
+// its tile's first summed group on (polar truncation, AN_POLAR_TAU; runs of
+// whole batches of UNR loads, the first issued before the Fourier staging).
+// Per group v_mfma_f32_16x16x4f32 takes A = 16 degrees x 4 latitude pairs,
+// 64 consecutive FP32 table values (one 4-byte load per lane), and B = the
+// north +/- south Fourier data of the same pairs rounded to FP32 and staged
+// in LDS as [jp][16] (columns 2f, 2f+1 = Re, Im of field f, zero past 2 NF);
+// FP32 accumulation over the latitudes in order, as the untiled kernel.
+template <int NF, int UNR>
+__global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tblk, const float* __restrict__ pan4f,
+                                                    const long long* __restrict__ off4,
+                                                    const double2* __restrict__ G, double2* __restrict__ cout,
+                                                    int N, int nmax_use, int J, int F, int f0, int S,
+                                                    long long G_stride, long long cout_stride) {
+    static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
+    extern __shared__ float gsf[];                      // [Jh][16]
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
+    const int mp = tb.x, tx = tb.y;
+    if (mp < 0) return;                                 // padding block (uniform)
+    const int m = mp >> 1, p = mp & 1;
+    const int K = kcount(nmax_use, m, p);
+    if (tx * 64 >= K) return;                           // whole block idle (uniform)
+    const int Jh = J / 2;
+    const int k0 = tx * 64 + 16 * wv;                   // this wavefront's first degree row
+    const bool rows = k0 < K;                           // wave-uniform
+    const int kq = lane >> 4, col = lane & 15;
+    const int ngrp = (Jh + 3) / 4;
+    const float* P = pan4f + off4[mp] + (long long)(k0 >> 4) * ngrp * 64 + lane;
+    const int cb0 = tb.w;                               // first staged latitude group
+    const int cw0 = __builtin_amdgcn_readfirstlane(rows ? (tb.z >> (8 * wv)) & 255 : ngrp);
+    const float* Pw = P + (long long)cw0 * 64;
+    const int nrun = ngrp - cw0, jw = 4 * cw0 + kq;
+    const bool pre = rows && nrun >= UNR;               // wave-uniform
+    float pv0[UNR];
+    if (pre) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * 64];
+    }
+    const double sg = p ? -1.0 : 1.0;
+    const long long rowstride = (long long)(N + 1) * F;
+    for (int s = 0; s < S; ++s) {
+        const double2* g = G + s * G_stride + (long long)m * F + f0;
+        __syncthreads();                                // previous state's readers are done
+        for (int i = 4 * cb0 * 8 + threadIdx.x; i < Jh * 8; i += 256) {
+            const int jp = i >> 3, f = i & 7;
+            float re = 0.f, im = 0.f;
+            if (f < NF) {
+                const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+                re = (float)(a.x + sg * b.x);
+                im = (float)(a.y + sg * b.y);
+            }
+            gsf[jp * 16 + 2 * f] = re;
+            gsf[jp * 16 + 2 * f + 1] = im;
+        }
+        __syncthreads();
+        if (!rows) continue;                            // uniform
+        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        auto step = [&](float a, int jp) {
+            const float b = jp < Jh ? gsf[jp * 16 + col] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        };
+        int c = 0;
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) step(pv0[u], jw + 4 * u);
+            c = UNR;
+        }
+        for (; c + UNR <= nrun; c += UNR) {
+            float pv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * 64];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
+        }
+        for (; c < nrun; ++c) step(Pw[c * 64], jw + 4 * c);
+        // D[4 (l/16) + r][l % 16]: row k0 + 4 (l/16) + r, column l % 16
+        if (col < 2 * NF) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = k0 + 4 * kq + r;
+                if (k < K) {
+                    double* o = reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F +
+                                                          f0 + col / 2);
+                    o[col & 1] = (double)acc[r];
+                }
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- synthesis
 // D[jp][c] = sum_k P[k][jp] C[k][c], C = coefficients of order m, parity p.
 // grid (ceil(Jh/64), N+1, 2), 4 waves: wave w owns latitudes jb + 16 w .. + 15.
@@ -789,8 +883,37 @@ void syn_mx(const shx_plan* pl, const double2* cin, double2* out, int F, int f0,
         pl->pf, pl->ninv);
 }
 
+template <int NF>
+void an_f32(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
+            hipStream_t st) {
+    const size_t lds = (size_t)pl->Jh * 16 * sizeof(float);
+    const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
+    const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
+    if (an_batch(pl->Jh) == 8)
+        k_leg_an_f32<NF, 8><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4f, pl->off4, G, cout, pl->N, nmax_use, pl->J,
+                                                          F, f0, S, gst, cst);
+    else
+        k_leg_an_f32<NF, 4><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4f, pl->off4, G, cout, pl->N, nmax_use, pl->J,
+                                                          F, f0, S, gst, cst);
+}
+
 template <int MODE>
 void an_mode(const shx_plan* pl, const double2* G, double2* cout, int F, int S, int nmax_use, hipStream_t st) {
+    if (MODE == 1 && pl->pan4f) {                       // tiled FP32 table, chunks of 8 fields
+        for (int f0 = 0; f0 < F; f0 += 8) {
+            switch (F - f0 < 8 ? F - f0 : 8) {
+                case 1: an_f32<1>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 2: an_f32<2>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 3: an_f32<3>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 4: an_f32<4>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 5: an_f32<5>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 6: an_f32<6>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 7: an_f32<7>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                default: an_f32<8>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            }
+        }
+        return;
+    }
     for (int f0 = 0; f0 < F; f0 += 16) {
         const int nf = F - f0 < 16 ? F - f0 : 16;
         if (nf <= 8) an_mx<MODE, 1>(pl, G, cout, F, f0, nf, S, nmax_use, st);
@@ -831,7 +954,11 @@ hipError_t launch_leg_an_mixed(const shx_plan* pl, const double2* G, double2* co
 
 hipError_t launch_leg_syn_mixed_swe(const shx_plan* pl, double a, const double2* state, double2* out, int S,
                                     hipStream_t st) {
-    if (pl->tmode == SHX_TABLE_ONTHEFLY) {
+    // the tendency's 4-field FP32 synthesis regenerates P^m_n from 160
+    // latitude pairs up also where the plan holds tables: there the FP32
+    // table stream costs more than the recurrence (T255: 14.1 against 12.5
+    // us), below it less (T127: 7.5 against 7.8)
+    if (pl->tmode == SHX_TABLE_ONTHEFLY || (pl->prec == SHX_FP32 && pl->Jh >= 160)) {
         const long long cs = 3 * pl->nspec;
         switch (pl->prec) {
             case SHX_FP32: syn_mo<4, 1, 1>(pl, state, out, 4, 0, S, pl->nmax, cs, a, st); break;

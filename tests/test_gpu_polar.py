@@ -1,7 +1,7 @@
-"""Polar truncation of the table analysis (the near-pole omission of the
+"""Polar truncation of the table analyses (the near-pole omission of the
 transform library the method builds on, Sec. 3, Schaeffer 2013).
 
-FP64 plans with tables on at most 512 latitudes leave out of the Legendre
+FP64 and FP32 plans with tables on at most 512 latitudes leave out of the Legendre
 analysis, per order, parity and 16-degree tile, the groups of 4 latitude
 pairs nearest the pole for as long as every |P^m_n| of the group is below
 1e-20, less the groups that make the summed run whole batches of loads
@@ -74,6 +74,9 @@ def test_polar_terms_follow_the_rule(pk, N, J, I):
         assert terms < 0.95 * full                  # the truncation does take effect at T255
     otf = pk.Plan(N, J, I, table_mode=pk.SHX_TABLE_ONTHEFLY)
     assert otf.analysis_terms(N + 1) == (full, (N + 1) * (J // 2))
+    # FP32 plans with tables truncate their FP32 tiles by the same rule
+    t32, r32 = pk.Plan(N, J, I, pk.SHX_FP32).analysis_terms(N + 1)
+    assert lo_t <= t32 <= hi_t and lo_r <= r32 <= hi_r, (t32, r32)
 
 
 @pytest.mark.parametrize("N,J,I", [(127, 192, 384), (255, 384, 768)])
