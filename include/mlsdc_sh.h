@@ -130,8 +130,9 @@ int shx_plan_legendre(const shx_plan* plan, int m, int n, double* out);
  * sh_legendre_analysis, swe_tendency) forms per field for degrees
  * n <= nmax (nmax = ntrunc or ntrunc + 1, else SHX_EINVAL), counted per
  * latitude pair.  Plans that generate P^m_n sum every latitude pair: the
- * count is sum over (m, n) of nlat/2.  FP64 and FP32 plans with tables on at most
- * 512 latitudes apply the polar truncation of the transform library the
+ * count is sum over (m, n) of nlat/2.  FP64 plans with tables on at most
+ * 512 latitudes and FP32 plans with tables on at most 2040 latitudes apply
+ * the polar truncation of the transform library the
  * method builds on (Sec. 3, Schaeffer 2013) to chunks of up to 6 fields
  * (fields go in chunks of 8; chunks of 7 or 8 fields sum every pair), and
  * the count is that of such a chunk.  Per order m, parity of n - m and

@@ -248,7 +248,9 @@ bool convert_tables(shx_plan* p) {
     const int N = p->N, nb = 2 * (N + 1);
     bool ok = true;
     if (p->prec == SHX_FP32) {
-        ok = dalloc(&p->psyn32, p->table_elems) == hipSuccess && dalloc(&p->pan32, p->table_elems) == hipSuccess;
+        // the untiled FP32 analysis table only where the tiled one is not held
+        ok = dalloc(&p->psyn32, p->table_elems) == hipSuccess &&
+             (p->pan4f || dalloc(&p->pan32, p->table_elems) == hipSuccess);
         ok = ok && launch_tables_to_f32(p, 0) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     } else {
         const int NP = p->prec == SHX_SPLIT_BF16_2 ? 2 : 3;
@@ -882,7 +884,8 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
     ok = ok && hipMemcpy(p->ord_e, orde.data(), orde.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(p->deg_e, dege.data(), dege.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && launch_plm_table(p, 0) == hipSuccess;
-    if (ok && (prec == SHX_FP64 || prec == SHX_FP32) && table_mode == SHX_TABLE_HBM && p->Jh <= AN_TAB_JH) {
+    if (ok && table_mode == SHX_TABLE_HBM &&
+        ((prec == SHX_FP64 && p->Jh <= AN_TAB_JH) || (prec == SHX_FP32 && p->Jh <= AN_TAB_JH_F32))) {
         // the analysis table in the layout of the matrix-core table analysis
         // (FP64, or rounded to FP32 for SHX_FP32 plans)
         const int ngrp = (p->Jh + 3) / 4;

@@ -23,6 +23,10 @@ __host__ __device__ inline long long nspec_ext_of(int N) { return (long long)(N 
 // latitude pairs up to which the FP64 analysis of up to 6 fields streams
 // its table (beyond: the matrix-core kernel that generates P^m_n)
 constexpr int AN_TAB_JH = 256;
+// latitude pairs up to which FP32 plans with tables hold the tiled FP32
+// analysis table (the first summed group of a tile is packed in a byte:
+// at most 255 groups of 4 pairs)
+constexpr int AN_TAB_JH_F32 = 1020;
 
 // Polar truncation of the table analysis (the near-pole omission of the
 // transform library of Sec. 3, Schaeffer 2013): a group of 4 latitude pairs
@@ -216,7 +220,7 @@ struct shx_plan {
     // latitude pairs, so that one operand of 16 degrees x 4 latitude pairs is
     // 64 consecutive values.
     double* pan4 = nullptr;
-    float* pan4f = nullptr;         // the same layout rounded to FP32 (SHX_FP32 plans, Jh <= AN_TAB_JH)
+    float* pan4f = nullptr;         // the same layout rounded to FP32 (SHX_FP32 plans, Jh <= AN_TAB_JH_F32)
     long long* off4 = nullptr;
     // an_c0[(2m+p) * an_kt + kt]: first latitude group c of tile kt of pan4
     // that holds a value of magnitude >= AN_POLAR_TAU (ngrp if none); an_kt =

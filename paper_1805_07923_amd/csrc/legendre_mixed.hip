@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
 }
 
 // FP32 analysis from the tiled FP32 table pan4f (SHX_FP32 plans with tables
-// and at most AN_TAB_JH latitude pairs), the counterpart of the FP64 table
+// and at most AN_TAB_JH_F32 latitude pairs), the counterpart of the FP64 table
 // analysis: one block per (m, parity, 64 degrees) from the plan's block list,
 // one wavefront per 16 degrees summing the latitude groups of 4 pairs from
 // its tile's first summed group on (polar truncation, AN_POLAR_TAU; runs of
@@ -1000,7 +1000,7 @@ hipError_t launch_leg_syn_mixed(const shx_plan* pl, const double2* cin, double2*
 hipError_t launch_tables_to_f32(const shx_plan* pl, hipStream_t st) {
     const unsigned nb = (unsigned)((pl->table_elems + 255) / 256);
     k_tab_to_f32<<<nb, 256, 0, st>>>(pl->psyn, pl->psyn32, pl->table_elems);
-    k_tab_to_f32<<<nb, 256, 0, st>>>(pl->pan, pl->pan32, pl->table_elems);
+    if (pl->pan32) k_tab_to_f32<<<nb, 256, 0, st>>>(pl->pan, pl->pan32, pl->table_elems);
     return hipGetLastError();
 }
 
