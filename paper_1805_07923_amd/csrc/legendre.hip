@@ -544,8 +544,9 @@ __global__ __launch_bounds__(64) void k_an_polar(const T* __restrict__ pan4,
     if (lane == 0) c0[mp * kt_all + kt] = c;
 }
 
-// Analysis from the table on the matrix cores (up to AN_TAB_JH latitude
-// pairs and 6 fields; beyond, k_leg_an_m generates P^m_n instead):
+// Analysis from the table on the matrix cores (plans with up to AN_TAB_JH
+// latitude pairs, 1-16 fields per launch; beyond, k_leg_an_m generates P^m_n
+// instead):
 // cout[s][ext(m, m+2k+p)][f0+f] = sum_jp P[m][p][jp][k] (G[s][jp][m] + (-1)^p G[s][J-1-jp][m]).
 // One block per (m, p, 64-degree tile holding rows) from the plan's list
 // (the blocks of an order on one XCD), one wavefront per 16 degrees summing
@@ -738,9 +739,9 @@ void syn_chunk(const shx_plan* pl, const double2* cin, double2* out, int F, int 
 }
 
 template <int NF>
-void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
-              hipStream_t st) {
-    if (NF <= 6 && pl->pan4) {                         // FP64 plans with tables, Jh <= AN_TAB_JH
+void an_tab(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
+            hipStream_t st) {
+    {                                                   // FP64 plans with tables, Jh <= AN_TAB_JH
         const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
         const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
         const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
@@ -752,8 +753,12 @@ void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0
         else
             k_leg_an<NF, 4, 2><<<pl->tb_nblk, 512, lds2, st>>>(tb, pl->pan4, pl->off4, G, cout, pl->N, pl->nmax,
                                                               nmax_use, pl->J, F, f0, S, gst, cst);
-        return;
     }
+}
+
+template <int NF>
+void an_chunk(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
+              hipStream_t st) {
     const int ngrp = (pl->Jh + 63) / 64;
     const int nw = ngrp < 4 ? ngrp : 4;
     const size_t lds = (size_t)nw * 2 * 64 * 17 * sizeof(double);
@@ -835,6 +840,29 @@ hipError_t launch_leg_syn_swe_adj(const shx_plan* pl, double a, const double2* l
 hipError_t launch_leg_an(const shx_plan* pl, const double2* G, double2* cout, int F, int S,
                          int nmax_use, hipStream_t st) {
     if (pl->prec != SHX_FP64) return launch_leg_an_mixed(pl, G, cout, F, S, nmax_use, st);
+    if (pl->pan4) {                                     // the table streamed once per 16 fields
+        for (int f0 = 0; f0 < F; f0 += 16) {
+            switch (F - f0 < 16 ? F - f0 : 16) {
+                case 1: an_tab<1>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 2: an_tab<2>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 3: an_tab<3>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 4: an_tab<4>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 5: an_tab<5>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 6: an_tab<6>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 7: an_tab<7>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 8: an_tab<8>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 9: an_tab<9>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 10: an_tab<10>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 11: an_tab<11>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 12: an_tab<12>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 13: an_tab<13>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 14: an_tab<14>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 15: an_tab<15>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                default: an_tab<16>(pl, G, cout, F, f0, S, nmax_use, st); break;
+            }
+        }
+        return hipGetLastError();
+    }
     for (int f0 = 0; f0 < F; f0 += 8) {
         const int nf = (F - f0 < 8) ? F - f0 : 8;
         switch (nf) {
