@@ -260,16 +260,20 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
 // Per group v_mfma_f32_16x16x4f32 takes A = 16 degrees x 4 latitude pairs,
 // 64 consecutive FP32 table values (one 4-byte load per lane), and B = the
 // north +/- south Fourier data of the same pairs rounded to FP32 and staged
-// in LDS as [jp][16] (columns 2f, 2f+1 = Re, Im of field f, zero past 2 NF);
-// FP32 accumulation over the latitudes in order, as the untiled kernel.
+// in LDS as [jp][16 NCT] (columns 2f, 2f+1 = Re, Im of field f, zero past
+// 2 NF; NCT = 1 or 2 products of 16 columns per group for up to 8 or 16
+// fields); FP32 accumulation over the latitudes in order, as the untiled
+// kernel.
 template <int NF, int UNR>
 __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tblk, const float* __restrict__ pan4f,
                                                     const long long* __restrict__ off4,
                                                     const double2* __restrict__ G, double2* __restrict__ cout,
                                                     int N, int nmax_use, int J, int F, int f0, int S,
                                                     long long G_stride, long long cout_stride) {
-    static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
-    extern __shared__ float gsf[];                      // [Jh][16]
+    static_assert(NF >= 1 && NF <= 16, "two 16-column products at most");
+    constexpr int NCT = (NF + 7) / 8;                   // 16-column products per latitude group
+    constexpr int CW = 16 * NCT;                        // staged columns
+    extern __shared__ float gsf[];                      // [Jh][CW]
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
     const int mp = tb.x, tx = tb.y;
@@ -298,23 +302,28 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();                                // previous state's readers are done
-        for (int i = 4 * cb0 * 8 + threadIdx.x; i < Jh * 8; i += 256) {
-            const int jp = i >> 3, f = i & 7;
+        for (int i = 4 * cb0 * (CW / 2) + threadIdx.x; i < Jh * (CW / 2); i += 256) {
+            const int jp = i / (CW / 2), f = i - jp * (CW / 2);
             float re = 0.f, im = 0.f;
             if (f < NF) {
                 const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
                 re = (float)(a.x + sg * b.x);
                 im = (float)(a.y + sg * b.y);
             }
-            gsf[jp * 16 + 2 * f] = re;
-            gsf[jp * 16 + 2 * f + 1] = im;
+            gsf[jp * CW + 2 * f] = re;
+            gsf[jp * CW + 2 * f + 1] = im;
         }
         __syncthreads();
         if (!rows) continue;                            // uniform
-        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        floatx4 acc[NCT];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         auto step = [&](float a, int jp) {
-            const float b = jp < Jh ? gsf[jp * 16 + col] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const float b = jp < Jh ? gsf[jp * CW + 16 * t + col] : 0.f;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+            }
         };
         int c = 0;
         if (pre) {
@@ -330,15 +339,18 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
             for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
         }
         for (; c < nrun; ++c) step(Pw[c * 64], jw + 4 * c);
-        // D[4 (l/16) + r][l % 16]: row k0 + 4 (l/16) + r, column l % 16
-        if (col < 2 * NF) {
+        // D[4 (l/16) + r][l % 16]: row k0 + 4 (l/16) + r, column 16 t + l % 16
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = 16 * t + col;
+            if (c >= 2 * NF) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int k = k0 + 4 * kq + r;
                 if (k < K) {
                     double* o = reinterpret_cast<double*>(cout + s * cout_stride + ext_idx(N, m, m + p + 2 * k) * F +
-                                                          f0 + col / 2);
-                    o[col & 1] = (double)acc[r];
+                                                          f0 + c / 2);
+                    o[c & 1] = (double)acc[t][r];
                 }
             }
         }
@@ -886,7 +898,7 @@ void syn_mx(const shx_plan* pl, const double2* cin, double2* out, int F, int f0,
 template <int NF>
 void an_f32(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
             hipStream_t st) {
-    const size_t lds = (size_t)pl->Jh * 16 * sizeof(float);
+    const size_t lds = (size_t)pl->Jh * 16 * ((NF + 7) / 8) * sizeof(float);
     const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
     const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
     if (an_batch(pl->Jh) == 8)
@@ -899,9 +911,11 @@ void an_f32(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, 
 
 template <int MODE>
 void an_mode(const shx_plan* pl, const double2* G, double2* cout, int F, int S, int nmax_use, hipStream_t st) {
-    if (MODE == 1 && pl->pan4f) {                       // tiled FP32 table, chunks of 8 fields
-        for (int f0 = 0; f0 < F; f0 += 8) {
-            switch (F - f0 < 8 ? F - f0 : 8) {
+    if (MODE == 1 && pl->pan4f) {                       // tiled FP32 table, chunks of 16 fields
+        // (of 8 where 16 fields would stage more than 64 KB of LDS)
+        const int chunk = (size_t)pl->Jh * 32 * sizeof(float) <= 65536 ? 16 : 8;
+        for (int f0 = 0; f0 < F; f0 += chunk) {
+            switch (F - f0 < chunk ? F - f0 : chunk) {
                 case 1: an_f32<1>(pl, G, cout, F, f0, S, nmax_use, st); break;
                 case 2: an_f32<2>(pl, G, cout, F, f0, S, nmax_use, st); break;
                 case 3: an_f32<3>(pl, G, cout, F, f0, S, nmax_use, st); break;
@@ -909,7 +923,15 @@ void an_mode(const shx_plan* pl, const double2* G, double2* cout, int F, int S, 
                 case 5: an_f32<5>(pl, G, cout, F, f0, S, nmax_use, st); break;
                 case 6: an_f32<6>(pl, G, cout, F, f0, S, nmax_use, st); break;
                 case 7: an_f32<7>(pl, G, cout, F, f0, S, nmax_use, st); break;
-                default: an_f32<8>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 8: an_f32<8>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 9: an_f32<9>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 10: an_f32<10>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 11: an_f32<11>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 12: an_f32<12>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 13: an_f32<13>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 14: an_f32<14>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                case 15: an_f32<15>(pl, G, cout, F, f0, S, nmax_use, st); break;
+                default: an_f32<16>(pl, G, cout, F, f0, S, nmax_use, st); break;
             }
         }
         return;
