@@ -578,7 +578,7 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
     constexpr int NG = NF / 2;                          // groups of 4 real columns (two fields) on MFMA
     constexpr bool ODD = NF % 2 == 1;                   // last field: its two columns on the VALU
     constexpr int NR = NG + (ODD ? 2 : 0);              // partial sums per lane handed between halves
-    extern __shared__ double2 gsh[];                    // [Jh][NF], then (SPLIT 2) [4][NR][64] doubles
+    extern __shared__ double2 gsh[];                    // [4 ngrp][NF], then (SPLIT 2) [4][NR][64] doubles
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tw = wv & 3, half = wv >> 2;              // tile of the block, latitude half (SPLIT 2)
     const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
@@ -622,14 +622,20 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
 #pragma unroll
         for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * 64];
     }
-    double* red = reinterpret_cast<double*>(gsh + (size_t)Jh * NF) + (size_t)tw * NR * 64 + lane;
+    double* red = reinterpret_cast<double*>(gsh + (size_t)4 * ngrp * NF) + (size_t)tw * NR * 64 + lane;
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();                                // previous state's readers are done
-        for (int i = 4 * cb0 * NF + threadIdx.x; i < Jh * NF; i += 256 * SPLIT) {
+        // rows of whole latitude groups: zeros past the last pair, so that
+        // the products read their operands without a bounds test
+        for (int i = 4 * cb0 * NF + threadIdx.x; i < 4 * ngrp * NF; i += 256 * SPLIT) {
             const int jp = i / NF, f = i - jp * NF;
-            const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
-            gsh[i] = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+            double2 v = make_double2(0.0, 0.0);
+            if (jp < Jh) {
+                const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
+                v = make_double2(a.x + sg * b.x, a.y + sg * b.y);
+            }
+            gsh[i] = v;
         }
         __syncthreads();
         double acc[NG > 0 ? NG : 1];
@@ -637,14 +643,13 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
         for (int g2 = 0; g2 < NG; ++g2) acc[g2] = 0.0;
         double vr = 0.0, vi = 0.0;                      // odd field: this lane's latitude slot
         auto step = [&](double a, int jp) {
-            const bool in = jp < Jh;
 #pragma unroll
             for (int g2 = 0; g2 < NG; ++g2) {
-                const double b = in ? gs[jp * 2 * NF + 4 * g2 + cb] : 0.0;
+                const double b = gs[jp * 2 * NF + 4 * g2 + cb];
                 acc[g2] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[g2], 0, 0, 0);
             }
             if constexpr (ODD) {
-                const double2 z = in ? gsh[jp * NF + NF - 1] : make_double2(0.0, 0.0);
+                const double2 z = gsh[jp * NF + NF - 1];
                 vr = fma(a, z.x, vr);
                 vi = fma(a, z.y, vi);
             }
@@ -742,7 +747,7 @@ template <int NF>
 void an_tab(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
             hipStream_t st) {
     {                                                   // FP64 plans with tables, Jh <= AN_TAB_JH
-        const size_t lds = (size_t)pl->Jh * NF * sizeof(double2);
+        const size_t lds = (size_t)4 * ((pl->Jh + 3) / 4) * NF * sizeof(double2);
         const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
         const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
         constexpr int NR = NF / 2 + (NF % 2 ? 2 : 0);

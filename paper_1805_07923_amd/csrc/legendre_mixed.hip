@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
     static_assert(NF >= 1 && NF <= 16, "two 16-column products at most");
     constexpr int NCT = (NF + 7) / 8;                   // 16-column products per latitude group
     constexpr int CW = 16 * NCT;                        // staged columns
-    extern __shared__ float gsf[];                      // [Jh][CW]
+    extern __shared__ float gsf[];                      // [4 ngrp][CW]
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int4 tb = tblk[blockIdx.x];                   // (2m+p, tile, first groups, their minimum)
     const int mp = tb.x, tx = tb.y;
@@ -302,10 +302,12 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
     for (int s = 0; s < S; ++s) {
         const double2* g = G + s * G_stride + (long long)m * F + f0;
         __syncthreads();                                // previous state's readers are done
-        for (int i = 4 * cb0 * (CW / 2) + threadIdx.x; i < Jh * (CW / 2); i += 256) {
+        // rows of whole latitude groups (zeros past the last pair), so that
+        // the products read their operands without a bounds test
+        for (int i = 4 * cb0 * (CW / 2) + threadIdx.x; i < 4 * ngrp * (CW / 2); i += 256) {
             const int jp = i / (CW / 2), f = i - jp * (CW / 2);
             float re = 0.f, im = 0.f;
-            if (f < NF) {
+            if (f < NF && jp < Jh) {
                 const double2 a = g[jp * rowstride + f], b = g[(J - 1 - jp) * rowstride + f];
                 re = (float)(a.x + sg * b.x);
                 im = (float)(a.y + sg * b.y);
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
         auto step = [&](float a, int jp) {
 #pragma unroll
             for (int t = 0; t < NCT; ++t) {
-                const float b = jp < Jh ? gsf[jp * CW + 16 * t + col] : 0.f;
+                const float b = gsf[jp * CW + 16 * t + col];
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
             }
         };
@@ -898,7 +900,7 @@ void syn_mx(const shx_plan* pl, const double2* cin, double2* out, int F, int f0,
 template <int NF>
 void an_f32(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, int S, int nmax_use,
             hipStream_t st) {
-    const size_t lds = (size_t)pl->Jh * 16 * ((NF + 7) / 8) * sizeof(float);
+    const size_t lds = (size_t)4 * ((pl->Jh + 3) / 4) * 16 * ((NF + 7) / 8) * sizeof(float);
     const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
     const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
     if (an_batch(pl->Jh) == 8)
@@ -913,7 +915,7 @@ template <int MODE>
 void an_mode(const shx_plan* pl, const double2* G, double2* cout, int F, int S, int nmax_use, hipStream_t st) {
     if (MODE == 1 && pl->pan4f) {                       // tiled FP32 table, chunks of 16 fields
         // (of 8 where 16 fields would stage more than 64 KB of LDS)
-        const int chunk = (size_t)pl->Jh * 32 * sizeof(float) <= 65536 ? 16 : 8;
+        const int chunk = (size_t)4 * ((pl->Jh + 3) / 4) * 32 * sizeof(float) <= 65536 ? 16 : 8;
         for (int f0 = 0; f0 < F; f0 += chunk) {
             switch (F - f0 < chunk ? F - f0 : chunk) {
                 case 1: an_f32<1>(pl, G, cout, F, f0, S, nmax_use, st); break;
