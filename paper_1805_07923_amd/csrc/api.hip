@@ -155,6 +155,25 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
             wt.qd[j] = j < n1 ? rows.qd[m][j] : 0.0;
         }
         double2* r = rec ? rec + (size_t)m * ns3 : nullptr;
+        const size_t o = (size_t)(m + 1) * ns3;
+        if (m > 0 && pl->prec == SHX_FP64) {
+            // FP64: node m's update (F of node m from t.cout, Theta^{m+1})
+            // formed in the staging of the synthesis of Theta^{m+1}
+            NodeFuse nf;
+            nf.m = m;
+            nf.h = rows.h[m];
+            nf.wt = wt;
+            nf.p = lv->p;
+            nf.cout = t.cout;
+            nf.theta = th;
+            nf.fi = fi_new;
+            nf.fe = fe_new;
+            nf.rec = r;
+            HIPCHK(timed(SHX_KC_LEGENDRE_SYN, st, [&] { return launch_leg_syn_swe_node(pl, nf, t.FI, st); }));
+            HIPCHK(timed(SHX_KC_GRID, st, [&] { return launch_swe_grid(pl, t.FI, t.G, 1, lv->p.omega, st); }));
+            HIPCHK(timed(SHX_KC_LEGENDRE_AN, st, [&] { return launch_leg_an(pl, t.G, t.cout, 5, 1, pl->nmax, st); }));
+            continue;
+        }
         // the first update forms the old-F part of every node's right-hand
         // side (held in fe_new at nodes 2..M until those are written); the
         // F of node m (m >= 1) is formed inside node m's update from t.cout
@@ -162,7 +181,6 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
             return m == 0 ? launch_sdc_node_first(pl, lv->p, M, rows, th, fi_old, fe_old, tau, fe_new, r, st)
                           : launch_sdc_node(pl, lv->p, m, M, wt, rows.h[m], th, fi_new, fe_new, t.cout, r, st);
         }));
-        const size_t o = (size_t)(m + 1) * ns3;
         int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st, false);
         if (rc) return rc;
     }

@@ -71,19 +71,18 @@ __host__ __device__ inline double eps_nm(int n, int m) {
 //   U_n = [(n-1) eps_n psi_{n-1} - (n+2) eps_{n+1} psi_{n+1} + i m chi_n] / a,
 //   V_n = [i m psi_n - (n-1) eps_n chi_{n-1} + (n+2) eps_{n+1} chi_{n+1}] / a.
 // pfm = pf + ext(m, m); a2 = a^2, ia = 1/a.
-__device__ inline void swe_prep_row(const double2* __restrict__ state, long long nspec, int N, double a2,
-                                    double ia, const double2* __restrict__ pfm, const double* __restrict__ ninv,
-                                    int m, int n, double2 o[4]) {
-    const double2* phi = state;
-    const double2* zeta = state + nspec;
-    const double2* delta = zeta + nspec;
-    // every load is issued before the first is used: indices outside m..N
+// ld(f, nn): state field f (0 Phi', 1 zeta, 2 delta) at degree nn of order m,
+// called with m <= nn <= N only.
+template <class Ld>
+__device__ inline void swe_prep_row_t(Ld ld, int N, double a2, double ia, const double2* __restrict__ pfm,
+                                      const double* __restrict__ ninv, int m, int n, double2 o[4]) {
+    // every load is issued before the first is used: degrees outside m..N
     // are clamped to a stored entry of the order and their factor is zero
-    auto at = [&](int nn) { return spec_idx(N, m, nn < m ? m : (nn > N ? N : nn)); };
-    const long long id = at(n - 1), i0 = at(n), iu = at(n + 1);
-    const double2 zd = zeta[id], z0 = zeta[i0], zu = zeta[iu];
-    const double2 dd = delta[id], d0 = delta[i0], du = delta[iu];
-    const double2 p0 = phi[i0];
+    auto cl = [&](int nn) { return nn < m ? m : (nn > N ? N : nn); };
+    const int id = cl(n - 1), i0 = cl(n), iu = cl(n + 1);
+    const double2 zd = ld(1, id), z0 = ld(1, i0), zu = ld(1, iu);
+    const double2 dd = ld(2, id), d0 = ld(2, i0), du = ld(2, iu);
+    const double2 p0 = ld(0, i0);
     const double2 cf = pfm[n - m];
     const double nd = ninv[n > 0 ? n - 1 : 0], n0 = ninv[n], nu = ninv[n + 1];
     // -1/L_nn (zero outside the stored degrees and at nn = 0)
@@ -101,6 +100,13 @@ __device__ inline void swe_prep_row(const double2* __restrict__ state, long long
     o[1] = in ? p0 : make_double2(0.0, 0.0);
     o[2] = make_double2(ia * U.x, ia * U.y);
     o[3] = make_double2(ia * V.x, ia * V.y);
+}
+
+__device__ inline void swe_prep_row(const double2* __restrict__ state, long long nspec, int N, double a2,
+                                    double ia, const double2* __restrict__ pfm, const double* __restrict__ ninv,
+                                    int m, int n, double2 o[4]) {
+    swe_prep_row_t([&](int f, int nn) { return state[f * nspec + spec_idx(N, m, nn)]; }, N, a2, ia, pfm, ninv, m,
+                   n, o);
 }
 
 // Transpose of the F_E combine (F_E = [-div(C, D), -div(A, B), curl(A, B)
@@ -279,6 +285,20 @@ struct NodeWeights {
 struct Mat9x9 {
     double a[81];
 };
+// A node update m >= 1 of an FP64 sweep formed in the staging of the next
+// tendency's synthesis (that of Theta^{m+1}): the data of the separate
+// update (k_sdc_node).
+struct NodeFuse {
+    int m = 0;                        // node whose new F is formed; Theta^{m+1} is computed
+    double h = 0.0;                   // dt * QD[m+1][m+1]
+    NodeWeights wt{};                 // row m+1 of dt Q, dt QE, dt QD
+    swe_params p{};
+    const double2* cout = nullptr;    // analyses of node m's tendency, [ext][5]
+    double2* theta = nullptr;         // the sweep's nodes, [M+1][3][nspec]
+    double2* fi = nullptr;            // new F_I at the nodes
+    double2* fe = nullptr;            // new F_E at the nodes; node m+1 holds the old-F part S_m
+    double2* rec = nullptr;           // tape of Theta^{m+1}, or null
+};
 // The weights of every node update of a sweep (row m = node m+1, M <= 8).
 struct NodeRows {
     double q[8][9];   // dt * Q[m+1][j]
@@ -339,6 +359,7 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
 // cout_m != nullptr (m >= 1): the new F at node m is formed from these
 // analyses of node m's tendency inside the node update (and stored).
 // rec != nullptr: Theta^{m+1} is also stored there (the adjoint's tape).
+hipError_t launch_leg_syn_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st);
 hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
                                  double2* theta, const double2* fi_old, const double2* fe_old, const double2* tau,
                                  double2* sq, double2* rec, hipStream_t st);

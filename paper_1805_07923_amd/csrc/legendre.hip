@@ -19,6 +19,7 @@
 // Fourier coefficients of one latitude) is the same for every lane and is
 // staged in LDS.
 #include "internal.h"
+#include "swe_node.h"
 
 namespace {
 
@@ -220,7 +221,8 @@ __global__ void k_plm_one(const double* __restrict__ mu, const double* __restric
 // staged rows are the tendency's grid fields (swe_prep_row; NF = F = 4);
 // STAGE = 2: cin holds F_E cotangents [S][3][nspec] and the staged rows are
 // the cotangents of the five weighted analyses (swe_combine_adj_row;
-// NF = F = 5).  The coefficient rows and the recurrence coefficients of the
+// NF = F = 5); STAGE = 3: as STAGE 1 for the state that a sweep's node
+// update produces, formed by each block for its order in LDS first (nfu).  The coefficient rows and the recurrence coefficients of the
 // round's 4 L degrees are staged in LDS, segment by segment, each segment
 // padded by 32 bytes so that the four segments' reads of one step fall on
 // different banks; rows past nmax_use are staged as zeros and recurrence
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
                                                    long long nspec, double a, int Lmax,
                                                    const double2* __restrict__ pf,
                                                    const double* __restrict__ ninv,
-                                                   const double* __restrict__ nn1) {
+                                                   const double* __restrict__ nn1, NodeFuse nfu) {
     static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
     constexpr int U = 8;                                // degrees per batch of LDS reads
     constexpr int NG = (2 * NF + 3) / 4;                // groups of 4 real columns
@@ -272,6 +274,52 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
     const double* csm = cs + ext_idx(N, m, m);
     const double2* pfm = pf + ext_idx(N, m, m);
     const double ia = 1.0 / a, a2 = a * a, ia2 = ia * ia;
+    // STAGE 3: the sweep's node update of order m (S = 1), Theta^{k+1} =
+    // solve(S_k + sum_{j<=k} [dtQE F_E^j + dtQD F_I^j], h) with F at node k =
+    // nfu.m formed from its analyses, into LDS thn [3][N+1] (degrees m..N);
+    // the block of the first latitude group also stores Theta^{k+1} and the
+    // F of node k (the sweep's outputs) and the tape
+    double2* thn = csh + 4 * (Lmax * (NF + 1) + 4);
+    if constexpr (STAGE == 3) {
+        static_assert(STAGE != 3 || NF == 4, "the tendency synthesis has four fields");
+        const long long ns3 = 3 * nspec;
+        const int k = nfu.m;
+        for (int t = threadIdx.x; t <= N - m; t += 64 * syn_wb(SYN_LS)) {
+            const int n = m + t;
+            const long long i = spec_idx(N, m, n);
+            double2 fem[3], fim[3], acc[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] = nfu.fe[(k + 1) * ns3 + c * nspec + i];   // S_k
+            swe_node::combine_one(nfu.cout, nfu.theta + k * ns3, N, nspec, nfu.p, i, m, n, fem, fim);
+            for (int j = 1; j < k; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    acc[c] = swe_node::caxpy(nfu.wt.qe[j], nfu.fe[j * ns3 + c * nspec + i], acc[c]);
+                    acc[c] = swe_node::caxpy(nfu.wt.qd[j], nfu.fi[j * ns3 + c * nspec + i], acc[c]);
+                }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[c] = swe_node::caxpy(nfu.wt.qe[k], fem[c], acc[c]);
+                acc[c] = swe_node::caxpy(nfu.wt.qd[k], fim[c], acc[c]);
+            }
+            const double L = n * (n + 1.0) / (nfu.p.a * nfu.p.a);
+            double2 x[3];
+            swe_node::solve_one(L, nfu.h, nfu.p, acc[0], acc[1], acc[2], x[0], x[1], x[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) thn[c * (N + 1) + t] = x[c];
+            if (tile.x == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const long long o = c * nspec + i;
+                    nfu.theta[(k + 1) * ns3 + o] = x[c];
+                    nfu.fe[k * ns3 + o] = fem[c];
+                    nfu.fi[k * ns3 + o] = fim[c];
+                    if (nfu.rec) nfu.rec[o] = x[c];
+                }
+            }
+        }
+        // the staging below reads thn after its first barrier
+    }
     for (int s = 0; s < S; ++s) {
         double accE[SYN_LS][NG], accO[SYN_LS][NG];
 #pragma unroll
@@ -291,7 +339,14 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
                 const int qs = kl / L, ts = kl - qs * L, kk = kr0 + kl;
                 double2* row = csh + qs * SC + ts * NF;
                 if (kk < Ku) {
-                    if constexpr (STAGE == 1) {
+                    if constexpr (STAGE == 3) {
+                        double2 o[4];
+                        swe_prep_row_t([&](int f, int nn) { return thn[f * (N + 1) + (nn - m)]; }, N, a2, ia, pfm,
+                                       ninv, m, m + kk, o);
+                        const double c = csm[kk];
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) row[f] = make_double2(c * o[f].x, c * o[f].y);
+                    } else if constexpr (STAGE == 1) {
                         static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
                         double2 o[4];
                         swe_prep_row(cin + s * cin_stride, nspec, N, a2, ia, pfm, ninv, m, m + kk, o);
@@ -715,10 +770,11 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
 
 template <int NF, int STAGE = 0>
 void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S, int nmax_use,
-           long long cin_stride, double a, hipStream_t st) {
+           long long cin_stride, double a, hipStream_t st, const NodeFuse& nfu = NodeFuse{}) {
     int Lmax = 0;                                       // longest segment over the orders
     for (int m = 0; m <= pl->N; ++m) Lmax = seg_len(pl->nmax - m + 1) > Lmax ? seg_len(pl->nmax - m + 1) : Lmax;
-    const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2);
+    const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2) +
+                       (STAGE == 3 ? (size_t)3 * (pl->N + 1) * sizeof(double2) : 0);
     const long long os = (long long)pl->J * (pl->N + 1) * F;
     // two latitude sets per wavefront from 384 latitude pairs up (fewer
     // wavefronts; measured faster at T1023, slower at T255 and below)
@@ -727,13 +783,13 @@ void syn_r(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, 
         k_leg_syn_m<NF, STAGE, 2><<<gx * (pl->N + 1), 64 * syn_wb(2), lds, st>>>(
             pl->ck, pl->ckoff, pl->rq, pl->cs, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S,
             cin_stride, os,
-            gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1);
+            gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1, nfu);
     } else {
         const int gx = (pl->Jh + syn_lat(1) - 1) / syn_lat(1);
         k_leg_syn_m<NF, STAGE, 1><<<gx * (pl->N + 1), 64 * syn_wb(1), lds, st>>>(
             pl->ck, pl->ckoff, pl->rq, pl->cs, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S,
             cin_stride, os,
-            gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1);
+            gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, pl->nn1, nfu);
     }
 }
 
@@ -832,6 +888,12 @@ hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state
                               hipStream_t st) {
     if (pl->prec != SHX_FP64) return launch_leg_syn_mixed_swe(pl, a, state, out, S, st);
     syn_r<4, 1>(pl, state, out, 4, 0, S, pl->nmax, 3 * pl->nspec, a, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_syn_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st) {
+    if (pl->prec != SHX_FP64 || nf.m < 1 || !nf.cout || !nf.theta || !nf.fi || !nf.fe) return hipErrorInvalidValue;
+    syn_r<4, 3>(pl, nullptr, out, 4, 0, 1, pl->nmax, 0, nf.p.a, st, nf);
     return hipGetLastError();
 }
 
