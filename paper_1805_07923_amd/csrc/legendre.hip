@@ -280,6 +280,11 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
     // the block of the first latitude group also stores Theta^{k+1} and the
     // F of node k (the sweep's outputs) and the tape
     double2* thn = csh + 4 * (Lmax * (NF + 1) + 4);
+    double2 c0first[SYN_LS];                            // round 0's restart pairs, loaded before the update
+    if constexpr (STAGE == 3) {
+#pragma unroll
+        for (int ls = 0; ls < SYN_LS; ++ls) c0first[ls] = ckm[ls][(long long)q * Jh];
+    }
     if constexpr (STAGE == 3) {
         static_assert(STAGE != 3 || NF == 4, "the tendency synthesis has four fields");
         const long long ns3 = 3 * nspec;
@@ -332,7 +337,8 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
             const int g = 4 * r + q;
             double2 c0[SYN_LS];                         // in flight during the staging
 #pragma unroll
-            for (int ls = 0; ls < SYN_LS; ++ls) c0[ls] = ckm[ls][(long long)g * Jh];
+            for (int ls = 0; ls < SYN_LS; ++ls)
+                c0[ls] = (STAGE == 3 && r == 0) ? c0first[ls] : ckm[ls][(long long)g * Jh];
             const double qinv = (g * L + 1 < Kt) ? 1.0 / csm[g * L + 1] : 0.0;   // Q_{gL+1} = P_{gL+1} / C
             __syncthreads();                            // previous readers of the rows are done
             for (int kl = threadIdx.x; kl < 4 * L; kl += 64 * syn_wb(SYN_LS)) {
