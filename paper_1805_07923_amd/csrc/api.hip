@@ -132,9 +132,12 @@ int tendency_impl(const shx_plan* pl, const swe_params& p, int nst, const double
 // from (fi_old, fe_old) and writing the new F at nodes 1..M to (fi_new,
 // fe_new); Theta is updated in place (node 0 read only).  Node 0 of the new
 // buffers is not touched.
+// form_last = false leaves the F of node M unformed (its analyses stay in
+// t.cout) for a following sweep on the same level, whose first update forms
+// it (old_last_from_cout = true); only that update reads it.
 int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_old, const double2* fe_old,
                double2* fi_new, double2* fe_new, const double2* tau, const TendWS& t, hipStream_t st,
-               double2* rec = nullptr) {
+               double2* rec = nullptr, bool form_last = true, bool old_last_from_cout = false) {
     const shx_plan* pl = lv->plan;
     const int M = lv->nnodes - 1, n1 = lv->nnodes;
     const size_t ns3 = 3 * (size_t)pl->nspec;
@@ -181,14 +184,15 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
         // side (held in fe_new at nodes 2..M until those are written); the
         // F of node m (m >= 1) is formed inside node m's update from t.cout
         HIPCHK(timed(SHX_KC_SDC_NODE, st, [&] {
-            return m == 0 ? launch_sdc_node_first(pl, lv->p, M, rows, th, fi_old, fe_old, tau, fe_new, r, st)
+            return m == 0 ? launch_sdc_node_first(pl, lv->p, M, rows, th, fi_old, fe_old,
+                                                  old_last_from_cout ? t.cout : nullptr, tau, fe_new, r, st)
                           : launch_sdc_node(pl, lv->p, m, M, wt, rows.h[m], th, fi_new, fe_new, t.cout, r, st);
         }));
         int rc = tendency_impl(pl, lv->p, 1, th + o, fi_new + o, fe_new + o, t, st, false);
         if (rc) return rc;
     }
     const size_t oM = (size_t)M * ns3;
-    HIPCHK(launch_swe_combine(pl, lv->p, t.cout, th + oM, fi_new + oM, fe_new + oM, 1, st));
+    if (form_last) HIPCHK(launch_swe_combine(pl, lv->p, t.cout, th + oM, fi_new + oM, fe_new + oM, 1, st));
     return SHX_OK;
 }
 
@@ -381,8 +385,9 @@ int step_body(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, dou
         // A) fine sweep(s), old -> new buffers
         for (int s2 = 0; s2 < o->nsweep_fine; ++s2) {
             double2* rec = tape ? tape->f + (1 + (size_t)(k * o->nsweep_fine + s2) * Mf) * nsf3 : nullptr;
+            // consecutive sweeps: the F of the last node is formed by the next sweep's first update
             rc = sweep_impl(fl, dt, w.thf, w.fif[fcur], w.fef[fcur], w.fif[1 - fcur], w.fef[1 - fcur], nullptr,
-                            w.tf, st, rec);
+                            w.tf, st, rec, s2 == o->nsweep_fine - 1, s2 > 0);
             if (rc) return rc;
             fcur = 1 - fcur;
         }
@@ -401,7 +406,8 @@ int step_body(const sdc_level* fl, const sdc_level* cl, const mlsdc_opts* o, dou
         const double2 *ci = w.fict, *ce = w.fect;
         for (int s2 = 0; s2 < o->nsweep_coarse; ++s2) {
             double2* rec = tape ? tape->c + (cbase + Mc + (size_t)s2 * Mc) * nsc3 : nullptr;
-            rc = sweep_impl(cl, dt, w.thc, ci, ce, w.fic[s2 & 1], w.fec[s2 & 1], w.tau, w.tc, st, rec);
+            rc = sweep_impl(cl, dt, w.thc, ci, ce, w.fic[s2 & 1], w.fec[s2 & 1], w.tau, w.tc, st, rec,
+                            s2 == o->nsweep_coarse - 1, s2 > 0);
             if (rc) return rc;
             ci = w.fic[s2 & 1];
             ce = w.fec[s2 & 1];
@@ -521,7 +527,7 @@ int step_multi_body(const sdc_level* const* lv, int L, int niter, const int* ns,
     for (int k = 0; k < niter; ++k) {
         for (int s2 = 0; s2 < ns[0]; ++s2) {
             rc = sweep_impl(lv[0], dt, w[0].th, w[0].fi[fcur], w[0].fe[fcur], w[0].fi[1 - fcur], w[0].fe[1 - fcur],
-                            nullptr, w[0].t, st);
+                            nullptr, w[0].t, st, nullptr, s2 == ns[0] - 1, s2 > 0);
             if (rc) return rc;
             fcur = 1 - fcur;
         }
@@ -543,7 +549,7 @@ int step_multi_body(const sdc_level* const* lv, int L, int niter, const int* ns,
             const double2 *fi_old = w[l].fit, *fe_old = w[l].fet;
             for (int s2 = 0; s2 < ns[l]; ++s2) {
                 rc = sweep_impl(lv[l], dt, w[l].th, fi_old, fe_old, w[l].fi[s2 & 1], w[l].fe[s2 & 1], w[l].tau, w[l].t,
-                                st);
+                                st, nullptr, s2 == ns[l] - 1, s2 > 0);
                 if (rc) return rc;
                 fi_old = w[l].fi[s2 & 1];
                 fe_old = w[l].fe[s2 & 1];

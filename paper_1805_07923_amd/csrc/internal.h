@@ -361,8 +361,8 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
 // rec != nullptr: Theta^{m+1} is also stored there (the adjoint's tape).
 hipError_t launch_leg_syn_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st);
 hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
-                                 double2* theta, const double2* fi_old, const double2* fe_old, const double2* tau,
-                                 double2* sq, double2* rec, hipStream_t st);
+                                 double2* theta, const double2* fi_old, const double2* fe_old, const double2* cout_M,
+                                 const double2* tau, double2* sq, double2* rec, hipStream_t st);
 hipError_t launch_sdc_node(const shx_plan* pl, const swe_params& p, int m, int M, const NodeWeights& wts,
                            double h, double2* theta, double2* fi, double2* fe, const double2* cout_m,
                            double2* rec, hipStream_t st);

@@ -137,7 +137,8 @@ __global__ void k_imex_solve(const int* __restrict__ deg, const double2* rhs, do
 //         - sum_{j=1}^{m} [dtQE[m+1][j] F_E^{j,old} + dtQD[m+1][j] F_I^{j,old}]
 //         - h_m F_I^{m+1,old} + tau^{m+1},
 // is formed for every m by the first update (k_sdc_node_first), which reads
-// the old F once: it solves with S_0 and stores S_m, m >= 1, in the slot of
+// the old F once (when the previous sweep left the F of node M unformed,
+// cout_M != null, it forms that F from node M's analyses and Theta^M): it solves with S_0 and stores S_m, m >= 1, in the slot of
 // the new F_E of node m+1, which the sweep fills only later (node m+1's
 // update, or the closing combine for node M).  k_sdc_node (m >= 1) reads
 // S_m, forms the new F at node m from the analyses of node m's tendency
@@ -165,11 +166,13 @@ __device__ __forceinline__ void node_solve(const int* __restrict__ deg, const sw
     if (rec) rec[o] = v;
 }
 
-__global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node_first(const int* __restrict__ deg, long long nspec,
+__global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node_first(const int* __restrict__ ord,
+                                                              const int* __restrict__ deg, int N, long long nspec,
                                                               swe_params p, int M, NodeRows R,
                                                               double2* __restrict__ theta,
                                                               const double2* __restrict__ fi_old,
                                                               const double2* __restrict__ fe_old,
+                                                              const double2* __restrict__ cout_M,
                                                               const double2* __restrict__ tau,
                                                               double2* __restrict__ sq,
                                                               double2* __restrict__ rec) {
@@ -184,8 +187,12 @@ __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node_first(const int* __res
 #pragma unroll
         for (int j = 0; j < 9; ++j)
             if (j <= M) {
-                fi[j] = fi_old[j * ns3 + o];
-                fe[j] = fe_old[j * ns3 + o];
+                if (j == M && cout_M) {                 // formed here from node M's analyses and Theta^M
+                    combine_field(cout_M, theta + M * ns3, N, nspec, p, i, ord[i], deg[i], c, fe[j], fi[j]);
+                } else {
+                    fi[j] = fi_old[j * ns3 + o];
+                    fe[j] = fe_old[j * ns3 + o];
+                }
             }
         const double2 t0 = theta[o];
         for (int m = 0; m < M; ++m) {
@@ -421,11 +428,12 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
 }
 
 hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
-                                 double2* theta, const double2* fi_old, const double2* fe_old, const double2* tau,
-                                 double2* sq, double2* rec, hipStream_t st) {
+                                 double2* theta, const double2* fi_old, const double2* fe_old, const double2* cout_M,
+                                 const double2* tau, double2* sq, double2* rec, hipStream_t st) {
     if (M < 1 || M > 8) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((pl->nspec + NODE_CO - 1) / NODE_CO);
-    k_sdc_node_first<<<nb, 3 * NODE_CO, 0, st>>>(pl->deg, pl->nspec, p, M, rows, theta, fi_old, fe_old, tau, sq, rec);
+    k_sdc_node_first<<<nb, 3 * NODE_CO, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, M, rows, theta, fi_old,
+                                                fe_old, cout_M, tau, sq, rec);
     return hipGetLastError();
 }
 
