@@ -159,9 +159,9 @@ int sweep_impl(const sdc_level* lv, double dt, double2* th, const double2* fi_ol
         }
         double2* r = rec ? rec + (size_t)m * ns3 : nullptr;
         const size_t o = (size_t)(m + 1) * ns3;
-        if (m > 0 && pl->prec == SHX_FP64 && pl->Jh < 384) {
-            // FP64: node m's update (F of node m from t.cout, Theta^{m+1})
-            // formed in the staging of the synthesis of Theta^{m+1} (below
+        if (m > 0 && leg_syn_swe_node_supported(pl) && pl->Jh < 384) {
+            // node m's update (F of node m from t.cout, Theta^{m+1}) formed
+            // in the staging of the synthesis of Theta^{m+1} (below
             // 384 latitude pairs: with more, the 4+ latitude-group blocks of
             // an order repeating the order's update cost more than the
             // separate launch; T1023 22.5 -> 19.9 steps/s)

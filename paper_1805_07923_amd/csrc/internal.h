@@ -359,7 +359,13 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
 // cout_m != nullptr (m >= 1): the new F at node m is formed from these
 // analyses of node m's tendency inside the node update (and stored).
 // rec != nullptr: Theta^{m+1} is also stored there (the adjoint's tape).
+// The tendency synthesis with a sweep's node update formed in its staging
+// (FP64 plans, and reduced-precision plans whose tendency synthesis
+// regenerates P^m_n).
+bool leg_syn_swe_node_supported(const shx_plan* pl);
+bool leg_syn_mixed_swe_node_supported(const shx_plan* pl);
 hipError_t launch_leg_syn_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st);
+hipError_t launch_leg_syn_mixed_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st);
 hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
                                  double2* theta, const double2* fi_old, const double2* fe_old, const double2* cout_M,
                                  const double2* tau, double2* sq, double2* rec, hipStream_t st);

@@ -287,43 +287,8 @@ __global__ __launch_bounds__(64 * syn_wb(SYN_LS)) void k_leg_syn_m(const double2
     }
     if constexpr (STAGE == 3) {
         static_assert(STAGE != 3 || NF == 4, "the tendency synthesis has four fields");
-        const long long ns3 = 3 * nspec;
-        const int k = nfu.m;
-        for (int t = threadIdx.x; t <= N - m; t += 64 * syn_wb(SYN_LS)) {
-            const int n = m + t;
-            const long long i = spec_idx(N, m, n);
-            double2 fem[3], fim[3], acc[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] = nfu.fe[(k + 1) * ns3 + c * nspec + i];   // S_k
-            swe_node::combine_one(nfu.cout, nfu.theta + k * ns3, N, nspec, nfu.p, i, m, n, fem, fim);
-            for (int j = 1; j < k; ++j)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    acc[c] = swe_node::caxpy(nfu.wt.qe[j], nfu.fe[j * ns3 + c * nspec + i], acc[c]);
-                    acc[c] = swe_node::caxpy(nfu.wt.qd[j], nfu.fi[j * ns3 + c * nspec + i], acc[c]);
-                }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                acc[c] = swe_node::caxpy(nfu.wt.qe[k], fem[c], acc[c]);
-                acc[c] = swe_node::caxpy(nfu.wt.qd[k], fim[c], acc[c]);
-            }
-            const double L = n * (n + 1.0) / (nfu.p.a * nfu.p.a);
-            double2 x[3];
-            swe_node::solve_one(L, nfu.h, nfu.p, acc[0], acc[1], acc[2], x[0], x[1], x[2]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) thn[c * (N + 1) + t] = x[c];
-            if (tile.x == 0) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const long long o = c * nspec + i;
-                    nfu.theta[(k + 1) * ns3 + o] = x[c];
-                    nfu.fe[k * ns3 + o] = fem[c];
-                    nfu.fi[k * ns3 + o] = fim[c];
-                    if (nfu.rec) nfu.rec[o] = x[c];
-                }
-            }
-        }
         // the staging below reads thn after its first barrier
+        swe_node::node_update_order(nfu, N, nspec, m, tile.x == 0, thn, threadIdx.x, 64 * syn_wb(SYN_LS));
     }
     for (int s = 0; s < S; ++s) {
         double accE[SYN_LS][NG], accO[SYN_LS][NG];
@@ -897,8 +862,13 @@ hipError_t launch_leg_syn_swe(const shx_plan* pl, double a, const double2* state
     return hipGetLastError();
 }
 
+bool leg_syn_swe_node_supported(const shx_plan* pl) {
+    return pl->prec == SHX_FP64 || leg_syn_mixed_swe_node_supported(pl);
+}
+
 hipError_t launch_leg_syn_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st) {
-    if (pl->prec != SHX_FP64 || nf.m < 1 || !nf.cout || !nf.theta || !nf.fi || !nf.fe) return hipErrorInvalidValue;
+    if (nf.m < 1 || !nf.cout || !nf.theta || !nf.fi || !nf.fe) return hipErrorInvalidValue;
+    if (pl->prec != SHX_FP64) return launch_leg_syn_mixed_swe_node(pl, nf, out, st);
     syn_r<4, 3>(pl, nullptr, out, 4, 0, 1, pl->nmax, 0, nf.p.a, st, nf);
     return hipGetLastError();
 }

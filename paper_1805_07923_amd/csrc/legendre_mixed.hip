@@ -21,6 +21,7 @@
 // [m][p][k][jp], synthesis: [m][p][jp][k]) padded with zeros to a multiple of
 // 16, so each lane reads its four reduction elements as one 8-byte load.
 #include "internal.h"
+#include "swe_node.h"
 
 namespace {
 
@@ -564,11 +565,11 @@ __global__ __launch_bounds__(256) void k_leg_syn_mo(const double2* __restrict__ 
                                                     long long cin_stride, long long out_stride, int gx,
                                                     long long nspec, double a, int Lmax,
                                                     const double2* __restrict__ pf,
-                                                    const double* __restrict__ ninv) {
+                                                    const double* __restrict__ ninv, NodeFuse nfu) {
     static_assert(NF >= 1 && NF <= 8, "16 real columns per product");
     constexpr int NP = (MODE == 1) ? 1 : MODE;
     constexpr int U = 8;                                // degrees per batch of LDS reads
-    extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc
+    extern __shared__ double2 csh[];                    // [4][L NF + 2] rows, then [4][L + 2] rc, then (STAGE 3) [3][N+1]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane & 15, q = lane >> 4;
     const int ic = i < 2 * NF ? i : 2 * NF - 1;
@@ -588,6 +589,14 @@ __global__ __launch_bounds__(256) void k_leg_syn_mo(const double2* __restrict__ 
     const double2* rcm = rc + ext_idx(N, m, m);
     const double2* pfm = pf + ext_idx(N, m, m);
     const double ia = 1.0 / a, a2 = a * a;
+    // STAGE 3: the sweep's node update of order m (FP64) into LDS first, the
+    // tendency rows (as STAGE 1) then staged from there; the block of the
+    // first latitude group stores the sweep's outputs (S = 1)
+    double2* thn = csh + 4 * (Lmax * (NF + 1) + 4);
+    if constexpr (STAGE == 3) {
+        static_assert(STAGE != 3 || NF == 4, "the tendency synthesis has four fields");
+        swe_node::node_update_order(nfu, N, nspec, m, tile.x == 0, thn, threadIdx.x, 256);
+    }
     for (int s = 0; s < S; ++s) {
         floatx4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = e0, o0 = e0, o1 = e0;
         for (int r = 0; r < R; ++r) {
@@ -604,6 +613,12 @@ __global__ __launch_bounds__(256) void k_leg_syn_mo(const double2* __restrict__ 
                         static_assert(STAGE != 1 || NF == 4, "the tendency synthesis has four fields");
                         double2 o[4];
                         swe_prep_row(cin + s * cin_stride, nspec, N, a2, ia, pfm, ninv, m, m + kk, o);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) row[f] = o[f];
+                    } else if constexpr (STAGE == 3) {
+                        double2 o[4];
+                        swe_prep_row_t([&](int f, int nn) { return thn[f * (N + 1) + (nn - m)]; }, N, a2, ia, pfm,
+                                       ninv, m, m + kk, o);
 #pragma unroll
                         for (int f = 0; f < 4; ++f) row[f] = o[f];
                     } else {
@@ -808,14 +823,15 @@ __global__ __launch_bounds__(256) void k_leg_an_mo(const int* __restrict__ blist
 
 template <int NF, int MODE, int STAGE>
 void syn_mo(const shx_plan* pl, const double2* cin, double2* out, int F, int f0, int S, int nmax_use,
-            long long cin_stride, double a, hipStream_t st) {
+            long long cin_stride, double a, hipStream_t st, const NodeFuse& nfu = NodeFuse{}) {
     const int gx = (pl->Jh + 63) / 64;
     int Lmax = 0;
     for (int m = 0; m <= pl->N; ++m) Lmax = seg_len(pl->nmax - m + 1) > Lmax ? seg_len(pl->nmax - m + 1) : Lmax;
-    const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2);
+    const size_t lds = (size_t)4 * (Lmax * (NF + 1) + 4) * sizeof(double2) +
+                       (STAGE == 3 ? (size_t)3 * (pl->N + 1) * sizeof(double2) : 0);
     k_leg_syn_mo<NF, MODE, STAGE><<<gx * (pl->N + 1), 256, lds, st>>>(
         pl->ck, pl->ckoff, pl->rc, pl->mu, cin, out, pl->N, pl->nmax, nmax_use, pl->Jh, F, f0, S, cin_stride,
-        (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a, Lmax, pl->pf, pl->ninv);
+        (long long)pl->J * (pl->N + 1) * F, gx, pl->nspec, a, Lmax, pl->pf, pl->ninv, nfu);
 }
 
 template <int NF, int MODE>
@@ -996,6 +1012,25 @@ hipError_t launch_leg_syn_mixed_swe(const shx_plan* pl, double a, const double2*
         case SHX_FP32: syn_mx<1, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
         case SHX_SPLIT_BF16_2: syn_mx<2, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
         case SHX_SPLIT_BF16_3: syn_mx<3, 1, true>(pl, state, out, 4, 0, 4, S, pl->nmax, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// the fused update uses the synthesis that regenerates P^m_n: every FP32
+// plan (below 160 latitude pairs its table synthesis is a little faster
+// alone, 7.5 against 7.8 us at T127, but not against the node-update launch
+// that the fusion saves) and the plans without tables
+bool leg_syn_mixed_swe_node_supported(const shx_plan* pl) {
+    return pl->tmode == SHX_TABLE_ONTHEFLY || pl->prec == SHX_FP32;
+}
+
+hipError_t launch_leg_syn_mixed_swe_node(const shx_plan* pl, const NodeFuse& nf, double2* out, hipStream_t st) {
+    if (!leg_syn_mixed_swe_node_supported(pl)) return hipErrorInvalidValue;
+    switch (pl->prec) {
+        case SHX_FP32: syn_mo<4, 1, 3>(pl, nullptr, out, 4, 0, 1, pl->nmax, 0, nf.p.a, st, nf); break;
+        case SHX_SPLIT_BF16_2: syn_mo<4, 2, 3>(pl, nullptr, out, 4, 0, 1, pl->nmax, 0, nf.p.a, st, nf); break;
+        case SHX_SPLIT_BF16_3: syn_mo<4, 3, 3>(pl, nullptr, out, 4, 0, 1, pl->nmax, 0, nf.p.a, st, nf); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

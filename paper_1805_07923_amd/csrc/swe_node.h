@@ -63,4 +63,51 @@ __device__ __forceinline__ void solve_one(double L, double h, const swe_params& 
     xz = make_double2(bz.x / c, bz.y / c);
 }
 
+// The sweep's node update k = nf.m >= 1 for the coefficients of order m
+// (degrees m..N), done by threads tid, tid + nthreads, ... of a block:
+//   Theta^{k+1} = solve(S_k + sum_{j<=k} [dtQE F_E^j + dtQD F_I^j], h),
+// S_k from the new-F_E slot of node k+1, the F of node k formed from its
+// analyses (nf.cout) and Theta^k.  Theta^{k+1} goes to thn [3][N+1] (LDS,
+// degree n at n - m); with store, also Theta^{k+1} and the F of node k to
+// memory and Theta^{k+1} to the tape.
+__device__ inline void node_update_order(const NodeFuse& nf, int N, long long nspec, int m, bool store,
+                                         double2* thn, int tid, int nthreads) {
+    const long long ns3 = 3 * nspec;
+    const int k = nf.m;
+    for (int t = tid; t <= N - m; t += nthreads) {
+        const int n = m + t;
+        const long long i = spec_idx(N, m, n);
+        double2 fem[3], fim[3], acc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = nf.fe[(k + 1) * ns3 + c * nspec + i];   // S_k
+        combine_one(nf.cout, nf.theta + k * ns3, N, nspec, nf.p, i, m, n, fem, fim);
+        for (int j = 1; j < k; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[c] = caxpy(nf.wt.qe[j], nf.fe[j * ns3 + c * nspec + i], acc[c]);
+                acc[c] = caxpy(nf.wt.qd[j], nf.fi[j * ns3 + c * nspec + i], acc[c]);
+            }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] = caxpy(nf.wt.qe[k], fem[c], acc[c]);
+            acc[c] = caxpy(nf.wt.qd[k], fim[c], acc[c]);
+        }
+        const double L = n * (n + 1.0) / (nf.p.a * nf.p.a);
+        double2 x[3];
+        solve_one(L, nf.h, nf.p, acc[0], acc[1], acc[2], x[0], x[1], x[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) thn[c * (N + 1) + t] = x[c];
+        if (store) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long o = c * nspec + i;
+                nf.theta[(k + 1) * ns3 + o] = x[c];
+                nf.fe[k * ns3 + o] = fem[c];
+                nf.fi[k * ns3 + o] = fim[c];
+                if (nf.rec) nf.rec[o] = x[c];
+            }
+        }
+    }
+}
+
 }  // namespace swe_node
