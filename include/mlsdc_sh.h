@@ -132,10 +132,8 @@ int shx_plan_legendre(const shx_plan* plan, int m, int n, double* out);
  * latitude pair.  Plans that generate P^m_n sum every latitude pair: the
  * count is sum over (m, n) of nlat/2.  FP64 plans with tables on at most
  * 512 latitudes and FP32 plans with tables on at most 2040 latitudes apply
- * the polar truncation of the transform library the
- * method builds on (Sec. 3, Schaeffer 2013) to chunks of up to 6 fields
- * (fields go in chunks of 8; chunks of 7 or 8 fields sum every pair), and
- * the count is that of such a chunk.  Per order m, parity of n - m and
+ * the polar truncation of the transform library the method builds on
+ * (Sec. 3, Schaeffer 2013) to every field.  Per order m, parity of n - m and
  * tile of 16 such degrees, the latitude pairs are taken in groups of 4 from
  * the pole (ngrp = ceil(nlat/8) groups); c0 is the first group holding a
  * |P^m_n| >= 1e-20 for a degree of the tile (ngrp if none); the sum runs
