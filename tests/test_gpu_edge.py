@@ -101,6 +101,34 @@ def test_two_node_sdc(pk):
         assert relerr(out[f], ref[f]) < TOL, f
 
 
+def test_consecutive_sweeps_two_nodes(pk):
+    """Several sweeps in a row on two-node levels: the first of two
+    consecutive sweeps leaves the F of its last node to the next sweep's
+    first update, which with two nodes reads and rewrites the same node
+    (Theta^M = Theta^1).  Single-level SDC with 3 sweeps per iteration, and
+    two levels (3 / 2 nodes) with 2 + 2 sweeps, against the oracle."""
+    print("CASE consecutive sweeps, two nodes", flush=True)
+    N, J, I = 31, 48, 96
+    par = pk.swe_params()
+    st = torch.tensor(workload.state(N, 1000))
+    lev2 = pk.Level(pk.Plan(N, J, I), par, pk.SDC_GAUSS_LOBATTO, 2)
+    out = pk.Stepper(lev2, None, niter=2, nsweep_fine=3).step(600.0, st.to("cuda"))
+    olev2 = OS.Level(oracle_problem(N, J, I), "lobatto", 2)
+    ref = OS.mlsdc_step(olev2, None, 600.0, st, niter=2, nsweep_fine=3)
+    for f in range(3):
+        assert relerr(out[f], ref[f]) < TOL, ("sdc", f)
+    lf = pk.Level(pk.Plan(N, J, I), par, pk.SDC_GAUSS_LOBATTO, 3)
+    lc = pk.Level(pk.Plan(15, 24, 48), par, pk.SDC_GAUSS_LOBATTO, 2)
+    out = pk.Stepper(lf, lc, niter=2, nsweep_fine=2, nsweep_coarse=2).step(600.0, st.to("cuda"))
+    of = OS.Level(oracle_problem(N, J, I), "lobatto", 3)
+    oc = OS.Level(oracle_problem(15, 24, 48), "lobatto", 2)
+    R, P = OS.spectral_transfer(N, 15)
+    ref = OS.mlsdc_step(of, oc, 600.0, st, niter=2, nsweep_fine=2, nsweep_coarse=2, restrict_space=R,
+                        interp_space=P)
+    for f in range(3):
+        assert relerr(out[f], ref[f]) < TOL, ("mlsdc", f)
+
+
 def test_mlsdc_equal_node_counts(pk):
     """Two levels with three Gauss-Lobatto nodes each (T31 / T15): only the
     space is coarsened, the time restriction and interpolation are the
