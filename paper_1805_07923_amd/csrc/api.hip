@@ -919,10 +919,14 @@ int shx_plan_create(int N, int J, int I, int prec, int table_mode, shx_plan** ou
         std::vector<long long> off4(2 * (N + 1));
         long long tot = 0, mx = 0;
         for (int mp = 0; mp < 2 * (N + 1); ++mp) {
-            const long long sz = (long long)((kcount(p->nmax, mp >> 1, mp & 1) + 15) / 16) * ngrp * 64;
+            // whole tiles of 64 values per latitude group, the last tile
+            // 4 x its rows per group
+            const int K = kcount(p->nmax, mp >> 1, mp & 1), nt = (K + 15) / 16;
+            const long long sz = K > 0 ? ((long long)(nt - 1) * 64 + 4 * (K - 16 * (nt - 1))) * ngrp : 0;
             off4[mp] = tot;
             tot += sz;
-            mx = sz > mx ? sz : mx;
+            const long long padded = (long long)nt * ngrp * 64;
+            mx = padded > mx ? padded : mx;
         }
         p->an_kt = (kcount(p->nmax, 0, 0) + 15) / 16;   // tiles of the largest block (m = 0, p = 0)
         ok = (prec == SHX_FP64 ? dalloc(&p->pan4, tot) : dalloc(&p->pan4f, tot)) == hipSuccess &&

@@ -221,10 +221,11 @@ struct shx_plan {
     long long* off = nullptr;       // device [(N+1)*2] table offsets (elements)
     // Analysis table laid out for the matrix-core table analyses (FP64
     // plans with tables and at most 256 latitude pairs; pan4f for FP32):
-    // pan4[off4[2m+p] + ((kt * ngrp + c) * 4 + kq) * 16 + i] = P^m_{m+p+2k}(mu_jp),
-    // k = 16 kt + i, jp = 4 c + kq, ngrp = ceil(Jh / 4); zero past the rows and
-    // latitude pairs, so that one operand of 16 degrees x 4 latitude pairs is
-    // 64 consecutive values.
+    // pan4[off4[2m+p] + kt * ngrp * 64 + (c * 4 + kq) * r + i] = P^m_{m+p+2k}(mu_jp),
+    // k = 16 kt + i (i < r), jp = 4 c + kq, ngrp = ceil(Jh / 4), r = the rows
+    // of tile kt (16, fewer in the block's last tile); zero past the latitude
+    // pairs, so that one operand of r degrees x 4 latitude pairs is 4 r
+    // consecutive values (64 for a whole tile) and no padding rows are stored.
     double* pan4 = nullptr;
     float* pan4f = nullptr;         // the same layout rounded to FP32 (SHX_FP32 plans, Jh <= AN_TAB_JH_F32)
     long long* off4 = nullptr;

@@ -535,7 +535,8 @@ __global__ __launch_bounds__(256) void k_leg_an_m(const int* __restrict__ blist,
 }
 
 // pan4 (FP64) or pan4f (FP32, rounded) from pan (layout in shx_plan): one
-// thread per destination element of order-parity block blockIdx.y = 2 m + p.
+// thread per element of the block's tiles counted as whole (order-parity
+// block blockIdx.y = 2 m + p); the rows past the last degree are not stored.
 template <class T>
 __global__ void k_an_tab4(const double* __restrict__ pan, const long long* __restrict__ off,
                           const long long* __restrict__ off4, T* __restrict__ pan4, int nmax, int Jh) {
@@ -547,8 +548,12 @@ __global__ void k_an_tab4(const double* __restrict__ pan, const long long* __res
     const long long blk = e / 64;
     const int l = (int)(e - blk * 64);
     const int kt = (int)(blk / ngrp), c = (int)(blk - (long long)kt * ngrp);
-    const int k = 16 * kt + (l & 15), jp = 4 * c + (l >> 4);
-    pan4[off4[mp] + e] = (T)((k < K && jp < Jh) ? pan[off[mp] + (long long)jp * K + k] : 0.0);
+    const int i = l & 15, kq = l >> 4;
+    const int r = K - 16 * kt < 16 ? K - 16 * kt : 16;  // rows of tile kt
+    if (i >= r) return;
+    const int k = 16 * kt + i, jp = 4 * c + kq;
+    pan4[off4[mp] + (long long)kt * ngrp * 64 + (long long)(4 * c + kq) * r + i] =
+        (T)(jp < Jh ? pan[off[mp] + (long long)jp * K + k] : 0.0);
 }
 
 // First summed latitude group of each 16-degree tile of pan4 (an_c0 in
@@ -561,11 +566,14 @@ __global__ __launch_bounds__(64) void k_an_polar(const T* __restrict__ pan4,
                                                  int nmax, int Jh, int kt_all, double tau) {
     const int mp = blockIdx.y, kt = blockIdx.x, lane = threadIdx.x;
     const int ngrp = (Jh + 3) / 4;
+    const int K = kcount(nmax, mp >> 1, mp & 1);
     int c = ngrp;
-    if (16 * kt < kcount(nmax, mp >> 1, mp & 1)) {
-        const T* t = pan4 + off4[mp] + (long long)kt * ngrp * 64 + lane;
+    if (16 * kt < K) {
+        const int r = K - 16 * kt < 16 ? K - 16 * kt : 16, i = lane & 15;
+        const bool on = i < r;                          // lanes of stored rows
+        const T* t = pan4 + off4[mp] + (long long)kt * ngrp * 64 + (lane >> 4) * r + (on ? i : 0);
         for (c = 0; c < ngrp; ++c)
-            if (__ballot(fabs((double)t[(long long)c * 64]) >= tau) != 0) break;
+            if (__ballot(on && fabs((double)t[(long long)c * 4 * r]) >= tau) != 0) break;
     }
     if (lane == 0) c0[mp * kt_all + kt] = c;
 }
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(64) void k_an_polar(const T* __restrict__ pan4,
 // over all latitude pairs, so no partial sums cross wavefronts.  Per group
 // of 4 latitude pairs the four-block v_mfma_f64_4x4x4f64 takes A = 16
 // degrees x 4 latitude pairs of the table, 64 consecutive values of pan4 (one
-// 8-byte load per lane), and B = the north +/- south Fourier data of the
+// 8-byte load per lane; 4 x the rows of the block's last tile there), and B = the north +/- south Fourier data of the
 // same latitude pairs staged in LDS (column 4 g + lane % 4): one instruction
 // per pair of fields; D lane 4 b + j + 16 i holds degree row 4 b + i,
 // column 4 g + j.  With an odd field count the last field's two columns are
@@ -618,8 +626,15 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
     const bool rows = k0 < K;                           // wave-uniform
     const int kq = lane >> 4;                           // latitude slot of the operands
     const int ngrp = (Jh + 3) / 4;                      // groups of 4 latitude pairs
-    // A operands of this wavefront's 16 degrees: 64 consecutive values per group
-    const double* P = pan4 + off4[2 * m + p] + (long long)(k0 >> 4) * ngrp * 64 + lane;
+    // A operands of this wavefront's degrees: 4 r consecutive values per
+    // group, r = the tile's stored rows (16 but in the block's last tile);
+    // lanes of the missing rows read row 0 again, and their output rows are
+    // not stored
+    const int Kt = kcount(nmax_tab, m, p);
+    const int r = __builtin_amdgcn_readfirstlane(Kt - k0 < 16 ? (Kt - k0 > 0 ? Kt - k0 : 1) : 16);
+    const int os = 4 * r;                               // operand stride
+    const double* P = pan4 + off4[2 * m + p] + (long long)(k0 >> 4) * ngrp * 64 + kq * r +
+                      ((lane & 15) < r ? (lane & 15) : 0);
     const int cb0 = tb.w;                               // first staged latitude group
     // the tile's first summed group (wave-uniform: kept in a scalar register
     // so that the group loop and its addresses stay scalar)
@@ -637,7 +652,7 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
         const int b0 = (nrun / UNR + 1) / 2;
         if (half == 0) cend = b0 * UNR; else cbeg = b0 * UNR;
     }
-    const double* Pw = P + (long long)(cw0 + cbeg) * 64;
+    const double* Pw = P + (long long)(cw0 + cbeg) * os;
     const int nmine = cend - cbeg, jw = 4 * (cw0 + cbeg) + kq;
     // the first batch of table values is loaded before the Fourier data are
     // staged, so that the two memory round trips overlap; the table is the
@@ -646,7 +661,7 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
     double pv0[UNR];
     if (pre) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * 64];
+        for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * os];
     }
     double* red = reinterpret_cast<double*>(gsh + (size_t)4 * ngrp * NF) + (size_t)tw * NR * 64 + lane;
     for (int s = 0; s < S; ++s) {
@@ -690,11 +705,11 @@ __global__ __launch_bounds__(256 * SPLIT) void k_leg_an(const int4* __restrict__
             for (; c + UNR <= nmine; c += UNR) {
                 double pv[UNR];
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * 64];
+                for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * os];
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
             }
-            for (; c < nmine; ++c) step(Pw[c * 64], jw + 4 * c);
+            for (; c < nmine; ++c) step(Pw[c * os], jw + 4 * c);
         }
         if constexpr (SPLIT == 2) {
             // half 1 hands its partial sums to half 0 (same lane, same tile),

@@ -259,7 +259,8 @@ __global__ __launch_bounds__(256) void k_leg_an_mx(const void* __restrict__ tab,
 // its tile's first summed group on (polar truncation, AN_POLAR_TAU; runs of
 // whole batches of UNR loads, the first issued before the Fourier staging).
 // Per group v_mfma_f32_16x16x4f32 takes A = 16 degrees x 4 latitude pairs,
-// 64 consecutive FP32 table values (one 4-byte load per lane), and B = the
+// 64 consecutive FP32 table values (one 4-byte load per lane; 4 x the rows
+// of the block's last tile there), and B = the
 // north +/- south Fourier data of the same pairs rounded to FP32 and staged
 // in LDS as [jp][16 NCT] (columns 2f, 2f+1 = Re, Im of field f, zero past
 // 2 NF; NCT = 1 or 2 products of 16 columns per group for up to 8 or 16
@@ -269,8 +270,8 @@ template <int NF, int UNR>
 __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tblk, const float* __restrict__ pan4f,
                                                     const long long* __restrict__ off4,
                                                     const double2* __restrict__ G, double2* __restrict__ cout,
-                                                    int N, int nmax_use, int J, int F, int f0, int S,
-                                                    long long G_stride, long long cout_stride) {
+                                                    int N, int nmax_tab, int nmax_use, int J, int F, int f0,
+                                                    int S, long long G_stride, long long cout_stride) {
     static_assert(NF >= 1 && NF <= 16, "two 16-column products at most");
     constexpr int NCT = (NF + 7) / 8;                   // 16-column products per latitude group
     constexpr int CW = 16 * NCT;                        // staged columns
@@ -287,16 +288,21 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
     const bool rows = k0 < K;                           // wave-uniform
     const int kq = lane >> 4, col = lane & 15;
     const int ngrp = (Jh + 3) / 4;
-    const float* P = pan4f + off4[mp] + (long long)(k0 >> 4) * ngrp * 64 + lane;
+    // 4 r consecutive values per group, r = the tile's stored rows; lanes of
+    // missing rows read row 0 again and their output rows are not stored
+    const int Kt = kcount(nmax_tab, m, p);
+    const int r = __builtin_amdgcn_readfirstlane(Kt - k0 < 16 ? (Kt - k0 > 0 ? Kt - k0 : 1) : 16);
+    const int os = 4 * r;                               // operand stride
+    const float* P = pan4f + off4[mp] + (long long)(k0 >> 4) * ngrp * 64 + kq * r + (col < r ? col : 0);
     const int cb0 = tb.w;                               // first staged latitude group
     const int cw0 = __builtin_amdgcn_readfirstlane(rows ? (tb.z >> (8 * wv)) & 255 : ngrp);
-    const float* Pw = P + (long long)cw0 * 64;
+    const float* Pw = P + (long long)cw0 * os;
     const int nrun = ngrp - cw0, jw = 4 * cw0 + kq;
     const bool pre = rows && nrun >= UNR;               // wave-uniform
     float pv0[UNR];
     if (pre) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * 64];
+        for (int u = 0; u < UNR; ++u) pv0[u] = Pw[u * os];
     }
     const double sg = p ? -1.0 : 1.0;
     const long long rowstride = (long long)(N + 1) * F;
@@ -337,11 +343,11 @@ __global__ __launch_bounds__(256) void k_leg_an_f32(const int4* __restrict__ tbl
         for (; c + UNR <= nrun; c += UNR) {
             float pv[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * 64];
+            for (int u = 0; u < UNR; ++u) pv[u] = Pw[(c + u) * os];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) step(pv[u], jw + 4 * (c + u));
         }
-        for (; c < nrun; ++c) step(Pw[c * 64], jw + 4 * c);
+        for (; c < nrun; ++c) step(Pw[c * os], jw + 4 * c);
         // D[4 (l/16) + r][l % 16]: row k0 + 4 (l/16) + r, column 16 t + l % 16
 #pragma unroll
         for (int t = 0; t < NCT; ++t) {
@@ -920,11 +926,11 @@ void an_f32(const shx_plan* pl, const double2* G, double2* cout, int F, int f0, 
     const int4* tb = reinterpret_cast<const int4*>(pl->tblk);
     const long long gst = (long long)pl->J * (pl->N + 1) * F, cst = pl->nspec_e * F;
     if (an_batch(pl->Jh) == 8)
-        k_leg_an_f32<NF, 8><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4f, pl->off4, G, cout, pl->N, nmax_use, pl->J,
-                                                          F, f0, S, gst, cst);
+        k_leg_an_f32<NF, 8><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4f, pl->off4, G, cout, pl->N, pl->nmax, nmax_use,
+                                                          pl->J, F, f0, S, gst, cst);
     else
-        k_leg_an_f32<NF, 4><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4f, pl->off4, G, cout, pl->N, nmax_use, pl->J,
-                                                          F, f0, S, gst, cst);
+        k_leg_an_f32<NF, 4><<<pl->tb_nblk, 256, lds, st>>>(tb, pl->pan4f, pl->off4, G, cout, pl->N, pl->nmax, nmax_use,
+                                                          pl->J, F, f0, S, gst, cst);
 }
 
 template <int MODE>
