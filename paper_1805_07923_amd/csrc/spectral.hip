@@ -144,11 +144,11 @@ __global__ void k_imex_solve(const int* __restrict__ deg, const double2* rhs, do
 // S_m, forms the new F at node m from the analyses of node m's tendency
 // (cout) and Theta^m, stores it to (fi, fe) node m, and adds
 // sum_{j=1}^{m} [dtQE[m+1][j] F_E^{j,new} + dtQD[m+1][j] F_I^{j,new}].
-// Blocks of NODE_CO coefficients x 3 fields: thread group c accumulates
-// field c; the 2 x 2 solve of (Phi', delta) meets the three right-hand
-// sides in LDS.  32 coefficients per block (96 threads, a quarter of the
-// second wave idle) measured faster than 64 (8.8 vs 10.1 us at T255): twice
-// the blocks spread the memory-bound loop over more CUs.
+// k_sdc_node: blocks of NODE_CO coefficients x 3 fields, thread group c
+// accumulates field c; the 2 x 2 solve of (Phi', delta) meets the three
+// right-hand sides in LDS.  32 coefficients per block (96 threads, a quarter
+// of the second wave idle) measured faster than 64 (8.8 vs 10.1 us at T255):
+// twice the blocks spread the memory-bound loop over more CUs.
 constexpr int NODE_CO = 32;
 
 __device__ __forceinline__ void node_solve(const int* __restrict__ deg, const swe_params& p, double h, int c,
@@ -166,57 +166,65 @@ __device__ __forceinline__ void node_solve(const int* __restrict__ deg, const sw
     if (rec) rec[o] = v;
 }
 
-__global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node_first(const int* __restrict__ ord,
-                                                              const int* __restrict__ deg, int N, long long nspec,
-                                                              swe_params p, int M, NodeRows R,
-                                                              double2* __restrict__ theta,
-                                                              const double2* __restrict__ fi_old,
-                                                              const double2* __restrict__ fe_old,
-                                                              const double2* __restrict__ cout_M,
-                                                              const double2* __restrict__ tau,
-                                                              double2* __restrict__ sq,
-                                                              double2* __restrict__ rec) {
-    __shared__ double2 bsh[3][NODE_CO];
-    const int c = threadIdx.x / NODE_CO, loc = threadIdx.x - c * NODE_CO;
-    const long long i = (long long)blockIdx.x * NODE_CO + loc;
-    const bool on = i < nspec;
-    const long long ns3 = 3 * nspec, o = c * nspec + i;
-    double2 acc0 = make_double2(0.0, 0.0);
-    if (on) {
-        double2 fi[9], fe[9];                           // the old F at nodes 0..M (M <= 8)
+// The first update: one thread per coefficient with its three fields in
+// registers (the solve needs no exchange), M + 1 old F per field; 64-thread
+// blocks, a quarter of the wavefronts of one thread per (coefficient, field).
+constexpr int NODE_T1 = 64;
+template <int M>
+__global__ __launch_bounds__(NODE_T1) void k_sdc_node_first(const int* __restrict__ ord,
+                                                          const int* __restrict__ deg, int N, long long nspec,
+                                                          swe_params p, NodeRows R, double2* __restrict__ theta,
+                                                          const double2* __restrict__ fi_old,
+                                                          const double2* __restrict__ fe_old,
+                                                          const double2* __restrict__ cout_M,
+                                                          const double2* __restrict__ tau,
+                                                          double2* __restrict__ sq, double2* __restrict__ rec) {
+    const long long i = (long long)blockIdx.x * NODE_T1 + threadIdx.x;
+    if (i >= nspec) return;
+    const long long ns3 = 3 * nspec;
+    double2 fi[M + 1][3], fe[M + 1][3];                 // the old F at nodes 0..M
+    const int JL = cout_M ? M : M + 1;                  // nodes read from memory
 #pragma unroll
-        for (int j = 0; j < 9; ++j)
-            if (j <= M) {
-                if (j == M && cout_M) {                 // formed here from node M's analyses and Theta^M
-                    combine_field(cout_M, theta + M * ns3, N, nspec, p, i, ord[i], deg[i], c, fe[j], fi[j]);
-                } else {
-                    fi[j] = fi_old[j * ns3 + o];
-                    fe[j] = fe_old[j * ns3 + o];
-                }
+    for (int j = 0; j <= M; ++j)
+        if (j < JL) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fi[j][c] = fi_old[j * ns3 + c * nspec + i];
+                fe[j][c] = fe_old[j * ns3 + c * nspec + i];
             }
-        const double2 t0 = theta[o];
-        for (int m = 0; m < M; ++m) {
-            double2 acc = t0;
-#pragma unroll
-            for (int j = 0; j < 9; ++j)
-                if (j <= M) acc = caxpy(R.q[m][j], cadd(fi[j], fe[j]), acc);
-#pragma unroll
-            for (int j = 1; j < 9; ++j)
-                if (j <= m) {
-                    acc = caxpy(-R.qe[m][j], fe[j], acc);
-                    acc = caxpy(-R.qd[m][j], fi[j], acc);
-                }
-#pragma unroll
-            for (int j = 1; j < 9; ++j)
-                if (j == m + 1) acc = caxpy(-R.h[m], fi[j], acc);
-            if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + o]);
-            if (m == 0)
-                acc0 = acc;
-            else
-                sq[(m + 1) * ns3 + o] = acc;
         }
+    if (cout_M)                                         // node M's F from its analyses and Theta^M
+        combine_one(cout_M, theta + M * ns3, N, nspec, p, i, ord[i], deg[i], fe[M], fi[M]);
+    double2 t0[3], acc0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t0[c] = theta[c * nspec + i];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double2 acc = t0[c];
+#pragma unroll
+            for (int j = 0; j <= M; ++j) acc = caxpy(R.q[m][j], cadd(fi[j][c], fe[j][c]), acc);
+#pragma unroll
+            for (int j = 1; j <= m; ++j) {
+                acc = caxpy(-R.qe[m][j], fe[j][c], acc);
+                acc = caxpy(-R.qd[m][j], fi[j][c], acc);
+            }
+            acc = caxpy(-R.h[m], fi[m + 1][c], acc);
+            if (tau) acc = cadd(acc, tau[(m + 1) * ns3 + c * nspec + i]);
+            if (m == 0)
+                acc0[c] = acc;
+            else
+                sq[(m + 1) * ns3 + c * nspec + i] = acc;
+        }
+    const int n = deg[i];
+    double2 x[3];
+    solve_one(n * (n + 1.0) / (p.a * p.a), R.h[0], p, acc0[0], acc0[1], acc0[2], x[0], x[1], x[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        theta[ns3 + c * nspec + i] = x[c];
+        if (rec) rec[c * nspec + i] = x[c];
     }
-    node_solve(deg, p, R.h[0], c, loc, i, on, acc0, bsh, theta + ns3, rec, o);
 }
 
 __global__ __launch_bounds__(3 * NODE_CO) void k_sdc_node(const int* __restrict__ ord, const int* __restrict__ deg,
@@ -430,10 +438,19 @@ hipError_t launch_imex_solve(const shx_plan* pl, const swe_params& p, double h, 
 hipError_t launch_sdc_node_first(const shx_plan* pl, const swe_params& p, int M, const NodeRows& rows,
                                  double2* theta, const double2* fi_old, const double2* fe_old, const double2* cout_M,
                                  const double2* tau, double2* sq, double2* rec, hipStream_t st) {
-    if (M < 1 || M > 8) return hipErrorInvalidValue;
-    const unsigned nb = (unsigned)((pl->nspec + NODE_CO - 1) / NODE_CO);
-    k_sdc_node_first<<<nb, 3 * NODE_CO, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, M, rows, theta, fi_old,
-                                                fe_old, cout_M, tau, sq, rec);
+    const unsigned nb = (unsigned)((pl->nspec + NODE_T1 - 1) / NODE_T1);
+    switch (M) {
+#define SHX_NODE_FIRST(MM)                                                                                        \
+    case MM:                                                                                                      \
+        k_sdc_node_first<MM><<<nb, NODE_T1, 0, st>>>(pl->ord, pl->deg, pl->N, pl->nspec, p, rows, theta, fi_old, \
+                                                     fe_old, cout_M, tau, sq, rec);                              \
+        break;
+        SHX_NODE_FIRST(1) SHX_NODE_FIRST(2) SHX_NODE_FIRST(3) SHX_NODE_FIRST(4)
+        SHX_NODE_FIRST(5) SHX_NODE_FIRST(6) SHX_NODE_FIRST(7) SHX_NODE_FIRST(8)
+#undef SHX_NODE_FIRST
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
