@@ -310,29 +310,44 @@ __global__ void k_fas_tau(const int* __restrict__ ordc, const int* __restrict__ 
 
 // For fine nodes m = 1..nf-1: X_f^m += Pad(sum_i Pfc[m][i] (X_c^i - X~_c^i)) for
 // X in {Theta, F_I, F_E}; only the coefficients with n <= N_c change.  One
-// thread per (coarse coefficient, field = blockIdx.y, fine node m = 1 + blockIdx.z).
-__global__ void k_interp(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf, int Nc,
-                         long long nsf, long long nsc, Mat9x9 P, int nf, int nc,
-                         const double2* __restrict__ thc, const double2* __restrict__ thct,
-                         const double2* __restrict__ fic, const double2* __restrict__ fict,
-                         const double2* __restrict__ fec, const double2* __restrict__ fect,
-                         double2* __restrict__ thf, double2* __restrict__ fif, double2* __restrict__ fef) {
-    const long long c = (long long)blockIdx.x * TB + threadIdx.x;
+// thread per (coarse coefficient, field = blockIdx.y) reads the coarse
+// differences once and updates every fine node (nf, nc <= 9).
+__global__ __launch_bounds__(64) void k_interp(const int* __restrict__ ordc, const int* __restrict__ degc, int Nf,
+                                               int Nc, long long nsf, long long nsc, Mat9x9 P, int nf, int nc,
+                                               const double2* __restrict__ thc, const double2* __restrict__ thct,
+                                               const double2* __restrict__ fic, const double2* __restrict__ fict,
+                                               const double2* __restrict__ fec, const double2* __restrict__ fect,
+                                               double2* __restrict__ thf, double2* __restrict__ fif,
+                                               double2* __restrict__ fef) {
+    const long long c = (long long)blockIdx.x * 64 + threadIdx.x;
     if (c >= nsc) return;
-    const int f = blockIdx.y, m = 1 + blockIdx.z;
+    const int f = blockIdx.y;
     const long long fidx = spec_idx(Nf, ordc[c], degc[c]);
-    double2 a = make_double2(0.0, 0.0), b = a, d = a;
-    for (int i = 0; i < nc; ++i) {
-        const long long o = (i * 3 + f) * nsc + c;
-        const double w = P.a[m * nc + i];
-        a = caxpy(w, csub(thc[o], thct[o]), a);
-        b = caxpy(w, csub(fic[o], fict[o]), b);
-        d = caxpy(w, csub(fec[o], fect[o]), d);
-    }
-    const long long o = (m * 3 + f) * nsf + fidx;
-    thf[o] = cadd(thf[o], a);
-    fif[o] = cadd(fif[o], b);
-    fef[o] = cadd(fef[o], d);
+    double2 a[8], b[8], d[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) a[m] = b[m] = d[m] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (i < nc) {
+            const long long o = (i * 3 + f) * nsc + c;
+            const double2 x = csub(thc[o], thct[o]), y = csub(fic[o], fict[o]), z = csub(fec[o], fect[o]);
+#pragma unroll
+            for (int m = 1; m < 9; ++m)
+                if (m < nf) {
+                    const double w = P.a[m * nc + i];
+                    a[m - 1] = caxpy(w, x, a[m - 1]);
+                    b[m - 1] = caxpy(w, y, b[m - 1]);
+                    d[m - 1] = caxpy(w, z, d[m - 1]);
+                }
+        }
+#pragma unroll
+    for (int m = 1; m < 9; ++m)
+        if (m < nf) {
+            const long long o = (m * 3 + f) * nsf + fidx;
+            thf[o] = cadd(thf[o], a[m - 1]);
+            fif[o] = cadd(fif[o], b[m - 1]);
+            fef[o] = cadd(fef[o], d[m - 1]);
+        }
 }
 
 // Per-block partial sums for the residual: [blk][M+1] of ||r^m||^2 (m >= 1)
@@ -492,8 +507,9 @@ hipError_t launch_interp(const shx_plan* fine, const shx_plan* coarse, const Mat
                          const double2* fe_c, const double2* fe_ct, double2* th_f, double2* fi_f,
                          double2* fe_f, hipStream_t st) {
     if (nf < 2) return hipSuccess;
-    dim3 g(nblocks(coarse->nspec), 3, nf - 1);
-    k_interp<<<g, TB, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec, coarse->nspec, Pfc, nf,
+    if (nf > 9 || nc > 9) return hipErrorInvalidValue;
+    dim3 g((unsigned)((coarse->nspec + 63) / 64), 3);
+    k_interp<<<g, 64, 0, st>>>(coarse->ord, coarse->deg, fine->N, coarse->N, fine->nspec, coarse->nspec, Pfc, nf,
                                nc, th_c, th_ct, fi_c, fi_ct, fe_c, fe_ct, th_f, fi_f, fe_f);
     return hipGetLastError();
 }
