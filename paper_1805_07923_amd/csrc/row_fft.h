@@ -340,14 +340,18 @@ __device__ __forceinline__ void wstage(double2* row, const double2* tws, double 
         const int j = lane + it * 64, k = j % Ns;
         if (NB % 64 == 0 || j < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double2 x = row[pidx(j + r * NB)];
-                if (Ns > 1 && r > 0) {
-                    double2 w = tw_half(tws, r * k * TWS, C);
-                    w.y *= -sg;
-                    x = cmul(x, w);
-                }
-                v[it][r] = x;
+            for (int r = 0; r < R; ++r) v[it][r] = row[pidx(j + r * NB)];
+            if constexpr (Ns > 1) {
+                // twiddles w^r, r = 1..R-1, as powers of the one table value
+                // w = e^{-+2 pi i k TWS / (2 C)} (squares and one product per
+                // step), so that a stage reads one twiddle from LDS, not R - 1
+                double2 w[R];
+                w[1] = tw_half(tws, k * TWS, C);
+                w[1].y *= -sg;
+#pragma unroll
+                for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w[1]);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], w[r]);
             }
             dft<R>(v[it], sg);
         }
