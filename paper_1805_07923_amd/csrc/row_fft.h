@@ -167,14 +167,16 @@ __device__ __forceinline__ void stage(const double2* src, double2* dst, const do
             const int row = item / NB, j = item - row * NB, k = j % Ns;
             const double2* b = src + row * padded(C);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double2 x = b[pidx(j + r * NB)];
-                if (Ns > 1 && r > 0) {
-                    double2 w = tw_half(tws, r * k * TWS, C);
-                    w.y *= -sg;
-                    x = cmul(x, w);
-                }
-                v[it][r] = x;
+            for (int r = 0; r < R; ++r) v[it][r] = b[pidx(j + r * NB)];
+            if constexpr (Ns > 1) {
+                // twiddles as powers of one table value (as in wstage)
+                double2 w[R];
+                w[1] = tw_half(tws, k * TWS, C);
+                w[1].y *= -sg;
+#pragma unroll
+                for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w[1]);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], w[r]);
             }
             dft<R>(v[it], sg);
         }
